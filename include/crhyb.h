@@ -1,0 +1,219 @@
+/*
+ * crhyb.h - hybridised Crouzeix-Raviart Stokes / Navier-Stokes solve on AMD gfx950.
+ *
+ * Implements the "hybrid method" of Chenier & Eymard, "Exact pressure
+ * elimination for the Crouzeix-Raviart scheme applied to the Stokes and
+ * Navier-Stokes problems" (arXiv 2101.03777), Section 3.2:
+ *   1. element-wise elimination of the coupled system [A D^t; D 0][U;P] = [R;0]
+ *      (Section 3.1, eq. syslin) into G W = S on d unknowns per interior face;
+ *   2. Krylov solution of G W = S;
+ *   3. element-wise recovery of U and P.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns cr_status (CR_OK = 0); no C++ exception crosses the ABI.
+ *    On failure cr_last_error() returns a message for the calling thread.
+ *  - Mesh arrays are HOST pointers, borrowed for the duration of the call and copied.
+ *  - Field arrays passed to cr_eliminate / cr_update_rhs and the outputs of
+ *    cr_recover are DEVICE pointers (memory of the device the system lives on,
+ *    e.g. torch tensors), borrowed for the duration of the enqueued work.
+ *  - All device work is enqueued on the HIP stream given to cr_assemble (NULL =
+ *    the null stream).  Calls that return host scalars (cr_solve, the exports)
+ *    synchronise that stream; the others are asynchronous.
+ *  - Device memory of a system comes from the cr_allocator given to cr_assemble
+ *    (NULL = hipMalloc/hipFree) and is released by cr_destroy.
+ *  - A cr_system is not thread-safe; distinct systems are independent.
+ *  - Canonical layouts (never the internal renumbering):
+ *      interior faces  ordered lexicographically by their sorted vertex-id tuple
+ *                      (cr_interior_faces returns them);
+ *      U, W, u_prev, u_lin  [n_int_faces][dim] doubles (face-major);
+ *      P, f_mean       in the caller's element order: P [n_elements],
+ *                      f_mean [n_elements][dim]; P[k0] = 0 (Section 2, Q_{h,0}).
+ *  - Sign choice C_K (eq. propc): +1 on the lower-index element of a face, -1 on
+ *    the other; W depends on it, U and P do not.
+ */
+#ifndef CRHYB_H
+#define CRHYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CR_OK = 0,
+  CR_E_INVAL = -1,      /* bad argument or call order */
+  CR_E_NOMEM = -2,      /* allocation failed */
+  CR_E_MESH = -3,       /* face shared by > 2 elements, zero-volume element, element without interior face */
+  CR_E_SINGULAR = -4,   /* B_K <= 0 (Section 3.2 item 4), singular local matrix, zero diagonal of G */
+  CR_E_NOCONV = -5,     /* iteration limit reached; best iterate kept, info filled */
+  CR_E_BREAKDOWN = -6,  /* Krylov breakdown (p^t G p <= 0 in CG, zero rho/omega in BiCGStab) */
+  CR_E_NONFINITE = -7,  /* NaN/Inf in an input or a solver scalar */
+  CR_E_DEVICE = -8      /* HIP runtime error */
+} cr_status;
+
+/* problem kinds (cr_params.problem) */
+enum { CR_STOKES = 0, CR_NS_NEWTON = 1 };
+/* face numbering (cr_params.renumber) */
+enum { CR_RCM = 0, CR_NATURAL = 1 };
+/* Krylov methods (cr_solve_opts.method) */
+enum { CR_PCG = 0, CR_BICGSTAB = 1 };
+/* arithmetic of the Krylov iterations (cr_solve_opts.precision) */
+enum { CR_FP64 = 0, CR_FP32_IR = 1 };
+
+typedef struct cr_system cr_system;
+
+/* Device allocator used for every buffer a system owns.  alloc returns NULL on
+ * failure.  stream is the system's hipStream_t. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx, void* stream);
+  void (*release)(void* ptr, void* ctx, void* stream);
+  void* ctx;
+} cr_allocator;
+
+/* A simplicial mesh without hanging nodes (Section 2 item 1): triangles (dim 2)
+ * or tetrahedra (dim 3), any orientation. */
+typedef struct {
+  int32_t dim;
+  int64_t n_vertices;
+  const double* coords;          /* host [n_vertices][dim] */
+  int64_t n_elements;
+  const int32_t* elem_vertices;  /* host [n_elements][dim+1] */
+} cr_mesh_desc;
+
+/* Coefficients of the strong form (Section 2): mu = 1/dt (transient) or 0
+ * (steady), nu = 1/Re > 0.  k0 is the element whose pressure is pinned to 0
+ * (Section 2 item 5).  problem = CR_NS_NEWTON selects the Newton linearisation
+ * of the convection form b_h (eq. defbh) about u_lin (2D only). */
+typedef struct {
+  double mu, nu;
+  int32_t k0;
+  int32_t problem;
+  int32_t renumber;
+} cr_params;
+
+/* Step a0: face topology, renumbering and upload of the mesh.
+ * Builds interior/exterior faces, element<->face tables, the sign choice C_K,
+ * reverse Cuthill-McKee face order (or natural), element order, and for mu = 0
+ * the element partition M1/M2 of Section 3.2 item 7 (greedy maximal independent
+ * set in caller order).  Host work plus host-to-device copies on hip_stream.
+ * Errors: CR_E_INVAL (dim not 2/3, nu <= 0, mu < 0, k0 out of range, NS in 3D),
+ * CR_E_MESH (see above), CR_E_NOMEM, CR_E_DEVICE.  *out is NULL on error. */
+cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params,
+                      const cr_allocator* alloc, void* hip_stream, cr_system** out);
+
+/* Steps a1-a3: element-wise elimination (Section 3.2 items 4-5) and assembly of
+ * G (same block stencil as A) and S.
+ * f_mean: device [n_elements][dim], element means of the force (eq. defrhs).
+ * u_prev: device [n_int_faces][dim] previous time-step velocity, or NULL; it
+ *         enters R_K through the lumped mass mu |K|/(d+1) U^{n-1}.
+ * u_lin:  device [n_int_faces][dim] Newton linearisation velocity (CR_NS_NEWTON
+ *         only, required there), else NULL.
+ * Synchronises the stream to report element errors.
+ * Errors: CR_E_SINGULAR (element id in the message), CR_E_NONFINITE, CR_E_INVAL. */
+cr_status cr_eliminate(cr_system* sys, const double* f_mean, const double* u_prev,
+                       const double* u_lin);
+
+/* Step a6: new right-hand side with the same G (constant time step, Stokes only):
+ * recomputes R_K and s_K from the stored element factors and re-gathers S.
+ * Same argument meaning as cr_eliminate.  Asynchronous. */
+cr_status cr_update_rhs(cr_system* sys, const double* f_mean, const double* u_prev);
+
+typedef struct {
+  int32_t method;      /* CR_PCG (symmetric positive definite G) or CR_BICGSTAB */
+  int32_t precision;   /* CR_FP64, or CR_FP32_IR: FP32 Krylov inside FP64 iterative refinement */
+  double tol;          /* stop when ||S - G W||_2 <= tol ||S||_2, residual recomputed in FP64 */
+  double inner_tol;    /* relative tolerance of each inner (refinement) solve; <= 0: automatic */
+  int32_t maxit;       /* cap on the total number of Krylov iterations */
+  int32_t max_outer;   /* cap on refinement passes */
+  int32_t check_every; /* iterations per convergence poll (rounded up to even); <= 0: automatic */
+  int32_t use_graph;   /* 1: replay the iteration block as a captured hipGraph */
+  int32_t warm_start;  /* 1: start from the resident W of the previous solve, 0: from W = 0 */
+} cr_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations executed */
+  int32_t outer_iters;  /* refinement passes (residual evaluations) */
+  double rel_residual;  /* ||S - G W|| / ||S|| in FP64 for the returned W */
+  double t_solve_ms;    /* wall time of the call */
+  int32_t reason;       /* 1 converged, 3 iteration limit, 4 breakdown, 5 non-finite */
+} cr_solve_info;
+
+/* Step a4: Krylov solve of G W = S; W stays resident on the device.
+ * PCG applies when mu > 0 and the problem is Stokes (G symmetric positive
+ * definite, Section 3.2 item 6); BiCGStab otherwise.  Jacobi preconditioning
+ * is applied as the symmetric scaling |diag G|^{-1/2} G |diag G|^{-1/2}.
+ * Synchronises.  Errors: CR_E_NOCONV, CR_E_BREAKDOWN, CR_E_NONFINITE, CR_E_INVAL
+ * (before cr_eliminate).  info may be NULL. */
+cr_status cr_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* info);
+
+/* Step a5: recovery (Section 3.2 items 2 and 4):
+ *   P_K = r_K^t (R_K - C_K W_K) / B_K (K != K0), P_K0 = 0,
+ *   U^_K = A^_K^{-1} (R_K - D_K P_K - C_K W_K);
+ * U is the copy of the element with C = +1.
+ * U: device [n_int_faces][dim] (canonical), P: device [n_elements] (caller order).
+ * jump (optional, device [1] or NULL): ||C^ U^||_2, the copy mismatch, which
+ * equals ||S - G W||_2.  Asynchronous. */
+cr_status cr_recover(cr_system* sys, double* U, double* P, double* jump);
+
+/* Sizes of the system: interior faces, structural non-zeros of G (d x d blocks
+ * of the stencil), non-zeros of the coupled matrix [A D^t; D 0]. Any pointer may be NULL. */
+cr_status cr_query_sizes(const cr_system* sys, int64_t* n_int_faces, int64_t* nnz_G,
+                         int64_t* nnz_coupled);
+
+/* Host copy of G (FP64, CSR, canonical face-major numbering, structural
+ * entries of the stencil) and of S.  Buffers sized from cr_query_sizes:
+ * rowptr [n+1], col [nnz_G], val [nnz_G], S [n] with n = dim * n_int_faces.
+ * Synchronises. */
+cr_status cr_export_G(const cr_system* sys, int64_t* rowptr, int32_t* col, double* val, double* S);
+
+/* Host copy of the resident W [n_int_faces][dim] (canonical). Synchronises. */
+cr_status cr_export_W(const cr_system* sys, double* W);
+
+/* Set the resident W from a host array [n_int_faces][dim] (canonical), e.g. to
+ * recover U and P from a W computed elsewhere.  Synchronises. */
+cr_status cr_import_W(cr_system* sys, const double* W);
+
+/* Host copy of the interior faces [n_int_faces][dim] as sorted vertex ids, canonical order. */
+cr_status cr_interior_faces(const cr_system* sys, int32_t* face_vertices);
+
+/* Host-only topology (step a0 without any device work), for inspection:
+ * n_int_faces, the internal position of every canonical face (perm [n_int_faces],
+ * may be NULL), the half bandwidth of the face adjacency in internal order and in
+ * canonical order, and the M1 flag of every element (m1 [n_elements], may be
+ * NULL; all zero when mu > 0). */
+cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t* n_int_faces,
+                      int32_t* perm, int64_t* bandwidth_internal, int64_t* bandwidth_canonical,
+                      int32_t* m1);
+
+/* Baseline: FP64 MINRES on the original coupled system [A D^t; D 0] on the same
+ * GPU, preconditioned by the positive diagonal diag(A) (+) diag(D diag(A)^{-1} D^t);
+ * Stokes only.  Same stopping rule on the coupled residual ||[R;0] - M [U;P]|| / ||R||.
+ * U, P as in cr_recover.  Synchronises.  Errors: CR_E_NOCONV (best iterate written). */
+cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* info,
+                           double* U, double* P);
+
+/* Average device time of the dominant Krylov kernel (SpMV fused with the CG
+ * direction updates) over reps back-to-back launches on the system's stream,
+ * measured with HIP events, on scratch copies of the state (the resident
+ * solution is untouched).  precision as in cr_solve_opts.  Also returns the
+ * algorithmic bytes one launch moves (matrix values and column indices, the
+ * gathered input vector once, and the fused vector reads/writes).  Synchronises. */
+cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t reps, double* avg_ms,
+                       double* bytes_per_launch);
+
+void cr_destroy(cr_system* sys);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* cr_last_error(void);
+
+/* Library version string. */
+const char* cr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRHYB_H */

@@ -1,0 +1,1028 @@
+// Element-wise kernels of the hybrid method (steps a1-a3, a5, a6), FP64.
+//
+// Paper: Chenier & Eymard, arXiv 2101.03777.
+//   Section 2 items 1-4: geometry, CR basis, lumped mass, right-hand side eq. defrhs.
+//   Section 2 item 6:    convection form b_h (eq. defbh), Newton Jacobian.
+//   Section 3.1:         element matrices S_K, A_K, D_K, R_K.
+//   Section 3.2:         E_K, C_K, B_K, G_K, s_K (items 4-5, 7), recovery (items 2, 4).
+//
+// One thread per element for elimination and recovery (the dense local algebra
+// lives in registers: (d+1)x(d+1) in the Stokes case, where A^_K = S_K (x) I_d,
+// and 6x6 for the 2D Newton step), one thread per interior face for the
+// gather assembly of G: the (sigma, sigma') block of G comes from the unique
+// element holding both faces and the diagonal block from the face's two
+// elements, so assembly needs no atomics.
+#include <cmath>
+
+#include "internal.h"
+
+namespace crh {
+namespace {
+
+constexpr int BS = 128;  // threads per block for element/face kernels
+
+enum : int { ERR_SINGULAR = 1, ERR_NONFINITE = 2, ERR_ZERODIAG = 4 };
+
+__device__ __forceinline__ void report(int32_t* err, int bits, int64_t id) {
+  atomicOr(err, bits);
+  atomicMin(err + 1, (int32_t)id);
+}
+
+// ---------------------------------------------------------------------------
+// geometry: |K|, a_{K,j} = |sigma_j| n_{K,sigma_j} (outward), x_K.
+// With E = [x_1 - x_0, ..., x_d - x_0], grad(lambda_j) is row j-1 of E^{-1} and
+// a_j = -d |K| grad(lambda_j), i.e. minus sign(det E) / (d-1)! times row j-1 of
+// adj(E); a_0 closes the surface.
+// ---------------------------------------------------------------------------
+template <int D>
+struct Geo {
+  double X[D + 1][D];
+  double a[D + 1][D];
+  double vol;
+  double xK[D];
+};
+
+template <int D>
+__device__ __forceinline__ void load_geometry(const double* __restrict__ ecoord, int64_t ne, int64_t k, Geo<D>& g) {
+#pragma unroll
+  for (int j = 0; j <= D; ++j)
+#pragma unroll
+    for (int r = 0; r < D; ++r) g.X[j][r] = ecoord[(j * D + r) * ne + k];
+  double E[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) E[r][c] = g.X[c + 1][r] - g.X[0][r];
+  if constexpr (D == 2) {
+    double det = E[0][0] * E[1][1] - E[0][1] * E[1][0];
+    double sg = det > 0.0 ? 1.0 : -1.0;
+    g.a[1][0] = -sg * E[1][1];
+    g.a[1][1] = sg * E[0][1];
+    g.a[2][0] = sg * E[1][0];
+    g.a[2][1] = -sg * E[0][0];
+    g.vol = 0.5 * fabs(det);
+  } else {
+    double e[3][3];  // e[c] = column c
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) e[c][r] = E[r][c];
+    double cr[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double* p = e[(j + 1) % 3];
+      const double* q = e[(j + 2) % 3];
+      cr[j][0] = p[1] * q[2] - p[2] * q[1];
+      cr[j][1] = p[2] * q[0] - p[0] * q[2];
+      cr[j][2] = p[0] * q[1] - p[1] * q[0];
+    }
+    double det = e[0][0] * cr[0][0] + e[0][1] * cr[0][1] + e[0][2] * cr[0][2];
+    double h = det > 0.0 ? -0.5 : 0.5;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) g.a[j + 1][r] = h * cr[j][r];
+    g.vol = fabs(det) / 6.0;
+  }
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    double s = 0.0, x = 0.0;
+#pragma unroll
+    for (int j = 1; j <= D; ++j) s += g.a[j][r];
+    g.a[0][r] = -s;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) x += g.X[j][r];
+    g.xK[r] = x / (D + 1);
+  }
+}
+
+// In-place Gauss-Jordan inverse of an N x N matrix held in registers.  With
+// PIVOT, rows are exchanged by compile-time-indexed conditional swaps so that
+// the largest remaining entry of each column becomes the pivot (partial
+// pivoting without dynamic register indexing).  Returns false on a zero pivot.
+template <int N, bool PIVOT>
+__device__ __forceinline__ bool gj_inverse(double (&A)[N][N], double (&Inv)[N][N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) Inv[r][c] = r == c ? 1.0 : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if constexpr (PIVOT) {
+#pragma unroll
+      for (int r = c + 1; r < N; ++r) {
+        bool sw = fabs(A[r][c]) > fabs(A[c][c]);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          double t0 = A[c][q], t1 = A[r][q];
+          A[c][q] = sw ? t1 : t0;
+          A[r][q] = sw ? t0 : t1;
+          double u0 = Inv[c][q], u1 = Inv[r][q];
+          Inv[c][q] = sw ? u1 : u0;
+          Inv[r][q] = sw ? u0 : u1;
+        }
+      }
+    }
+    double piv = A[c][c];
+    ok = ok && (piv != 0.0);
+    double ip = 1.0 / piv;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      A[c][q] *= ip;
+      Inv[c][q] *= ip;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      double f = A[r][c];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        A[r][q] -= f * A[c][q];
+        Inv[r][q] -= f * Inv[c][q];
+      }
+    }
+  }
+  return ok;
+}
+
+__device__ __forceinline__ bool interior(uint32_t fl, int j) { return (fl >> j) & 1u; }
+__device__ __forceinline__ double csign(uint32_t fl, int j) { return ((fl >> (8 + j)) & 1u) ? -1.0 : 1.0; }
+
+// packed symmetric index of (j, l), j <= l, in an N x N upper triangle (row-major)
+template <int N>
+__device__ __forceinline__ constexpr int sym(int j, int l) {
+  return j <= l ? j * N - j * (j - 1) / 2 + (l - j) : l * N - l * (l - 1) / 2 + (j - l);
+}
+
+// ---------------------------------------------------------------------------
+// Stokes pack: S_K^{-1} (symmetric, N(N+1)/2), V = A^_K^{-1} D_K as [N][D], 1/B_K.
+// For K0 the pack stores V = 0 and 1/B = 0, which turns every formula below
+// into its K0 form (G_K0 = C A^{-1} C, s_K0 = C A^{-1} R, P_K0 = 0).
+// ---------------------------------------------------------------------------
+template <int D>
+struct StokesPack {
+  static constexpr int N = D + 1;
+  static constexpr int NS = N * (N + 1) / 2;
+  static constexpr int SIZE = NS + N * D + 1;
+};
+
+template <int D>
+struct StokesFactors {
+  double Si[D + 1][D + 1];
+  double V[D + 1][D];
+  double invB;
+};
+
+template <int D>
+__device__ __forceinline__ void load_stokes_pack(const double* __restrict__ pack, int64_t ne, int64_t k,
+                                                 StokesFactors<D>& F) {
+  constexpr int N = D + 1;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int l = j; l < N; ++l) {
+      double v = pack[(int64_t)sym<N>(j, l) * ne + k];
+      F.Si[j][l] = v;
+      F.Si[l][j] = v;
+    }
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) F.V[j][i] = pack[(int64_t)(StokesPack<D>::NS + j * D + i) * ne + k];
+  F.invB = pack[(int64_t)(StokesPack<D>::SIZE - 1) * ne + k];
+}
+
+// R_K (eq. defrhs plus the lumped-mass transient term) and s_K from the factors.
+// (R_K)_{j,i} = a_j^(i) fbar.(x_sigma_j - x_K) with x_sigma_j - x_K = (x_K - x_j)/d.
+template <int D>
+__device__ __forceinline__ void stokes_rhs(const Geo<D>& g, uint32_t fl, const StokesFactors<D>& F,
+                                           const double* __restrict__ fbar, const double* __restrict__ uprev,
+                                           const int32_t* __restrict__ eface, double mu, int64_t ne, int64_t k,
+                                           double* __restrict__ RK, double* __restrict__ sK, int32_t* err) {
+  constexpr int N = D + 1;
+  double fb[D];
+  bool fin = true;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    fb[i] = fbar[k * D + i];
+    fin = fin && isfinite(fb[i]);
+  }
+  double R[N][D];
+  const double m = mu * g.vol / N;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double proj = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) proj += fb[i] * (g.xK[i] - g.X[j][i]);
+    proj *= 1.0 / D;
+    bool in = interior(fl, j);
+    int f = in ? eface[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double r = g.a[j][i] * proj;
+      if (uprev != nullptr && in) {
+        double u = uprev[(int64_t)f * D + i];
+        fin = fin && isfinite(u);
+        r += m * u;
+      }
+      R[j][i] = in ? r : 0.0;
+    }
+  }
+  if (!fin) report(err, ERR_NONFINITE, k);
+  double vr = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) vr += F.V[j][i] * R[j][i];
+  vr *= F.invB;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double c = csign(fl, j);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) t += F.Si[j][l] * R[l][i];
+      RK[(int64_t)(j * D + i) * ne + k] = R[j][i];
+      sK[(int64_t)(j * D + i) * ne + k] = c * (t - F.V[j][i] * vr);
+    }
+  }
+}
+
+// a1 + a2, Stokes: S_K (Section 3.1) with the lumped mass |K|/(d+1) per face
+// (Section 2 item 3) and grad(phi_j) = a_j/|K|; A^_K = S_K (x) I_d (E_K = 0 for
+// mu > 0, Section 3.2 item 6; for mu = 0 the Stokes E_K is diagonal per face and
+// is added to S_K); B_K = D_K^t A^_K^{-1} D_K with D_K = -a (Section 3.2 item 4).
+// Rows and columns of exterior faces are replaced by the identity and their
+// entries of D_K and R_K by zero, which removes them from every product.
+template <int D>
+__global__ void __launch_bounds__(BS) k_elim_stokes(int64_t ne, const double* __restrict__ ecoord,
+                                                    const uint32_t* __restrict__ eflags,
+                                                    const int32_t* __restrict__ eface,
+                                                    const int32_t* __restrict__ enb,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ fbar,
+                                                    const double* __restrict__ uprev, double mu, double nu,
+                                                    double* __restrict__ pack, double* __restrict__ RK,
+                                                    double* __restrict__ sK, int32_t* err) {
+  constexpr int N = D + 1;
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  const double m = mu * g.vol / N, iv = nu / g.vol;
+  double e[N];  // diagonal E_K (steady Stokes): -lambda_K on M1, +lambda_L on faces facing M1
+#pragma unroll
+  for (int j = 0; j < N; ++j) e[j] = 0.0;
+  if (lam != nullptr) {
+    if (fl & F_M1) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) e[j] = -lam[k];
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        int nb = enb[j * ne + k];
+        if (interior(fl, j) && nb >= 0 && (eflags[nb] & F_M1)) e[j] = lam[nb];
+      }
+    }
+  }
+  double S[N][N];
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      double v = iv * (g.a[j][0] * g.a[l][0] + g.a[j][1] * g.a[l][1] + (D == 3 ? g.a[j][D - 1] * g.a[l][D - 1] : 0.0));
+      if (j == l) v += m + e[j];
+      bool in = interior(fl, j) && interior(fl, l);
+      S[j][l] = in ? v : (j == l ? 1.0 : 0.0);
+    }
+  StokesFactors<D> F;
+  bool ok = gj_inverse<N, false>(S, F.Si);
+  double B = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) v -= F.Si[j][l] * (interior(fl, l) ? g.a[l][i] : 0.0);
+      F.V[j][i] = v;
+      B -= (interior(fl, j) ? g.a[j][i] : 0.0) * v;
+    }
+  // symmetric (mu > 0) case: B_K > 0; steady M1 elements have a negative definite A^_K, B_K < 0
+  if (!ok || !isfinite(B) || !(fabs(B) > 0.0) || (lam == nullptr && !(B > 0.0))) report(err, ERR_SINGULAR, k);
+  const bool k0 = fl & F_K0;
+  F.invB = k0 ? 0.0 : 1.0 / B;
+  if (k0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < D; ++i) F.V[j][i] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int l = j; l < N; ++l) pack[(int64_t)sym<N>(j, l) * ne + k] = F.Si[j][l];
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) pack[(int64_t)(StokesPack<D>::NS + j * D + i) * ne + k] = F.V[j][i];
+  pack[(int64_t)(StokesPack<D>::SIZE - 1) * ne + k] = F.invB;
+  stokes_rhs<D>(g, fl, F, fbar, uprev, eface, mu, ne, k, RK, sK, err);
+}
+
+// a6: new right-hand side from stored factors (same G).
+template <int D>
+__global__ void __launch_bounds__(BS) k_rhs_stokes(int64_t ne, const double* __restrict__ ecoord,
+                                                   const uint32_t* __restrict__ eflags,
+                                                   const int32_t* __restrict__ eface,
+                                                   const double* __restrict__ fbar,
+                                                   const double* __restrict__ uprev, double mu,
+                                                   const double* __restrict__ pack, double* __restrict__ RK,
+                                                   double* __restrict__ sK, int32_t* err) {
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  StokesFactors<D> F;
+  load_stokes_pack<D>(pack, ne, k, F);
+  stokes_rhs<D>(g, eflags[k], F, fbar, uprev, eface, mu, ne, k, RK, sK, err);
+}
+
+// ---------------------------------------------------------------------------
+// Navier-Stokes Newton step, 2D (N = 3 faces, 6 local unknowns, index j*2+i).
+// A_K = S_K (x) I_2 + d/du [N_K(u, u)] at ubar, where
+//   N_K(w, z)_{s,i} = 1/2 sum_{t != s} F_{s,t}(w) (z_{t,i} - z_{s,i}),
+//   F_{s,t}(w) = (W_s + W_t - sum_q W_q / 3) . (a_t - a_s) / 3
+// (second form of eq. defbh and the flux closed form of Section 2 item 6), and
+// R_K = R_f + N_K(ubar, ubar) (Newton right-hand side).  Exterior faces carry
+// U = 0 inside the sums; their rows and columns are removed.
+// ---------------------------------------------------------------------------
+struct NsPack {
+  static constexpr int NU = 6;
+  static constexpr int SIZE = NU * NU + 2 * NU + 1;  // A^{-1}, l, r, 1/B
+};
+
+__device__ __forceinline__ void ns_local(const Geo<2>& g, uint32_t fl, const double (&Ub)[3][2], double mu, double nu,
+                                         double (&A)[6][6], double (&Nuu)[3][2]) {
+  const double m = mu * g.vol / 3.0, iv = nu / g.vol;
+  double F[3][3], gx[3][3][2];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        gx[s][t][j] = (g.a[t][j] - g.a[s][j]) / 3.0;
+        double w = Ub[s][j] + Ub[t][j] - (Ub[0][j] + Ub[1][j] + Ub[2][j]) / 3.0;
+        v += w * gx[s][t][j];
+      }
+      F[s][t] = s == t ? 0.0 : v;
+    }
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) v += 0.5 * F[s][t] * (Ub[t][i] - Ub[s][i]);
+      Nuu[s][i] = v;
+    }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    double rowF = F[s][0] + F[s][1] + F[s][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          double v = 0.0;
+          if (i == j) {
+            v += (s == r ? m : 0.0) + iv * (g.a[s][0] * g.a[r][0] + g.a[s][1] * g.a[r][1]);
+            v += 0.5 * ((s == r ? 0.0 : F[s][r]) - (s == r ? rowF : 0.0));
+          }
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (t == s) continue;
+            double coef = (r == s ? 1.0 : 0.0) + (r == t ? 1.0 : 0.0) - 1.0 / 3.0;
+            v += 0.5 * coef * gx[s][t][j] * (Ub[t][i] - Ub[s][i]);
+          }
+          bool in = interior(fl, s) && interior(fl, r);
+          A[s * 2 + i][r * 2 + j] = in ? v : ((s == r && i == j) ? 1.0 : 0.0);
+        }
+  }
+}
+
+__device__ __forceinline__ void load_ubar(const double* __restrict__ ulin, const int32_t* __restrict__ eface,
+                                          uint32_t fl, int64_t ne, int64_t k, double (&Ub)[3][2]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    bool in = interior(fl, j);
+    int f = in ? eface[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) Ub[j][i] = in ? ulin[(int64_t)f * 2 + i] : 0.0;
+  }
+}
+
+// lambda_K = 2 ||A_K||_inf over the interior rows/columns, for K in M1 (Section 3.2 item 7)
+__global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __restrict__ ecoord,
+                                                  const uint32_t* __restrict__ eflags,
+                                                  const int32_t* __restrict__ eface,
+                                                  const double* __restrict__ ulin, double mu, double nu,
+                                                  double* __restrict__ lam) {
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  const uint32_t fl = eflags[k];
+  if (!(fl & F_M1)) {
+    lam[k] = 0.0;
+    return;
+  }
+  Geo<2> g;
+  load_geometry<2>(ecoord, ne, k, g);
+  double Ub[3][2], A[6][6], Nuu[3][2];
+  if (ulin != nullptr)
+    load_ubar(ulin, eface, fl, ne, k, Ub);
+  else
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Ub[j][0] = Ub[j][1] = 0.0;
+  ns_local(g, fl, Ub, mu, nu, A, Nuu);
+  double mx = 0.0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s += interior(fl, c / 2) ? fabs(A[r][c]) : 0.0;
+    mx = interior(fl, r / 2) ? fmax(mx, s) : mx;
+  }
+  lam[k] = 2.0 * mx;
+}
+
+// Stokes steady (mu = 0) lambda: same rule with the Stokes element matrix
+template <int D>
+__global__ void __launch_bounds__(BS) k_stokes_lambda(int64_t ne, const double* __restrict__ ecoord,
+                                                      const uint32_t* __restrict__ eflags, double mu, double nu,
+                                                      double* __restrict__ lam) {
+  constexpr int N = D + 1;
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  const uint32_t fl = eflags[k];
+  if (!(fl & F_M1)) {
+    lam[k] = 0.0;
+    return;
+  }
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const double m = mu * g.vol / N, iv = nu / g.vol;
+  double mx = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) v += g.a[j][i] * g.a[l][i];
+      v = iv * v + (j == l ? m : 0.0);
+      s += interior(fl, l) ? fabs(v) : 0.0;
+    }
+    mx = interior(fl, j) ? fmax(mx, s) : mx;
+  }
+  lam[k] = 2.0 * mx;
+}
+
+struct NsFactors {
+  double Ai[6][6];
+  double l[6], r[6];
+  double invB;
+};
+
+__device__ __forceinline__ void load_ns_pack(const double* __restrict__ pack, int64_t ne, int64_t k, NsFactors& F) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) F.Ai[a][b] = pack[(int64_t)(a * 6 + b) * ne + k];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    F.l[a] = pack[(int64_t)(36 + a) * ne + k];
+    F.r[a] = pack[(int64_t)(42 + a) * ne + k];
+  }
+  F.invB = pack[(int64_t)48 * ne + k];
+}
+
+// a1 + a2, 2D Newton step: A^_K = A_K + E_K (E_K from the M1/M2 partition when
+// mu = 0), general inverse, l = A^{-1} D, r = A^{-t} D, B = D^t A^{-1} D, and
+// s_K = C (A^{-1} R - l (r^t R) / B).
+__global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __restrict__ ecoord,
+                                                const uint32_t* __restrict__ eflags,
+                                                const int32_t* __restrict__ eface,
+                                                const int32_t* __restrict__ enb, const double* __restrict__ lam,
+                                                const double* __restrict__ fbar, const double* __restrict__ uprev,
+                                                const double* __restrict__ ulin, double mu, double nu,
+                                                double* __restrict__ pack, double* __restrict__ RK,
+                                                double* __restrict__ sK, int32_t* err) {
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  Geo<2> g;
+  load_geometry<2>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  double Ub[3][2], A[6][6], Nuu[3][2];
+  load_ubar(ulin, eface, fl, ne, k, Ub);
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) fin = fin && isfinite(Ub[j][0]) && isfinite(Ub[j][1]);
+  ns_local(g, fl, Ub, mu, nu, A, Nuu);
+  if (lam != nullptr) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double e = 0.0;
+      if (fl & F_M1) {
+        e = -lam[k];
+      } else {
+        int nb = enb[j * ne + k];
+        if (nb >= 0 && (eflags[nb] & F_M1)) e = lam[nb];
+      }
+      if (interior(fl, j)) {
+        A[j * 2][j * 2] += e;
+        A[j * 2 + 1][j * 2 + 1] += e;
+      }
+    }
+  }
+  NsFactors F;
+  bool ok = gj_inverse<6, true>(A, F.Ai);
+  double Dv[6];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) Dv[j * 2 + i] = interior(fl, j) ? -g.a[j][i] : 0.0;
+  double B = 0.0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    double lv = 0.0, rv = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      lv += F.Ai[a][b] * Dv[b];
+      rv += F.Ai[b][a] * Dv[b];
+    }
+    F.l[a] = lv;
+    F.r[a] = rv;
+    B += Dv[a] * lv;
+  }
+  if (!ok || !isfinite(B) || !(fabs(B) > 0.0)) report(err, ERR_SINGULAR, k);
+  const bool k0 = fl & F_K0;
+  F.invB = k0 ? 0.0 : 1.0 / B;
+  if (k0) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) F.l[a] = F.r[a] = 0.0;
+  }
+  // right-hand side: eq. defrhs + Newton completion + transient lumped mass
+  double fb[2] = {fbar[k * 2], fbar[k * 2 + 1]};
+  fin = fin && isfinite(fb[0]) && isfinite(fb[1]);
+  double R[6];
+  const double m = mu * g.vol / 3.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double proj = 0.5 * (fb[0] * (g.xK[0] - g.X[j][0]) + fb[1] * (g.xK[1] - g.X[j][1]));
+    bool in = interior(fl, j);
+    int f = in ? eface[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      double rr = g.a[j][i] * proj + Nuu[j][i];
+      if (uprev != nullptr && in) rr += m * uprev[(int64_t)f * 2 + i];
+      R[j * 2 + i] = in ? rr : 0.0;
+    }
+  }
+  if (!fin) report(err, ERR_NONFINITE, k);
+  double rR = 0.0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) rR += F.r[a] * R[a];
+  rR *= F.invB;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) t += F.Ai[a][b] * R[b];
+    RK[(int64_t)a * ne + k] = R[a];
+    sK[(int64_t)a * ne + k] = csign(fl, a / 2) * (t - F.l[a] * rR);
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = 0; b < 6; ++b) pack[(int64_t)(a * 6 + b) * ne + k] = F.Ai[a][b];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    pack[(int64_t)(36 + a) * ne + k] = F.l[a];
+    pack[(int64_t)(42 + a) * ne + k] = F.r[a];
+  }
+  pack[(int64_t)48 * ne + k] = F.invB;
+}
+
+// ---------------------------------------------------------------------------
+// a3: gather assembly of G (Section 3.2 item 5: G = sum_K H_K G_K H_K^t) into
+// block-ELL, one thread per interior face row f.  Slot 0 is the diagonal block
+// (sum over the two elements of f); slots 1..d the other faces of the owner K
+// in local order, slots d+1..2d those of the other element L.  Exterior faces
+// give a zero block pointing at f itself.  Writes the unscaled G, S, and the
+// Jacobi scale dsq = sqrt|diag G|; a second pass scales.
+//   Stokes: G_K[(j,i),(l,i')] = c_j c_l (delta_ii' S^{-1}_jl - V_ji V_li' / B)
+//   NS:     G_K[(j,i),(l,i')] = c_j c_l (A^{-1}[(j,i),(l,i')] - l_(j,i) r_(l,i') / B)
+// ---------------------------------------------------------------------------
+template <int D, bool NSK>
+struct BlockSrc;
+
+template <int D>
+struct BlockSrc<D, false> {
+  StokesFactors<D> F;
+  __device__ void load(const double* pack, int64_t ne, int64_t k) { load_stokes_pack<D>(pack, ne, k, F); }
+  __device__ double g(int j, int i, int l, int ip) const {
+    return (i == ip ? F.Si[j][l] : 0.0) - F.V[j][i] * F.V[l][ip] * F.invB;
+  }
+};
+
+template <>
+struct BlockSrc<2, true> {
+  NsFactors F;
+  __device__ void load(const double* pack, int64_t ne, int64_t k) { load_ns_pack(pack, ne, k, F); }
+  __device__ double g(int j, int i, int l, int ip) const {
+    return F.Ai[j * 2 + i][l * 2 + ip] - F.l[j * 2 + i] * F.r[l * 2 + ip] * F.invB;
+  }
+};
+
+template <int D, bool NSK>
+__global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, const int32_t* __restrict__ fel,
+                                                      const int32_t* __restrict__ floc,
+                                                      const int32_t* __restrict__ eface,
+                                                      const uint32_t* __restrict__ eflags,
+                                                      const double* __restrict__ pack,
+                                                      const double* __restrict__ sK, int32_t* __restrict__ cols,
+                                                      double* __restrict__ G, double* __restrict__ dsq,
+                                                      double* __restrict__ bs, int32_t* err) {
+  constexpr int N = D + 1, DD = D * D;
+  int64_t f = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t e2[2] = {fel[f], fel[nf + f]};
+  const int lc = floc[f];
+  const int jj[2] = {lc & 0xff, (lc >> 8) & 0xff};
+  double diag[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int ip = 0; ip < D; ++ip) diag[i][ip] = 0.0;
+  double Sf[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) Sf[i] = 0.0;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int64_t K = e2[side];
+    const int j = jj[side];
+    BlockSrc<D, NSK> src;
+    src.load(pack, ne, K);
+    const uint32_t fl = eflags[K];
+    const double cj = csign(fl, j);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      Sf[i] += sK[(int64_t)(j * D + i) * ne + K];
+#pragma unroll
+      for (int ip = 0; ip < D; ++ip) diag[i][ip] += src.g(j, i, j, ip);
+    }
+    int slot = 1 + side * D;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      if (l == j) continue;
+      const bool in = interior(fl, l);
+      const int64_t col = in ? eface[l * ne + K] : f;
+      const double c = cj * csign(fl, l);
+      cols[(int64_t)(slot - 1) * nf + f] = (int32_t)col;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int ip = 0; ip < D; ++ip)
+          G[(int64_t)(slot * DD + i * D + ip) * nf + f] = in ? c * src.g(j, i, l, ip) : 0.0;
+      ++slot;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+#pragma unroll
+    for (int ip = 0; ip < D; ++ip) G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
+    const double dg = fabs(diag[i][i]);
+    if (!(dg > 0.0) || !isfinite(dg)) report(err, ERR_ZERODIAG, f);
+    const double sq = sqrt(dg);
+    dsq[f * D + i] = sq;
+    bs[f * D + i] = Sf[i] / sq;
+  }
+}
+
+// scale G by dsq on both sides and round a copy to FP32
+template <int D>
+__global__ void __launch_bounds__(BS) k_face_scale(int64_t nf, const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ dsq, double* __restrict__ G,
+                                                   float* __restrict__ G32) {
+  constexpr int DD = D * D;
+  int64_t f = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (f >= nf) return;
+  double rs[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) rs[i] = 1.0 / dsq[f * D + i];
+#pragma unroll
+  for (int s = 0; s <= 2 * D; ++s) {
+    const int64_t c = s == 0 ? f : (int64_t)cols[(int64_t)(s - 1) * nf + f];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int ip = 0; ip < D; ++ip) {
+        const int64_t idx = (int64_t)(s * DD + i * D + ip) * nf + f;
+        const double v = G[idx] * rs[i] / dsq[c * D + ip];
+        G[idx] = v;
+        G32[idx] = (float)v;
+      }
+  }
+}
+
+// S re-gather for a new right-hand side (a6)
+template <int D>
+__global__ void __launch_bounds__(BS) k_face_rhs(int64_t nf, int64_t ne, const int32_t* __restrict__ fel,
+                                                 const int32_t* __restrict__ floc, const double* __restrict__ sK,
+                                                 const double* __restrict__ dsq, double* __restrict__ bs) {
+  int64_t f = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t K = fel[f], L = fel[nf + f];
+  const int lc = floc[f];
+  const int jK = lc & 0xff, jL = (lc >> 8) & 0xff;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    bs[f * D + i] = (sK[(int64_t)(jK * D + i) * ne + K] + sK[(int64_t)(jL * D + i) * ne + L]) / dsq[f * D + i];
+}
+
+// ---------------------------------------------------------------------------
+// a5: recovery, one thread per element.  W_K from the resident scaled solution
+// y = dsq * W.  P_K = r_K^t (R_K - C_K W_K) / B_K, U^_K = A^_K^{-1}(R_K - C_K W_K) - P_K l_K.
+// The copy with C = +1 is written to U (canonical order); the other copy goes
+// to Ujump for the mismatch diagnostic.
+// ---------------------------------------------------------------------------
+template <int D, bool NSK>
+__global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __restrict__ y,
+                                                const double* __restrict__ dsq, const double* __restrict__ pack,
+                                                const double* __restrict__ RK, const int32_t* __restrict__ eface,
+                                                const uint32_t* __restrict__ eflags,
+                                                const int32_t* __restrict__ ecaller,
+                                                const int32_t* __restrict__ fcanon, double* __restrict__ U,
+                                                double* __restrict__ P, double* __restrict__ Ujump) {
+  constexpr int N = D + 1;
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  const uint32_t fl = eflags[k];
+  double rhs[N][D];
+  int fc[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool in = interior(fl, j);
+    const int64_t f = in ? eface[j * ne + k] : 0;
+    fc[j] = in ? fcanon[f] : -1;
+    const double c = csign(fl, j);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double w = in ? y[f * D + i] / dsq[f * D + i] : 0.0;
+      rhs[j][i] = RK[(int64_t)(j * D + i) * ne + k] - c * w;
+    }
+  }
+  double u[N][D];
+  double p = 0.0;
+  if constexpr (!NSK) {
+    StokesFactors<D> F;
+    load_stokes_pack<D>(pack, ne, k, F);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < D; ++i) p += F.V[j][i] * rhs[j][i];
+    p *= F.invB;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) t += F.Si[j][l] * rhs[l][i];
+        u[j][i] = t - p * F.V[j][i];
+      }
+  } else {
+    NsFactors F;
+    load_ns_pack(pack, ne, k, F);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) p += F.r[a] * rhs[a / 2][a % 2];
+    p *= F.invB;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) t += F.Ai[a][b] * rhs[b / 2][b % 2];
+      u[a / 2][a % 2] = t - p * F.l[a];
+    }
+  }
+  P[ecaller[k]] = p;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (fc[j] < 0) continue;
+    double* dst = csign(fl, j) > 0.0 ? U : Ujump;
+    if (dst == nullptr) continue;
+#pragma unroll
+    for (int i = 0; i < D; ++i) dst[(int64_t)fc[j] * D + i] = u[j][i];
+  }
+}
+
+// deterministic sum of squared differences: per-block partials then one block
+__global__ void __launch_bounds__(256) k_sqdiff_partial(int64_t n, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double t = a[i] - b[i];
+    s += t * t;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_sqrt(int n, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(sh[0]);
+}
+
+// input permutation gathers
+__global__ void k_gather_rows(int64_t n, int width, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n * width) return;
+  int64_t r = t / width;
+  int c = (int)(t - r * width);
+  dst[t] = src[(int64_t)idx[r] * width + c];
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static cr_status read_err(cr_system* s, const char* stage) {
+  int32_t h[2];
+  cr_status st = check_hip(hipMemcpyAsync(h, s->err, sizeof h, hipMemcpyDeviceToHost, s->stream), stage);
+  if (st != CR_OK) return st;
+  st = check_hip(hipStreamSynchronize(s->stream), stage);
+  if (st != CR_OK) return st;
+  if (h[0] == 0) return CR_OK;
+  int64_t id = h[1];
+  if (h[0] & ERR_NONFINITE) {
+    set_error("%s: non-finite input at internal index %lld", stage, (long long)id);
+    return CR_E_NONFINITE;
+  }
+  if (h[0] & ERR_ZERODIAG) {
+    set_error("%s: zero or non-finite diagonal of G (internal face %lld)", stage, (long long)id);
+    return CR_E_SINGULAR;
+  }
+  int64_t caller = (id >= 0 && id < s->ne) ? s->topo.elem_iperm[id] : id;
+  set_error("%s: singular local system or B_K not positive at element %lld", stage, (long long)caller);
+  return CR_E_SINGULAR;
+}
+
+static cr_status reset_err(cr_system* s) {
+  int32_t h[2] = {0, INT32_MAX};
+  return check_hip(hipMemcpyAsync(s->err, h, sizeof h, hipMemcpyHostToDevice, s->stream), "reset error word");
+}
+
+static cr_status gather_inputs(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin) {
+  const int d = s->d;
+  if (f_mean) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblocks(s->ne * d, 256)), dim3(256), 0, s->stream, s->ne, d, s->ecaller,
+                       f_mean, s->fbar);
+  }
+  if (u_prev) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblocks(s->nf * d, 256)), dim3(256), 0, s->stream, s->nf, d, s->fcanon,
+                       u_prev, s->uprev);
+  }
+  if (u_lin) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblocks(s->nf * d, 256)), dim3(256), 0, s->stream, s->nf, d, s->fcanon,
+                       u_lin, s->ulin);
+  }
+  return check_hip(hipGetLastError(), "gather inputs");
+}
+
+cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin) {
+  const int d = s->d;
+  const bool ns = s->params.problem == CR_NS_NEWTON;
+  const bool steady = s->params.mu == 0.0;
+  cr_status st = reset_err(s);
+  if (st != CR_OK) return st;
+  st = gather_inputs(s, f_mean, u_prev, u_lin);
+  if (st != CR_OK) return st;
+  const double* up = u_prev ? s->uprev : nullptr;
+  const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
+  if (ns) {
+    if (steady)
+      hipLaunchKernelGGL(k_ns_lambda, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->ulin,
+                         s->params.mu, s->params.nu, s->lam);
+    hipLaunchKernelGGL(k_elim_ns, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->enb,
+                       steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack, s->RK,
+                       s->sK, s->err);
+    hipLaunchKernelGGL((k_face_assemble<2, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
+                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
+    hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+  } else if (d == 2) {
+    if (steady)
+      hipLaunchKernelGGL(k_stokes_lambda<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
+                         s->params.mu, s->params.nu, s->lam);
+    hipLaunchKernelGGL(k_elim_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
+                       s->sK, s->err);
+    hipLaunchKernelGGL((k_face_assemble<2, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
+                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
+    hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+  } else {
+    if (steady)
+      hipLaunchKernelGGL(k_stokes_lambda<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
+                         s->params.mu, s->params.nu, s->lam);
+    hipLaunchKernelGGL(k_elim_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
+                       s->sK, s->err);
+    hipLaunchKernelGGL((k_face_assemble<3, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
+                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
+    hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+  }
+  st = check_hip(hipGetLastError(), "eliminate launch");
+  if (st != CR_OK) return st;
+  st = read_err(s, "cr_eliminate");
+  if (st != CR_OK) return st;
+  st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * d, s->stream), "zero W");
+  if (st != CR_OK) return st;
+  s->eliminated = true;
+  s->has_solution = false;
+  return CR_OK;
+}
+
+cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_prev) {
+  const int d = s->d;
+  cr_status st = reset_err(s);
+  if (st != CR_OK) return st;
+  st = gather_inputs(s, f_mean, u_prev, nullptr);
+  if (st != CR_OK) return st;
+  const double* up = u_prev ? s->uprev : nullptr;
+  const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
+  if (d == 2) {
+    hipLaunchKernelGGL(k_rhs_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
+                       s->fbar, up, s->params.mu, s->pack, s->RK, s->sK, s->err);
+    hipLaunchKernelGGL(k_face_rhs<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->sK, s->dsq,
+                       s->bs);
+  } else {
+    hipLaunchKernelGGL(k_rhs_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
+                       s->fbar, up, s->params.mu, s->pack, s->RK, s->sK, s->err);
+    hipLaunchKernelGGL(k_face_rhs<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->sK, s->dsq,
+                       s->bs);
+  }
+  return check_hip(hipGetLastError(), "update_rhs launch");
+}
+
+cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {
+  const int d = s->d;
+  const bool ns = s->params.problem == CR_NS_NEWTON;
+  double* Uj = nullptr;
+  if (jump) {
+    if (!s->ujump) s->ujump = (double*)dev_alloc(s, sizeof(double) * (s->nf * d + 1024));
+    if (!s->ujump) return CR_E_NOMEM;
+    Uj = s->ujump;
+  }
+  const unsigned ge = nblocks(s->ne, BS);
+  if (ns)
+    hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+  else if (d == 2)
+    hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+  else
+    hipLaunchKernelGGL((k_recover<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+  if (jump) {
+    const int64_t n = s->nf * d;
+    hipLaunchKernelGGL(k_sqdiff_partial, dim3(1024), dim3(256), 0, s->stream, n, U, Uj, Uj + n);
+    hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s->stream, 1024, Uj + n, jump);
+  }
+  return check_hip(hipGetLastError(), "recover launch");
+}
+
+}  // namespace crh

@@ -1,0 +1,121 @@
+// Internal declarations of the crhyb library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/crhyb.h"
+
+namespace crh {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+// ---------------------------------------------------------------------------
+// host topology (step a0)
+// ---------------------------------------------------------------------------
+struct Topology {
+  int d = 0;
+  int64_t ne = 0, nv = 0, nf = 0;
+  // caller element order / canonical face order
+  std::vector<int32_t> elem_face;      // [ne][d+1] canonical interior face of local face j, -1 exterior
+  std::vector<int32_t> face_vertices;  // [nf][d] sorted vertex ids
+  std::vector<int32_t> face_elem;      // [nf][2] caller element ids, K < L
+  std::vector<int8_t> face_loc;        // [nf][2] local face index in K and in L
+  std::vector<uint8_t> m1;             // [ne] element partition M1 (mu == 0 only)
+  // renumbering
+  std::vector<int32_t> face_perm;      // canonical -> internal
+  std::vector<int32_t> face_iperm;     // internal -> canonical
+  std::vector<int32_t> elem_perm;      // caller -> internal
+  std::vector<int32_t> elem_iperm;     // internal -> caller
+  int64_t bw_internal = 0, bw_canonical = 0;
+};
+
+// Returns CR_OK or an error (message set).  need_m1: compute the M1/M2 split.
+cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, Topology& t);
+
+// element flag bits (device eflags)
+constexpr uint32_t F_INTERIOR0 = 1u;        // bit j: local face j interior
+constexpr uint32_t F_NEG0 = 1u << 8;        // bit 8+j: C_K = -1 on local face j
+constexpr uint32_t F_K0 = 1u << 16;         // pinned pressure element
+constexpr uint32_t F_M1 = 1u << 17;         // element in M1 (E_K = -lambda I)
+
+constexpr int NT = 256;                     // threads per block of the row kernels
+
+}  // namespace crh
+
+// ---------------------------------------------------------------------------
+// the opaque system
+// ---------------------------------------------------------------------------
+struct CgState;
+
+struct cr_system {
+  int d = 0;
+  int64_t ne = 0, nf = 0;
+  cr_params params{};
+  crh::Topology topo;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  cr_allocator alloc{};
+  bool has_alloc = false;
+  std::vector<void*> owned;
+
+  // element data, internal element order, structure of arrays
+  double* ecoord = nullptr;    // [(d+1)*d][ne] vertex coordinates
+  int32_t* eface = nullptr;    // [d+1][ne] internal interior face or -1
+  uint32_t* eflags = nullptr;  // [ne]
+  int32_t* ecaller = nullptr;  // [ne] caller id
+  int32_t* enb = nullptr;      // [d+1][ne] internal neighbour across local face j or -1
+  // face data, internal face order
+  int32_t* fel = nullptr;      // [2][nf] internal (owner K, other L)
+  int32_t* floc = nullptr;     // [nf] jK | jL << 8
+  int32_t* fcanon = nullptr;   // [nf] canonical id
+  int32_t* cols = nullptr;     // [2d][nf] off-diagonal block columns (self if padded)
+  // elimination products
+  double* pack = nullptr;      // [npack][ne] element factors
+  double* RK = nullptr;        // [(d+1)*d][ne] local right-hand side R_K
+  double* sK = nullptr;        // [(d+1)*d][ne] local s_K
+  double* lam = nullptr;       // [ne] lambda of M1 elements (mu == 0)
+  double* G64 = nullptr;       // [(2d+1)*d*d][nf] scaled G, FP64
+  float* G32 = nullptr;        // same, rounded to FP32
+  double* dsq = nullptr;       // [nf*d] sqrt|diag G|
+  double* bs = nullptr;        // [nf*d] S / dsq
+  double* y = nullptr;         // [nf*d] dsq * W (resident solution, scaled)
+  double* fbar = nullptr;      // [ne*d] internal element order
+  double* uprev = nullptr;     // [nf*d] internal face order
+  double* ulin = nullptr;      // [nf*d] internal face order
+  int32_t* err = nullptr;      // [4] device error word, first element
+  double* ujump = nullptr;     // [nf*d + 1024] non-owner copies for the mismatch diagnostic
+  int npack = 0;
+  bool eliminated = false;
+  bool has_solution = false;
+
+  // Krylov workspace (allocated on first solve)
+  void* kws = nullptr;
+};
+
+namespace crh {
+
+void* dev_alloc(cr_system* s, size_t bytes);
+cr_status check_hip(hipError_t e, const char* what);
+
+// element / face kernels (elements.hip)
+cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin);
+cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_prev);
+cr_status run_recover(cr_system* s, double* U, double* P, double* jump);
+
+// Krylov (krylov.hip)
+cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info);
+cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, double* bytes);
+void free_krylov(cr_system* s);
+
+// coupled baseline (coupled.hip)
+cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P);
+
+}  // namespace crh

@@ -1,0 +1,334 @@
+// Step a0: face topology, sign choice, reverse Cuthill-McKee face order, element
+// order and the element partition M1/M2.  Host code only (no device calls).
+//
+// Paper: Section 2 item 1 (simplicial mesh, faces, M_sigma with one or two
+// elements), Section 3.2 eq. propc (C_K = +-1, opposite on the two sides of a
+// face), Section 3.2 item 7 (M1/M2 partition for mu = 0), Section 3.2 item 5
+// (G has the block stencil of A, which the face adjacency below describes).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+
+#include "internal.h"
+
+namespace crh {
+
+namespace {
+
+struct LocalFace {
+  uint32_t v[3];
+  int32_t elem;
+  int8_t loc;
+};
+
+bool key_less(const LocalFace& a, const LocalFace& b) {
+  if (a.v[0] != b.v[0]) return a.v[0] < b.v[0];
+  if (a.v[1] != b.v[1]) return a.v[1] < b.v[1];
+  if (a.v[2] != b.v[2]) return a.v[2] < b.v[2];
+  if (a.elem != b.elem) return a.elem < b.elem;
+  return a.loc < b.loc;
+}
+
+bool key_eq(const LocalFace& a, const LocalFace& b) {
+  return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.v[2] == b.v[2];
+}
+
+// BFS levels from `root` restricted to unvisited-in-component nodes; returns the
+// last level and fills `depth` for the component.
+int bfs_eccentricity(int root, const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
+                     std::vector<int32_t>& depth, std::vector<int32_t>& touched, std::vector<int32_t>& last) {
+  for (int v : touched) depth[v] = -1;
+  touched.clear();
+  std::vector<int32_t> frontier{root};
+  depth[root] = 0;
+  touched.push_back(root);
+  int level = 0;
+  last = frontier;
+  while (!frontier.empty()) {
+    std::vector<int32_t> next;
+    for (int v : frontier)
+      for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) {
+        int w = adj[e];
+        if (depth[w] < 0) {
+          depth[w] = level + 1;
+          touched.push_back(w);
+          next.push_back(w);
+        }
+      }
+    if (!next.empty()) {
+      last = next;
+      ++level;
+    }
+    frontier.swap(next);
+  }
+  return level;
+}
+
+}  // namespace
+
+cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, Topology& t) {
+  const int d = mesh->dim;
+  if (d != 2 && d != 3) {
+    set_error("dim must be 2 or 3 (got %d)", d);
+    return CR_E_INVAL;
+  }
+  const int d1 = d + 1;
+  const int64_t ne = mesh->n_elements, nv = mesh->n_vertices;
+  if (ne < 1 || nv < d1 || !mesh->coords || !mesh->elem_vertices) {
+    set_error("empty mesh or NULL arrays");
+    return CR_E_INVAL;
+  }
+  if (ne * d1 > INT32_MAX || nv > INT32_MAX) {
+    set_error("mesh too large for 32-bit indices");
+    return CR_E_INVAL;
+  }
+  t = Topology();
+  t.d = d;
+  t.ne = ne;
+  t.nv = nv;
+  const int32_t* ev = mesh->elem_vertices;
+  const double* X = mesh->coords;
+
+  // validate elements: ids in range, distinct, non-degenerate
+  for (int64_t k = 0; k < ne; ++k) {
+    const int32_t* e = ev + k * d1;
+    for (int a = 0; a < d1; ++a) {
+      if (e[a] < 0 || e[a] >= nv) {
+        set_error("element %lld references vertex %d out of range", (long long)k, e[a]);
+        return CR_E_MESH;
+      }
+      for (int b = 0; b < a; ++b)
+        if (e[a] == e[b]) {
+          set_error("element %lld repeats a vertex", (long long)k);
+          return CR_E_MESH;
+        }
+    }
+    double E[3][3] = {};
+    double scale = 0.0;
+    for (int c = 0; c < d; ++c)
+      for (int r = 0; r < d; ++r) {
+        E[r][c] = X[(int64_t)e[c + 1] * d + r] - X[(int64_t)e[0] * d + r];
+        scale = std::max(scale, std::fabs(E[r][c]));
+      }
+    double det;
+    if (d == 2)
+      det = E[0][0] * E[1][1] - E[0][1] * E[1][0];
+    else
+      det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) - E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+            E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+    if (!(std::fabs(det) > 1e-14 * std::pow(scale, d)) || !std::isfinite(det)) {
+      set_error("element %lld has zero volume", (long long)k);
+      return CR_E_MESH;
+    }
+  }
+
+  // local faces, face j opposite local vertex j, key = sorted vertex ids
+  std::vector<LocalFace> lf((size_t)ne * d1);
+  for (int64_t k = 0; k < ne; ++k) {
+    const int32_t* e = ev + k * d1;
+    for (int j = 0; j < d1; ++j) {
+      LocalFace& f = lf[k * d1 + j];
+      int n = 0;
+      uint32_t v[3] = {0, 0, 0};
+      for (int a = 0; a < d1; ++a)
+        if (a != j) v[n++] = (uint32_t)e[a];
+      std::sort(v, v + d);
+      f.v[0] = v[0];
+      f.v[1] = v[1];
+      f.v[2] = d == 3 ? v[2] : 0u;
+      f.elem = (int32_t)k;
+      f.loc = (int8_t)j;
+    }
+  }
+  std::sort(lf.begin(), lf.end(), key_less);
+
+  t.elem_face.assign((size_t)ne * d1, -1);
+  int64_t nf = 0;
+  for (size_t i = 0; i < lf.size();) {
+    size_t j = i + 1;
+    while (j < lf.size() && key_eq(lf[i], lf[j])) ++j;
+    if (j - i > 2) {
+      set_error("a face is shared by %zu elements (element %d)", j - i, lf[i].elem);
+      return CR_E_MESH;
+    }
+    if (j - i == 2) {
+      // interior face: canonical id in lexicographic key order; K < L by caller id
+      for (int a = 0; a < d; ++a) t.face_vertices.push_back((int32_t)lf[i].v[a]);
+      t.face_elem.push_back(lf[i].elem);
+      t.face_elem.push_back(lf[i + 1].elem);
+      t.face_loc.push_back(lf[i].loc);
+      t.face_loc.push_back(lf[i + 1].loc);
+      t.elem_face[(size_t)lf[i].elem * d1 + lf[i].loc] = (int32_t)nf;
+      t.elem_face[(size_t)lf[i + 1].elem * d1 + lf[i + 1].loc] = (int32_t)nf;
+      ++nf;
+    }
+    i = j;
+  }
+  t.nf = nf;
+  if (nf == 0) {
+    set_error("mesh has no interior face");
+    return CR_E_MESH;
+  }
+  for (int64_t k = 0; k < ne; ++k) {
+    int s = 0;
+    for (int j = 0; j < d1; ++j) s += t.elem_face[k * d1 + j] >= 0;
+    if (s == 0) {
+      set_error("element %lld has no interior face", (long long)k);
+      return CR_E_MESH;
+    }
+  }
+
+  // face adjacency through elements (the block stencil of A and of G)
+  std::vector<int64_t> ptr(nf + 1, 0);
+  for (int64_t k = 0; k < ne; ++k)
+    for (int a = 0; a < d1; ++a) {
+      int fa = t.elem_face[k * d1 + a];
+      if (fa < 0) continue;
+      for (int b = 0; b < d1; ++b)
+        if (b != a && t.elem_face[k * d1 + b] >= 0) ptr[fa + 1]++;
+    }
+  for (int64_t f = 0; f < nf; ++f) ptr[f + 1] += ptr[f];
+  std::vector<int32_t> adj(ptr[nf]);
+  {
+    std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+    for (int64_t k = 0; k < ne; ++k)
+      for (int a = 0; a < d1; ++a) {
+        int fa = t.elem_face[k * d1 + a];
+        if (fa < 0) continue;
+        for (int b = 0; b < d1; ++b) {
+          int fb = t.elem_face[k * d1 + b];
+          if (b != a && fb >= 0) adj[pos[fa]++] = fb;
+        }
+      }
+  }
+
+  // face renumbering
+  t.face_perm.assign(nf, -1);
+  t.face_iperm.assign(nf, -1);
+  if (renumber == CR_NATURAL) {
+    for (int64_t f = 0; f < nf; ++f) t.face_perm[f] = t.face_iperm[f] = (int32_t)f;
+  } else if (renumber == CR_RCM) {
+    // Reverse Cuthill-McKee: per connected component, start from a
+    // pseudo-peripheral node (repeated BFS from a minimum-degree node of the
+    // last level), visit neighbours by increasing degree, reverse at the end.
+    std::vector<int32_t> deg(nf);
+    for (int64_t f = 0; f < nf; ++f) deg[f] = (int32_t)(ptr[f + 1] - ptr[f]);
+    std::vector<int32_t> order;
+    order.reserve(nf);
+    std::vector<uint8_t> seen(nf, 0);
+    std::vector<int32_t> depth(nf, -1), touched, last;
+    for (int64_t s0 = 0; s0 < nf; ++s0) {
+      if (seen[s0]) continue;
+      int root = (int)s0;
+      int ecc = bfs_eccentricity(root, ptr, adj, depth, touched, last);
+      for (int v : touched)  // minimum degree node of the component as the first guess
+        if (deg[v] < deg[root] || (deg[v] == deg[root] && v < root)) root = v;
+      ecc = bfs_eccentricity(root, ptr, adj, depth, touched, last);
+      for (int it = 0; it < 8; ++it) {
+        int cand = last[0];
+        for (int v : last)
+          if (deg[v] < deg[cand] || (deg[v] == deg[cand] && v < cand)) cand = v;
+        int e2 = bfs_eccentricity(cand, ptr, adj, depth, touched, last);
+        if (e2 <= ecc) break;
+        ecc = e2;
+        root = cand;
+      }
+      size_t head = order.size();
+      order.push_back(root);
+      seen[root] = 1;
+      std::vector<int32_t> nb;
+      while (head < order.size()) {
+        int v = order[head++];
+        nb.clear();
+        for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e)
+          if (!seen[adj[e]]) nb.push_back(adj[e]);
+        std::sort(nb.begin(), nb.end(), [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; });
+        for (int w : nb)
+          if (!seen[w]) {
+            seen[w] = 1;
+            order.push_back(w);
+          }
+      }
+    }
+    std::reverse(order.begin(), order.end());
+    for (int64_t i = 0; i < nf; ++i) {
+      t.face_iperm[i] = order[i];
+      t.face_perm[order[i]] = (int32_t)i;
+    }
+  } else {
+    set_error("unknown renumbering %d", renumber);
+    return CR_E_INVAL;
+  }
+  auto bandwidth = [&](const std::vector<int32_t>& pos) {
+    int64_t bw = 0;
+    for (int64_t f = 0; f < nf; ++f)
+      for (int64_t e = ptr[f]; e < ptr[f + 1]; ++e) bw = std::max<int64_t>(bw, std::llabs((int64_t)pos[f] - pos[adj[e]]));
+    return bw;
+  };
+  {
+    std::vector<int32_t> ident(nf);
+    std::iota(ident.begin(), ident.end(), 0);
+    t.bw_canonical = bandwidth(ident);
+    t.bw_internal = bandwidth(t.face_perm);
+  }
+
+  // element order: by smallest internal face id, ties by caller id
+  {
+    std::vector<int64_t> key(ne);
+    for (int64_t k = 0; k < ne; ++k) {
+      int64_t m = INT64_MAX;
+      for (int j = 0; j < d1; ++j) {
+        int f = t.elem_face[k * d1 + j];
+        if (f >= 0) m = std::min<int64_t>(m, t.face_perm[f]);
+      }
+      key[k] = m;
+    }
+    t.elem_iperm.resize(ne);
+    std::iota(t.elem_iperm.begin(), t.elem_iperm.end(), 0);
+    std::stable_sort(t.elem_iperm.begin(), t.elem_iperm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    t.elem_perm.resize(ne);
+    for (int64_t i = 0; i < ne; ++i) t.elem_perm[t.elem_iperm[i]] = (int32_t)i;
+  }
+
+  // M1: greedy maximal independent set in caller order (Section 3.2 item 7)
+  t.m1.assign(ne, 0);
+  if (need_m1) {
+    for (int64_t k = 0; k < ne; ++k) {
+      bool free_ = true;
+      for (int j = 0; j < d1 && free_; ++j) {
+        int f = t.elem_face[k * d1 + j];
+        if (f < 0) continue;
+        int other = t.face_elem[2 * f] == k ? t.face_elem[2 * f + 1] : t.face_elem[2 * f];
+        if (t.m1[other]) free_ = false;
+      }
+      t.m1[k] = free_ ? 1 : 0;
+    }
+  }
+  return CR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error_str() { return g_err.c_str(); }
+
+}  // namespace crh

@@ -1,0 +1,183 @@
+"""Parity of the HIP path with the CPU oracle (GPU only).
+
+Tolerances (stated by the task's accuracy targets and derived from the arithmetic):
+  * G, S (FP64 elimination): max |G_gpu - G_oracle| <= 1e-10 max |G_oracle|;
+  * FP64 path: ||U - U_o|| / ||U_o|| <= 1e-10 and the same for P;
+  * FP32 Krylov inside FP64 refinement: 1e-9.
+The solves run to a residual tolerance tight enough for these forward errors
+on the test meshes (condition numbers of G below 1e5 here).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import synth.workloads as wl
+from oracle import cr
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def make_case(name):
+    if name == "square16":
+        w = wl.square16()
+        return w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"], None, "stokes"
+    if name == "jitter12":
+        coords, elems = synth.square_mesh(12, jitter=0.2, seed=7)
+        fbar = np.random.default_rng(7).normal(size=(len(elems), 2))
+        return coords, elems, 300.0, 1.0, fbar, None, "stokes"
+    if name == "cube3":
+        coords, elems = synth.cube_mesh(3)
+        fbar = np.random.default_rng(8).normal(size=(len(elems), 3))
+        return coords, elems, 100.0, 1.0, fbar, None, "stokes"
+    if name == "steady10":
+        coords, elems = synth.square_mesh(10, jitter=0.1, seed=9)
+        fbar = np.random.default_rng(9).normal(size=(len(elems), 2))
+        return coords, elems, 0.0, 1.0, fbar, None, "stokes"
+    if name == "ns10":
+        w = wl.ns_square(10, nu=0.01, seed=2)
+        return w["coords"], w["elems"], 0.0, w["nu"], w["fbar"], w["ulin"], "ns"
+    raise KeyError(name)
+
+
+CASES = ["square16", "jitter12", "cube3", "steady10", "ns10"]
+
+
+def oracle_problem(case, k0=0):
+    coords, elems, mu, nu, fbar, ulin, prob = case
+    return cr.make_problem(coords, elems, mu, nu, fbar, ulin=ulin, k0=k0)
+
+
+def gpu_system(gpu, case, k0=0):
+    coords, elems, mu, nu, fbar, ulin, prob = case
+    s = gpu.System(coords, elems, mu, nu, k0=k0, problem=prob)
+    s.eliminate(dev(fbar), None, None if ulin is None else dev(ulin))
+    return s
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_faces_and_G_S(gpu, name):
+    case = make_case(name)
+    print(f"case {name}", flush=True)
+    P = oracle_problem(case)
+    s = gpu_system(gpu, case)
+    assert (s.interior_faces() == P.mesh.faces).all()
+    H = cr.eliminate(P)
+    G, S = s.export_G()
+    Go = H.G.tocsr()
+    Go.sum_duplicates()
+    Go.sort_indices()
+    assert G.nnz == Go.nnz == s.nnz_G
+    assert (G.indptr == Go.indptr).all() and (G.indices == Go.indices).all()
+    scale = np.abs(Go.data).max()
+    assert np.abs(G.data - Go.data).max() <= 1e-10 * scale
+    assert np.abs(S - H.S).max() <= 1e-10 * np.abs(H.S).max()
+    s.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_recover_from_oracle_W(gpu, name):
+    """Recovery alone: the oracle's W in, U and P out, against the oracle's recovery."""
+    case = make_case(name)
+    P = oracle_problem(case)
+    U_o, P_o, W_o, H, _ = cr.solve_hybrid(P)
+    s = gpu_system(gpu, case)
+    s.import_W(W_o)
+    U, Pk, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+    assert relerr(U.cpu().numpy(), U_o) <= 1e-10
+    assert relerr(Pk.cpu().numpy(), P_o) <= 1e-10
+    assert float(Pk[0]) == 0.0
+    # copy mismatch equals the residual of W (zero up to rounding here)
+    assert float(J.item()) <= 1e-9 * np.linalg.norm(H.S)
+    s.close()
+
+
+def test_jump_equals_residual_random_W(gpu):
+    """For any W the copy mismatch ||C^ U^|| equals ||S - G W|| (substitution of the
+    recovery relations into the C^ row of the three-field system)."""
+    case = make_case("jitter12")
+    P = oracle_problem(case)
+    H = cr.eliminate(P)
+    W = np.random.default_rng(3).normal(size=H.S.shape)
+    s = gpu_system(gpu, case)
+    s.import_W(W.reshape(-1, 2))
+    _, _, J = s.recover(jump=True)
+    ref = np.linalg.norm(H.S - H.G @ W)
+    assert abs(J.item() - ref) <= 1e-9 * ref
+    s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+@pytest.mark.parametrize("name", ["square16", "jitter12", "cube3"])
+def test_pcg_solution_parity(gpu, name, precision, bar):
+    case = make_case(name)
+    print(f"case {name} {precision}", flush=True)
+    P = oracle_problem(case)
+    U_o, P_o = cr.solve_coupled(P)
+    s = gpu_system(gpu, case)
+    info = s.solve("pcg", precision, tol=1e-13, check_every=8)
+    assert info["rel_residual"] <= 1e-13
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    assert relerr(U.cpu().numpy(), U_o) <= bar
+    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+@pytest.mark.parametrize("name", ["steady10", "ns10"])
+def test_bicgstab_solution_parity(gpu, name, precision, bar):
+    case = make_case(name)
+    print(f"case {name} {precision}", flush=True)
+    P = oracle_problem(case)
+    U_o, P_o = cr.solve_coupled(P)
+    s = gpu_system(gpu, case)
+    info = s.solve("bicgstab", precision, tol=1e-13, check_every=8, maxit=200000)
+    assert info["rel_residual"] <= 1e-13
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    assert relerr(U.cpu().numpy(), U_o) <= bar
+    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    s.close()
+
+
+def test_graph_and_plain_launches_agree(gpu):
+    """The captured-graph replay and plain launches run the same kernels: same iterates."""
+    case = make_case("jitter12")
+    s = gpu_system(gpu, case)
+    a = s.solve("pcg", "fp32_ir", tol=1e-11, check_every=6, graph=True)
+    Wa = s.export_W()
+    b = s.solve("pcg", "fp32_ir", tol=1e-11, check_every=6, graph=False)
+    Wb = s.export_W()
+    assert a["iters"] == b["iters"]
+    assert np.array_equal(Wa, Wb)
+    s.close()
+
+
+def test_error_paths(gpu):
+    case = make_case("square16")
+    coords, elems, mu, nu, fbar, _, _ = case
+    s = gpu.System(coords, elems, mu, nu)
+    with pytest.raises(gpu.CRError):
+        s.solve()                                   # before eliminate
+    bad = fbar.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(gpu.CRError) as e:
+        s.eliminate(dev(bad))
+    assert e.value.status == -7
+    s.eliminate(dev(fbar))
+    out = s.solve("pcg", "fp64", tol=1e-12, maxit=3, raise_on_error=False)
+    assert out["status"] == -5 and out["iters"] <= 3
+    s.close()
