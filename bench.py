@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybridised Crouzeix-Raviart transient-Stokes solve on one MI355X.
+
+Workload (default): 2D transient Stokes on the unit square, 512 x 512 cells cut
+into 2 triangles (524,288 elements), interior vertices jittered by up to 0.2 h
+(seeded), nu = 1, mu = 1/dt = 1000, homogeneous Dirichlet, right-hand side from
+a seeded smooth manufactured velocity; hybridised SPD system of 1,570,816
+unknowns solved to ||S - G W|| <= 1e-10 ||S|| (FP64 residual), FP32 CG inside
+FP64 iterative refinement, Jacobi scaling.
+
+One step = the whole hot path on device-resident inputs: element-wise
+elimination and assembly of G and S, Krylov solve, element-wise recovery of U
+and P.  The value is steps (solves) per second.  Also reported: the dominant
+kernel's achieved bandwidth against the HBM peak (timed with HIP events on the
+solver's stream), the FP64-Krylov variant, the FP64 MINRES solve of the
+original coupled system on the same GPU, and the CPU oracle on a bounded
+sample of the workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "hybridised solve time & SpMV HBM GB/s vs coupled solve; solves/s, p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for name in ("krylov.hip", "rowkern.h"):
+        with open(os.path.join(ROOT, "paper_2101_03777_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_oracle_baseline(ne_target, mu, nu, n_sample=128):
+    """Oracle (sparse LU of the coupled system, FP64) on a 128x128x2 sample of the
+    same workload family, scaled linearly in the element count to the target."""
+    import synth.workloads as wl
+    from oracle import cr
+    w = wl.square(n_sample, mu=mu, nu=nu, jitter=0.2, seed=0, quad=3)
+    t0, c0 = time.perf_counter(), time.process_time()
+    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+    cr.solve_coupled(P)
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    ne_s = len(w["elems"])
+    t_scaled = wall * ne_target / ne_s
+    return {"value": 1.0 / t_scaled, "unit": "solves/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": (f"oracle coupled sparse-LU solve (assembly + SuperLU + back-substitution, FP64) of the same "
+                       f"workload on {n_sample}x{n_sample}x2 elements ({ne_s}), {wall:.2f} s wall, scaled linearly "
+                       f"by element count to {ne_target} elements (sparse LU grows faster, so this favours the CPU)")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--n", type=int, default=512, help="cells per side (512 = the benchmark workload)")
+    ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--coupled-maxit", type=int, default=60000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_03777_amd as crh
+    import synth.workloads as wl
+
+    crh.load()
+    torch.cuda.set_device(0)
+    mu, nu, n = 1000.0, 1.0, args.n
+    t0 = time.perf_counter()
+    w = wl.square(n, mu=mu, nu=nu, jitter=0.2, seed=0, quad=3)
+    log(f"inputs {n}x{n}x2: {len(w['elems'])} elements, {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    s = crh.System(w["coords"], w["elems"], mu, nu)
+    t_topo = time.perf_counter() - t0
+    log(f"topology + upload: {t_topo:.2f} s, {s.n_int_faces} interior faces")
+    fbar = torch.from_numpy(w["fbar"]).cuda()
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        e0.record(stream)
+        s.eliminate(fbar)
+        e1.record(stream)
+        info = s.solve("pcg", args.precision, tol=args.tol)
+        e2.record(stream)
+        U, P = s.recover()
+        e3.record(stream)
+        e3.synchronize()
+        if record is not None:
+            record.append(dict(elim_ms=e0.elapsed_time(e1), solve_ms=e1.elapsed_time(e2),
+                               recover_ms=e2.elapsed_time(e3), total_ms=e0.elapsed_time(e3), **info))
+        return U, P
+
+    for k in range(args.warmup):
+        step(None)
+        log(f"warmup {k + 1}/{args.warmup} done")
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(recs)
+        log(f"step {k + 1}/{args.steps}: {recs[-1]['total_ms']:.1f} ms, {recs[-1]['iters']} iterations, "
+            f"rel residual {recs[-1]['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([r["total_ms"] for r in recs])
+    last = recs[-1]
+
+    # dominant kernel: SpMV fused with the CG direction updates, timed with HIP events
+    ms_k, bytes_k = s.time_spmv(args.precision, reps=200)
+    gbs = bytes_k / (ms_k * 1e-3) / 1e9
+    traffic = measured_traffic(f"square{n}j", "cg_spmv_" + args.precision)
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_cg_spmv<2,{'float' if args.precision == 'fp32_ir' else 'double'}>",
+                "avg_launch_us": round(ms_k * 1e3, 2), "algorithmic_bytes_per_launch": int(bytes_k)}
+    log(f"dominant kernel: {ms_k * 1e3:.2f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    # accuracy diagnostic: copy mismatch of the recovered velocity (equals the residual)
+    U, P, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+
+    # FP64 Krylov variant of the same solve
+    other = "fp64" if args.precision == "fp32_ir" else "fp32_ir"
+    s.eliminate(fbar)
+    info64 = s.solve("pcg", other, tol=args.tol)
+    log(f"{other} solve: {info64['t_solve_ms']:.1f} ms, {info64['iters']} iterations")
+
+    coupled = None
+    if not args.no_coupled:
+        Uc, Pc, ci = s.coupled_solve(tol=args.tol, maxit=args.coupled_maxit, raise_on_error=False)
+        torch.cuda.synchronize()
+        diff = (torch.linalg.norm(Uc - U) / torch.linalg.norm(U)).item()
+        coupled = {"method": "FP64 MINRES, diagonal block preconditioner diag(A) + diag(D diag(A)^-1 D^t)",
+                   "time_ms": round(ci["t_solve_ms"], 2), "iters": ci["iters"],
+                   "rel_residual": ci["rel_residual"], "converged": ci["status"] == 0,
+                   "rel_diff_U_vs_hybrid": diff}
+        log(f"coupled MINRES: {ci['t_solve_ms']:.1f} ms, {ci['iters']} iterations, "
+            f"residual {ci['rel_residual']:.2e}, converged={ci['status'] == 0}")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_oracle_baseline(len(w["elems"]), mu, nu)
+        log(f"cpu oracle: {cpu['value']:.4f} solves/s ({cpu['sample']})")
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / wall, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32_ir" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D transient Stokes, unit square {n}x{n} cells x2 triangles, jitter 0.2h (seed 0), "
+                               f"nu=1, mu=1/dt=1000, manufactured RHS; hybridised SPD system, Jacobi-scaled CG "
+                               f"({'FP32 inside FP64 iterative refinement' if args.precision == 'fp32_ir' else 'FP64'})"
+                               f" to rel residual {args.tol:g}",
+                   "elements": len(w["elems"]),
+                   "unknowns": s.n_int_faces * 2, "tol": args.tol, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_tol_ms": round(float(np.median([r["solve_ms"] for r in recs])), 3),
+        "iters": last["iters"], "outer_iters": last["outer_iters"], "rel_residual": last["rel_residual"],
+        "copy_mismatch": J.item(),
+        "eliminate_ms": round(float(np.median([r["elim_ms"] for r in recs])), 3),
+        "recover_ms": round(float(np.median([r["recover_ms"] for r in recs])), 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "topology_host_s": round(t_topo, 3),
+        f"{other}_time_to_tol_ms": round(info64["t_solve_ms"], 3), f"{other}_iters": info64["iters"],
+        "coupled_gpu": coupled,
+        "speedup_vs_coupled": (round(coupled["time_ms"] / float(np.median([r['solve_ms'] for r in recs])), 2)
+                               if coupled else None),
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

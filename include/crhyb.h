@@ -125,7 +125,8 @@ typedef struct {
   int32_t method;      /* CR_PCG (symmetric positive definite G) or CR_BICGSTAB */
   int32_t precision;   /* CR_FP64, or CR_FP32_IR: FP32 Krylov inside FP64 iterative refinement */
   double tol;          /* stop when ||S - G W||_2 <= tol ||S||_2, residual recomputed in FP64 */
-  double inner_tol;    /* relative tolerance of each inner (refinement) solve; <= 0: automatic */
+  double inner_tol;    /* factor by which the recursive residual falls between FP64 residual
+                          replacements (reliable updates); <= 0: automatic (0.1 for FP32) */
   int32_t maxit;       /* cap on the total number of Krylov iterations */
   int32_t max_outer;   /* cap on refinement passes */
   int32_t check_every; /* iterations per convergence poll (rounded up to even); <= 0: automatic */
@@ -139,12 +140,17 @@ typedef struct {
   double rel_residual;  /* ||S - G W|| / ||S|| in FP64 for the returned W */
   double t_solve_ms;    /* wall time of the call */
   int32_t reason;       /* 1 converged, 3 iteration limit, 4 breakdown, 5 non-finite */
+  int32_t fp32_iters;   /* iterations run in FP32 (CR_FP32_IR) */
+  int32_t fp64_fallback;/* 1 if CR_FP32_IR stalled and finished with FP64 iterations */
 } cr_solve_info;
 
 /* Step a4: Krylov solve of G W = S; W stays resident on the device.
  * PCG applies when mu > 0 and the problem is Stokes (G symmetric positive
  * definite, Section 3.2 item 6); BiCGStab otherwise.  Jacobi preconditioning
  * is applied as the symmetric scaling |diag G|^{-1/2} G |diag G|^{-1/2}.
+ * CR_FP32_IR runs the Krylov recurrences in FP32 with FP64 residual
+ * replacements; if the FP32 iterations stop reducing the FP64 residual, the
+ * remaining iterations run in FP64 (reported in cr_solve_info.fp64_fallback).
  * Synchronises.  Errors: CR_E_NOCONV, CR_E_BREAKDOWN, CR_E_NONFINITE, CR_E_INVAL
  * (before cr_eliminate).  info may be NULL. */
 cr_status cr_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* info);

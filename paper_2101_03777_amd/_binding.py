@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -61,7 +62,8 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("rel_residual", C.c_double),
-                ("t_solve_ms", C.c_double), ("reason", C.c_int32)]
+                ("t_solve_ms", C.c_double), ("reason", C.c_int32), ("fp32_iters", C.c_int32),
+                ("fp64_fallback", C.c_int32)]
 
 
 _lib = None
@@ -172,7 +174,8 @@ class TorchAllocator:
     def _do_release(self, ptr, ctx, stream):
         if ptr in self.live:
             del self.live[ptr]
-            self._torch.cuda.caching_allocator_delete(ptr)
+            if not sys.is_finalizing():
+                self._torch.cuda.caching_allocator_delete(ptr)
 
     @property
     def bytes_in_use(self):
@@ -238,7 +241,8 @@ class System:
         info = SolveInfo()
         st = self.lib.cr_solve(self.h, C.byref(o), C.byref(info))
         out = dict(status=st, iters=info.iters, outer_iters=info.outer_iters, rel_residual=info.rel_residual,
-                   t_solve_ms=info.t_solve_ms, reason=info.reason)
+                   t_solve_ms=info.t_solve_ms, reason=info.reason, fp32_iters=info.fp32_iters,
+                   fp64_fallback=bool(info.fp64_fallback))
         if raise_on_error:
             _check(st)
         return out
@@ -299,6 +303,9 @@ class System:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the process releases device memory itself
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -37,6 +37,7 @@ namespace {
 
 void release_all(cr_system* s) {
   free_krylov(s);
+  free_coupled(s);
   for (void* p : s->owned) {
     if (s->has_alloc)
       s->alloc.release(p, s->alloc.ctx, (void*)s->stream);

@@ -1,9 +1,652 @@
-// Baseline: FP64 MINRES on the coupled system (filled in below).
+// Baseline: FP64 MINRES on the original coupled system (Section 3.1, eq. syslin)
+//     [A  D^t] [U]   [R]
+//     [D   0 ] [P] = [0]
+// on the same GPU, for the Stokes problem (A = S (x) I_d), preconditioned by
+// the positive diagonal diag(A) (+) diag(D diag(A)^{-1} D^t).  This is the
+// comparison the hybrid method is measured against; it is not on the hybrid
+// path.
+//
+// Storage: A as scalar face-ELL (the same face stencil and column table as G,
+// one value per face pair since A = S (x) I_d); D^t P at face row f is
+// -a_{K,f} (P_K - P_L) with a_{K,f} of the owner K; D U at element K is
+// -sum_j a_{K,j}.U_j over its interior faces (the K0 row is removed: its
+// coefficients are zero and its preconditioner entry is zero, so P_K0 stays 0).
+// Vector layout: [u (nf*d, internal face order) | p (ne, internal element order)].
+//
+// Preconditioned MINRES (Paige-Saunders recurrences), three kernels per
+// iteration with the same partial-record reductions, parity-slotted scalars
+// and device stop flag as the hybrid Krylov kernels; the three-term vector
+// recurrences rotate through three buffers, so graphs hold multiples of six
+// iterations.  Outer passes restart from the current iterate until the true
+// FP64 residual meets the tolerance.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "geometry.h"
 #include "internal.h"
+#include "rowkern.h"
 
 namespace crh {
-cr_status run_coupled_solve(cr_system*, const cr_solve_opts*, cr_solve_info*, double*, double*) {
-  set_error("coupled baseline not built yet");
-  return CR_E_INVAL;
+namespace {
+
+struct CState {
+  double beta[2], oldb[2], dbar[2], epsln[2], cs[2], sn[2], phibar[2], alfa[2];
+  int it[2];
+  int done;
+  int iters;
+  double beta1, tres2, bnorm2, thr;
+  // host parameters
+  double tol2;
+  int maxit;
+  int pad;
+};
+
+struct CDims {
+  int64_t nf, ne;
+  int nbf, nbe;        // blocks over face rows / element rows (multiples of 8)
+  int64_t cf, ce;      // rows per block
+};
+
+__device__ __forceinline__ bool face_block(const CDims& C, int64_t& lo, int64_t& hi, int& lb) {
+  int b = blockIdx.x;
+  if (b < C.nbf) {
+    lb = (b & 7) * (C.nbf >> 3) + (b >> 3);
+    lo = (int64_t)lb * C.cf;
+    hi = min(C.nf, lo + C.cf);
+    return true;
+  }
+  b -= C.nbf;
+  const int l = (b & 7) * (C.nbe >> 3) + (b >> 3);
+  lb = C.nbf + l;
+  lo = (int64_t)l * C.ce;
+  hi = min(C.ne, lo + C.ce);
+  return false;
 }
+
+// ---------------------------------------------------------------------------
+// assembly: A values per face row (slot 0 = diagonal), owner face vectors, the
+// per-element D coefficients, preconditioner, assembled R.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(128) k_coupled_faces(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
+                                                       const uint32_t* __restrict__ eflags,
+                                                       const int32_t* __restrict__ fel,
+                                                       const int32_t* __restrict__ floc, const double* __restrict__ RK,
+                                                       double mu, double nu, double* __restrict__ Aval,
+                                                       double* __restrict__ an, double* __restrict__ bvec,
+                                                       double* __restrict__ dinv) {
+  constexpr int N = D + 1;
+  int64_t f = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t e2[2] = {fel[f], fel[nf + f]};
+  const int lc = floc[f];
+  const int jj[2] = {lc & 0xff, (lc >> 8) & 0xff};
+  double diag = 0.0;
+  double R[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) R[i] = 0.0;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int64_t K = e2[side];
+    const int j = jj[side];
+    Geo<D> g;
+    load_geometry<D>(ecoord, ne, K, g);
+    const uint32_t fl = eflags[K];
+    const double m = mu * g.vol / N, iv = nu / g.vol;
+    int slot = 1 + side * D;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      double dot = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) dot += g.a[j][i] * g.a[l][i];
+      const double v = iv * dot + (l == j ? m : 0.0);
+      if (l == j) {
+        diag += v;
+      } else {
+        Aval[(int64_t)slot * nf + f] = interior(fl, l) ? v : 0.0;
+        ++slot;
+      }
+    }
+    if (side == 0)
+#pragma unroll
+      for (int i = 0; i < D; ++i) an[f * D + i] = g.a[j][i];
+#pragma unroll
+    for (int i = 0; i < D; ++i) R[i] += RK[(int64_t)(j * D + i) * ne + K];
+  }
+  Aval[f] = diag;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    bvec[f * D + i] = R[i];
+    dinv[f * D + i] = 1.0 / diag;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(128) k_coupled_elems(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
+                                                       const uint32_t* __restrict__ eflags,
+                                                       const int32_t* __restrict__ eface,
+                                                       const double* __restrict__ Aval, double* __restrict__ ea,
+                                                       double* __restrict__ bvec, double* __restrict__ dinv) {
+  constexpr int N = D + 1;
+  int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (k >= ne) return;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  const bool k0 = fl & F_K0;
+  double sch = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool in = interior(fl, j) && !k0;
+    double a2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      ea[(int64_t)(j * D + i) * ne + k] = in ? g.a[j][i] : 0.0;
+      a2 += g.a[j][i] * g.a[j][i];
+    }
+    if (in) sch += a2 / Aval[eface[j * ne + k]];
+  }
+  bvec[nf * D + k] = 0.0;
+  dinv[nf * D + k] = k0 ? 0.0 : 1.0 / sch;
+}
+
+// one row of y = M v for the coupled matrix M; In(c) gives v_u at face c,
+// Pin(k) gives v_p at element k
+template <int D, class In, class Pin>
+__device__ __forceinline__ void coupled_face_row(const double* __restrict__ Aval, const int32_t* __restrict__ cols,
+                                                 const double* __restrict__ an, const int32_t* __restrict__ fel,
+                                                 int64_t nf, int64_t f, const In& in, const Pin& pin,
+                                                 double (&y)[D]) {
+  Vec<double, D> x0 = in(f);
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[i] = Aval[f] * x0.v[i];
+#pragma unroll
+  for (int s = 1; s <= 2 * D; ++s) {
+    const int64_t c = cols[(int64_t)(s - 1) * nf + f];
+    const double a = Aval[(int64_t)s * nf + f];
+    Vec<double, D> xc = in(c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[i] += a * xc.v[i];
+  }
+  const double dp = pin(fel[f]) - pin(fel[nf + f]);
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[i] -= an[f * D + i] * dp;
+}
+
+template <int D, class In>
+__device__ __forceinline__ double coupled_elem_row(const double* __restrict__ ea, const int32_t* __restrict__ eface,
+                                                   int64_t ne, int64_t k, const In& in) {
+  double y = 0.0;
+#pragma unroll
+  for (int j = 0; j <= D; ++j) {
+    const int f = eface[j * ne + k];
+    if (f < 0) continue;
+    Vec<double, D> x = in(f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) y -= ea[(int64_t)(j * D + i) * ne + k] * x.v[i];
+  }
+  return y;
+}
+
+struct MatArgs {
+  const double* Aval;
+  const int32_t* cols;
+  const double* an;
+  const int32_t* fel;
+  const double* ea;
+  const int32_t* eface;
+};
+
+template <int D>
+struct ScaledU {  // dinv * r / beta on the velocity part
+  const double* __restrict__ r;
+  const double* __restrict__ dinv;
+  double sb;
+  __device__ Vec<double, D> operator()(int64_t c) const {
+    Vec<double, D> a = ldv<double, D>(r, c), w = ldv<double, D>(dinv, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.v[i] *= w.v[i] * sb;
+    return a;
+  }
+};
+struct ScaledP {
+  const double* __restrict__ r;
+  const double* __restrict__ dinv;
+  double sb;
+  __device__ double operator()(int64_t k) const { return r[k] * dinv[k] * sb; }
+};
+template <int D>
+struct PlainU {
+  const double* __restrict__ x;
+  __device__ Vec<double, D> operator()(int64_t c) const { return ldv<double, D>(x, c); }
+};
+struct PlainP {
+  const double* __restrict__ x;
+  __device__ double operator()(int64_t k) const { return x[k]; }
+};
+
+// residual r = b - M x (FP64), r1 = r2 = r; partials [0] r.dinv.r, [1] r.r, [2] b.b
+template <int D>
+__global__ void __launch_bounds__(NT) k_mr_init(CDims C, MatArgs M, const double* __restrict__ b,
+                                                const double* __restrict__ dinv, const double* __restrict__ x,
+                                                double* __restrict__ r1, double* __restrict__ r2,
+                                                double* __restrict__ w0, double* __restrict__ w1,
+                                                double* __restrict__ pa, CState* __restrict__ st) {
+  int64_t lo, hi;
+  int lb;
+  const bool fb = face_block(C, lo, hi, lb);
+  const int64_t off = C.nf * D;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (fb) {
+    for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+      double y[D];
+      coupled_face_row<D>(M.Aval, M.cols, M.an, M.fel, C.nf, f, PlainU<D>{x}, PlainP{x + off}, y);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double bi = b[f * D + i], ri = bi - y[i];
+        r1[f * D + i] = ri;
+        r2[f * D + i] = ri;
+        w0[f * D + i] = 0.0;
+        w1[f * D + i] = 0.0;
+        acc[0] += ri * ri * dinv[f * D + i];
+        acc[1] += ri * ri;
+        acc[2] += bi * bi;
+      }
+    }
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += NT) {
+      const double ri = -coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x});
+      r1[off + k] = ri;
+      r2[off + k] = ri;
+      w0[off + k] = 0.0;
+      w1[off + k] = 0.0;
+      acc[0] += ri * ri * dinv[off + k];
+      acc[1] += ri * ri;
+    }
+  }
+  block_sum<3>(acc);
+  if (threadIdx.x == 0) {
+    pa[(int64_t)lb * NPART] = acc[0];
+    pa[(int64_t)lb * NPART + 1] = acc[1];
+    pa[(int64_t)lb * NPART + 2] = acc[2];
+  }
+  if (lead()) {
+    st->it[1] = 0;
+    st->oldb[1] = 0.0;
+    st->dbar[1] = 0.0;
+    st->epsln[1] = 0.0;
+    st->cs[1] = -1.0;
+    st->sn[1] = 0.0;
+    st->iters = 0;
+    st->done = 0;
+  }
+}
+
+// MA: v = dinv r2 / beta, y = M v - (beta/oldb) r1, partial v.y
+template <int D>
+__global__ void __launch_bounds__(NT) k_mr_a(CDims C, MatArgs M, const double* __restrict__ dinv,
+                                             const double* __restrict__ r1, const double* __restrict__ r2,
+                                             double* __restrict__ v, double* __restrict__ y,
+                                             const double* __restrict__ pa, double* __restrict__ pb,
+                                             CState* __restrict__ st, int q) {
+  if (st->done) return;
+  const int p = q ^ 1;
+  const int it = st->it[p];
+  const bool first = it == 0;
+  double beta, oldb;
+  int done = 0;
+  if (first) {
+    double s[3];
+    reduce_partials<3>(pa, C.nbf + C.nbe, 0, s);
+    beta = sqrt(s[0]);
+    oldb = 0.0;
+    const double thr = 0.1 * sqrt(st->tol2 * s[2]) * (s[1] > 0.0 ? beta / sqrt(s[1]) : 1.0);
+    if (s[1] <= st->tol2 * s[2]) done = 2;
+    else if (!(beta > 0.0) || !isfinite(beta)) done = isfinite(beta) ? 4 : 5;
+    else if (it >= st->maxit) done = 3;
+    if (lead()) {
+      st->beta1 = beta;
+      st->tres2 = s[1];
+      st->bnorm2 = s[2];
+      st->thr = thr;
+      st->beta[p] = beta;
+      st->phibar[p] = beta;
+    }
+  } else {
+    beta = st->beta[p];
+    oldb = st->oldb[p];
+    if (st->phibar[p] <= st->thr) done = 1;
+    else if (it >= st->maxit) done = 3;
+  }
+  if (lead()) {
+    st->it[q] = it + 1;
+    st->iters = it;
+    if (done) st->done = done;
+  }
+  if (done) return;
+  const double sb = 1.0 / beta;
+  const double c1 = first ? 0.0 : beta / oldb;
+  int64_t lo, hi;
+  int lb;
+  const bool fb = face_block(C, lo, hi, lb);
+  const int64_t off = C.nf * D;
+  const ScaledU<D> inu{r2, dinv, sb};
+  const ScaledP inp{r2 + off, dinv + off, sb};
+  double acc[1] = {0.0};
+  if (fb) {
+    for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+      double yy[D];
+      coupled_face_row<D>(M.Aval, M.cols, M.an, M.fel, C.nf, f, inu, inp, yy);
+      Vec<double, D> vv = inu(f);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        yy[i] -= c1 * r1[f * D + i];
+        v[f * D + i] = vv.v[i];
+        y[f * D + i] = yy[i];
+        acc[0] += vv.v[i] * yy[i];
+      }
+    }
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += NT) {
+      const double yy = coupled_elem_row<D>(M.ea, M.eface, C.ne, k, inu) - c1 * r1[off + k];
+      const double vv = inp(k);
+      v[off + k] = vv;
+      y[off + k] = yy;
+      acc[0] += vv * yy;
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) pb[(int64_t)lb * NPART] = acc[0];
+}
+
+// MB: alfa = v.y; y -= (alfa/beta) r2 (y becomes the new r2); partial y.dinv.y
+__global__ void __launch_bounds__(NT) k_mr_b(CDims C, int64_t n, const double* __restrict__ dinv,
+                                             const double* __restrict__ r2, double* __restrict__ y,
+                                             const double* __restrict__ pb, double* __restrict__ pc,
+                                             CState* __restrict__ st, int q) {
+  if (st->done) return;
+  double s[1];
+  reduce_partials<1>(pb, C.nbf + C.nbe, 0, s);
+  const double alfa = s[0];
+  const double beta = st->beta[q ^ 1];
+  const double c2 = alfa / beta;
+  // flat partition of all n entries over the same number of blocks
+  const int nb = C.nbf + C.nbe;
+  const int lb = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)lb * per, hi = min(n, lo + per);
+  double acc[1] = {0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const double yy = y[i] - c2 * r2[i];
+    y[i] = yy;
+    acc[0] += yy * yy * dinv[i];
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) pc[(int64_t)lb * NPART] = acc[0];
+  if (lead()) st->alfa[q] = alfa;
+}
+
+// MC: beta_new = sqrt(partials); plane rotations; w = (v - oldeps w1 - delta w2)/gamma; x += phi w
+__global__ void __launch_bounds__(NT) k_mr_c(CDims C, int64_t n, const double* __restrict__ v,
+                                             const double* __restrict__ w1, const double* __restrict__ w2,
+                                             double* __restrict__ wn, double* __restrict__ x,
+                                             const double* __restrict__ pc, CState* __restrict__ st, int q) {
+  if (st->done) return;
+  double s[1];
+  reduce_partials<1>(pc, C.nbf + C.nbe, 0, s);
+  const int p = q ^ 1;
+  if (!(s[0] >= 0.0) || !isfinite(s[0])) {
+    if (lead()) st->done = isfinite(s[0]) ? 4 : 5;
+    return;
+  }
+  const double beta = sqrt(s[0]);
+  const double oldb = st->beta[p];
+  const double alfa = st->alfa[q];
+  const double cs = st->cs[p], sn = st->sn[p], dbar = st->dbar[p], oldeps = st->epsln[p];
+  const double delta = cs * dbar + sn * alfa;
+  const double gbar = sn * dbar - cs * alfa;
+  const double epsln = sn * beta;
+  const double dbar_n = -cs * beta;
+  const double gamma = fmax(hypot(gbar, beta), 1e-300);
+  const double cs_n = gbar / gamma, sn_n = beta / gamma;
+  const double phibar = st->phibar[p];
+  const double phi = cs_n * phibar;
+  const double phibar_n = sn_n * phibar;
+  const double den = 1.0 / gamma;
+  const int nb = C.nbf + C.nbe;
+  const int lb = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)lb * per, hi = min(n, lo + per);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const double w = (v[i] - oldeps * w1[i] - delta * w2[i]) * den;
+    wn[i] = w;
+    x[i] += phi * w;
+  }
+  if (lead()) {
+    st->beta[q] = beta;
+    st->oldb[q] = oldb;
+    st->cs[q] = cs_n;
+    st->sn[q] = sn_n;
+    st->dbar[q] = dbar_n;
+    st->epsln[q] = epsln;
+    st->phibar[q] = phibar_n;
+  }
+}
+
+// internal -> caller layouts
+template <int D>
+__global__ void k_mr_scatter(int64_t nf, int64_t ne, const double* __restrict__ x, const int32_t* __restrict__ fcanon,
+                             const int32_t* __restrict__ ecaller, double* __restrict__ U, double* __restrict__ P) {
+  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < nf) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) U[(int64_t)fcanon[t] * D + i] = x[t * D + i];
+  } else if (t < nf + ne) {
+    const int64_t k = t - nf;
+    P[ecaller[k]] = x[nf * D + k];
+  }
+}
+
+struct CWs {
+  CDims dims{};
+  int64_t n = 0;
+  double* Aval = nullptr;
+  double* an = nullptr;
+  double* ea = nullptr;
+  double* b = nullptr;
+  double* dinv = nullptr;
+  double* x = nullptr;
+  double* v = nullptr;
+  double* R[3] = {};
+  double* W[3] = {};
+  double* pa = nullptr;
+  double* pb = nullptr;
+  double* pc = nullptr;
+  CState* st = nullptr;
+  CState* hst = nullptr;
+  hipEvent_t ev[2] = {};
+  bool assembled = false;
+};
+
+CDims make_dims(int64_t nf, int64_t ne) {
+  CDims C;
+  C.nf = nf;
+  C.ne = ne;
+  auto part = [](int64_t rows, int& nb, int64_t& chunk) {
+    const int64_t tiles = (rows + (int64_t)NT * (MAXBLK / 2) - 1) / ((int64_t)NT * (MAXBLK / 2));
+    chunk = std::max<int64_t>(1, tiles) * NT;
+    int64_t b = (rows + chunk - 1) / chunk;
+    nb = (int)((b + 7) / 8 * 8);
+  };
+  part(nf, C.nbf, C.cf);
+  part(ne, C.nbe, C.ce);
+  return C;
+}
+
+cr_status ensure_cws(cr_system* s, CWs*& w) {
+  w = (CWs*)s->cws;
+  if (w) return CR_OK;
+  w = new CWs();
+  const int d = s->d;
+  w->dims = make_dims(s->nf, s->ne);
+  w->n = s->nf * d + s->ne;
+  const size_t vb = sizeof(double) * w->n;
+  w->Aval = (double*)dev_alloc(s, sizeof(double) * (2 * d + 1) * s->nf);
+  w->an = (double*)dev_alloc(s, sizeof(double) * d * s->nf);
+  w->ea = (double*)dev_alloc(s, sizeof(double) * (d + 1) * d * s->ne);
+  w->b = (double*)dev_alloc(s, vb);
+  w->dinv = (double*)dev_alloc(s, vb);
+  w->x = (double*)dev_alloc(s, vb);
+  w->v = (double*)dev_alloc(s, vb);
+  for (auto& r : w->R) r = (double*)dev_alloc(s, vb);
+  for (auto& r : w->W) r = (double*)dev_alloc(s, vb);
+  const size_t pbytes = sizeof(double) * (w->dims.nbf + w->dims.nbe) * NPART;
+  w->pa = (double*)dev_alloc(s, pbytes);
+  w->pb = (double*)dev_alloc(s, pbytes);
+  w->pc = (double*)dev_alloc(s, pbytes);
+  w->st = (CState*)dev_alloc(s, sizeof(CState));
+  if (!w->Aval || !w->an || !w->ea || !w->b || !w->dinv || !w->x || !w->v || !w->R[2] || !w->W[2] || !w->pc ||
+      !w->st) {
+    delete w;
+    w = nullptr;
+    return CR_E_NOMEM;
+  }
+  cr_status st = check_hip(hipHostMalloc((void**)&w->hst, 2 * sizeof(CState), hipHostMallocDefault), "pinned");
+  for (auto& e : w->ev)
+    if (st == CR_OK) st = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  if (st != CR_OK) {
+    delete w;
+    w = nullptr;
+    return st;
+  }
+  s->cws = w;
+  return CR_OK;
+}
+
+void free_cws(CWs* w) {
+  if (!w) return;
+  for (auto& e : w->ev)
+    if (e) hipEventDestroy(e);
+  if (w->hst) hipHostFree(w->hst);
+  delete w;
+}
+
+template <int D>
+void enqueue_mr(cr_system* s, CWs* w, int k0, int niter) {
+  const CDims C = w->dims;
+  const MatArgs M{w->Aval, s->cols, w->an, s->fel, w->ea, s->eface};
+  const dim3 grid(C.nbf + C.nbe), blk(NT);
+  for (int k = k0; k < k0 + niter; ++k) {
+    const int q = k & 1;
+    double* r1 = w->R[k % 3];
+    double* r2 = w->R[(k + 1) % 3];
+    double* y = w->R[(k + 2) % 3];
+    double* w2old = w->W[k % 3];
+    double* wold = w->W[(k + 1) % 3];
+    double* wnew = w->W[(k + 2) % 3];
+    hipLaunchKernelGGL(k_mr_a<D>, grid, blk, 0, s->stream, C, M, w->dinv, r1, r2, w->v, y, w->pa, w->pb, w->st, q);
+    hipLaunchKernelGGL(k_mr_b, grid, blk, 0, s->stream, C, w->n, w->dinv, r2, y, w->pb, w->pc, w->st, q);
+    hipLaunchKernelGGL(k_mr_c, grid, blk, 0, s->stream, C, w->n, w->v, w2old, wold, wnew, w->x, w->pc, w->st, q);
+  }
+}
+
+template <int D>
+cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
+  auto t0 = std::chrono::steady_clock::now();
+  CWs* w = nullptr;
+  cr_status st = ensure_cws(s, w);
+  if (st != CR_OK) return st;
+  const CDims C = w->dims;
+  const MatArgs M{w->Aval, s->cols, w->an, s->fel, w->ea, s->eface};
+  hipLaunchKernelGGL(k_coupled_faces<D>, dim3((unsigned)((s->nf + 127) / 128)), dim3(128), 0, s->stream, s->nf, s->ne,
+                     s->ecoord, s->eflags, s->fel, s->floc, s->RK, s->params.mu, s->params.nu, w->Aval, w->an, w->b,
+                     w->dinv);
+  hipLaunchKernelGGL(k_coupled_elems<D>, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->nf, s->ne,
+                     s->ecoord, s->eflags, s->eface, w->Aval, w->ea, w->b, w->dinv);
+  st = check_hip(hipMemsetAsync(w->x, 0, sizeof(double) * w->n, s->stream), "coupled x");
+  const double tol = o->tol > 0 ? o->tol : 1e-10;
+  const int maxit = o->maxit > 0 ? o->maxit : 200000;
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+  int blk = o->check_every > 0 ? o->check_every : 48;
+  blk = std::max(6, (blk + 5) / 6 * 6);
+  int total = 0, outer = 0, reason = 0;
+  double rel = -1.0;
+  const dim3 grid(C.nbf + C.nbe), tb(NT);
+  while (st == CR_OK) {
+    const bool last = outer >= max_outer || total >= maxit;
+    CState* h = &w->hst[1];
+    h->tol2 = tol * tol;
+    h->maxit = last ? 0 : maxit - total;
+    const size_t off = offsetof(CState, tol2);
+    st = check_hip(hipMemcpyAsync((char*)w->st + off, (char*)h + off, sizeof(CState) - off, hipMemcpyHostToDevice,
+                                  s->stream), "coupled params");
+    if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "coupled params");
+    if (st != CR_OK) break;
+    hipLaunchKernelGGL(k_mr_init<D>, grid, tb, 0, s->stream, C, M, w->b, w->dinv, w->x, w->R[0], w->R[1], w->W[0],
+                       w->W[1], w->pa, w->st);
+    ++outer;
+    // iterate in blocks, polling the device flag after each
+    int issued = 0;
+    const int max_blocks = (last ? 0 : maxit - total) / blk + 2;
+    CState ks{};
+    for (;;) {
+      enqueue_mr<D>(s, w, issued * blk, blk);
+      ++issued;
+      hipMemcpyAsync(&w->hst[0], w->st, sizeof(CState), hipMemcpyDeviceToHost, s->stream);
+      st = check_hip(hipStreamSynchronize(s->stream), "coupled poll");
+      if (st != CR_OK) break;
+      ks = w->hst[0];
+      if (ks.done || issued >= max_blocks) break;
+    }
+    if (st != CR_OK) break;
+    total += ks.iters;
+    rel = ks.bnorm2 > 0 ? std::sqrt(ks.tres2 / ks.bnorm2) : std::sqrt(ks.tres2);
+    if (ks.done == 2) {
+      reason = 1;
+      break;
+    }
+    if (ks.done == 4 || ks.done == 5) {
+      reason = ks.done;
+      break;
+    }
+    if (last) {
+      reason = 3;
+      break;
+    }
+  }
+  if (st == CR_OK) {
+    hipLaunchKernelGGL(k_mr_scatter<D>, dim3((unsigned)((s->nf + s->ne + 255) / 256)), dim3(256), 0, s->stream, s->nf,
+                       s->ne, w->x, s->fcanon, s->ecaller, U, P);
+    st = check_hip(hipStreamSynchronize(s->stream), "coupled scatter");
+  }
+  if (st != CR_OK) return st;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->iters = total;
+    info->outer_iters = outer;
+    info->rel_residual = rel;
+    info->t_solve_ms = ms;
+    info->reason = reason;
+  }
+  if (reason == 1) return CR_OK;
+  if (reason == 4 || reason == 5) {
+    set_error("coupled MINRES breakdown after %d iterations", total);
+    return reason == 4 ? CR_E_BREAKDOWN : CR_E_NONFINITE;
+  }
+  set_error("coupled MINRES: relative residual %.3e after %d iterations", rel, total);
+  return CR_E_NOCONV;
+}
+
+}  // namespace
+
+cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
+  return s->d == 2 ? coupled_solve<2>(s, o, info, U, P) : coupled_solve<3>(s, o, info, U, P);
+}
+
+void free_coupled(cr_system* s) {
+  free_cws((CWs*)s->cws);
+  s->cws = nullptr;
+}
+
 }  // namespace crh

@@ -96,8 +96,9 @@ struct cr_system {
   bool eliminated = false;
   bool has_solution = false;
 
-  // Krylov workspace (allocated on first solve)
+  // Krylov workspace (allocated on first solve), coupled-baseline workspace
   void* kws = nullptr;
+  void* cws = nullptr;
 };
 
 namespace crh {
@@ -117,5 +118,6 @@ void free_krylov(cr_system* s);
 
 // coupled baseline (coupled.hip)
 cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P);
+void free_coupled(cr_system* s);
 
 }  // namespace crh

@@ -10,152 +10,68 @@
 // Jacobi preconditioning is folded into the matrix: the stored G is
 // Ds G Ds with Ds = |diag G|^{-1/2}, and the solver works on y = W / Ds.
 //
-// Iterative refinement: the residual of the current FP64 y is computed with
-// the FP64 plane; an inner Krylov solve (FP32 or FP64 plane) returns a
-// correction; y += correction.  The FP64-only mode is the same loop with an
-// FP64 inner solve.
+// Precision: the FP64 solution y is resident.  The Krylov recurrences run in
+// FP32 (or FP64) on a correction x; whenever the recursive residual has fallen
+// by a set factor since the last update, x is added to y and the residual is
+// recomputed from y with the FP64 matrix plane ("reliable update" / residual
+// replacement).  The search directions are kept across the update, so the
+// Krylov space is not lost as it would be by restarting an inner solve.  The
+// solve stops on the FP64 residual ||S - G W|| <= tol ||S||.
 //
-// Kernel structure: every kernel processes a contiguous range of face rows per
+// CG (symmetric positive definite G) runs two kernels per iteration: the
+// product w = G r fused with the direction updates p = r + beta p and
+// q = w + beta q (q = G p without a second product) and the partial p.q; then
+// alpha = rho / p.q, x += alpha p, r -= alpha q and the partial r.r.
+// BiCGStab (non-symmetric G) uses three kernels per iteration.  A Krylov
+// breakdown caused by rounding (p.q <= 0, rho = 0, ...) triggers a restart
+// from the FP64 residual with a fresh direction.
+//
+// Reductions: every kernel processes a contiguous range of face rows per
 // workgroup (remapped so that each XCD gets a contiguous eighth of the rows)
-// and writes one partial sum per workgroup for each dot product it produces.
-// The consuming kernel reduces the (few hundred) partials redundantly in every
-// workgroup in a fixed order, so all workgroups see bit-identical scalars and
-// no atomics or intra-kernel grid synchronisation are needed.  Per-iteration
-// scalars alternate between two slots by iteration parity, which is a kernel
-// argument, so an even number of iterations can be captured once in a hipGraph
-// and replayed.  A device flag stops all later kernels once the iteration has
-// converged or failed, so replays past convergence are no-ops.
+// and writes one partial sum per workgroup and dot product; the consuming
+// kernel reduces the partials redundantly in every workgroup in a fixed order,
+// so all workgroups see bit-identical scalars, without atomics.  Per-iteration
+// scalars alternate between two slots by iteration parity, a kernel argument,
+// so an even number of iterations is captured once in a hipGraph and replayed.
+// A device flag stops all later kernels once the iteration has converged,
+// needs a residual replacement or failed, so replays past it are no-ops.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
 #include "internal.h"
+#include "rowkern.h"
 
 namespace crh {
 namespace {
 
-constexpr int MAXBLK = 1024;   // upper bound on workgroups of the row kernels
-constexpr int NPART = 4;       // doubles per partial record
+constexpr int NFIELD = 4;  // fields of a partial record
+
+// done codes
+enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5 };
 
 struct KState {
-  double rho[2];     // per parity: r.r (CG) or rhat.r (BiCGStab) at the start of the iteration
-  double alpha[2];
-  double omega[2];
-  int it[2];         // iterations completed when the iteration of this parity started (+1)
-  int done;          // 0 running, 1 inner converged, 2 outer converged, 3 limit, 4 breakdown, 5 non-finite
-  int iters;         // iterations completed in the current inner solve
-  double rr0, tres2, snorm2, thr2, last_rr;
-  // parameters written by the host before each inner solve
-  double inner_tol2, outer_tol2;
+  // per iteration parity
+  double gam[2];   // CG: r.r; BiCGStab: rho = rhat.r
+  double alp[2];
+  double omg[2];   // BiCGStab omega
+  int it[2];       // (index + 1) of the iteration run with this parity
+  // control: each written by one kernel, read by later kernels
+  int done;
+  int iters;       // index of the iteration at which the last stop happened
+  int it_rep;      // iteration index of the last residual replacement
+  int it_first;    // iteration index that starts a new direction (beta = 0)
+  int nrun;        // iterations executed since the start of the solve
+  int pad0;
+  double rr_rep, thr_rep, tgt, tres2, snorm2, last_rr;
+  // parameters written by the host
+  double rep_tol2, tol2;
   int maxit;
-  int pad;
+  int pad1;
 };
-
-struct Part {
-  int64_t nf;
-  int nblk;
-  int64_t chunk;
-};
-
-__device__ __forceinline__ int logical_block(int nblk) {
-  const int per = nblk >> 3;
-  const int b = blockIdx.x;
-  return (b & 7) * per + (b >> 3);
-}
-
-template <typename T, int D>
-struct Vec {
-  T v[D];
-};
-
-template <typename T, int D>
-__device__ __forceinline__ Vec<T, D> ldv(const T* __restrict__ p, int64_t f) {
-  Vec<T, D> r;
-  if constexpr (D == 2) {
-    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
-    V2 t = *reinterpret_cast<const V2*>(p + f * 2);
-    r.v[0] = t.x;
-    r.v[1] = t.y;
-  } else {
-#pragma unroll
-    for (int i = 0; i < D; ++i) r.v[i] = p[f * D + i];
-  }
-  return r;
-}
-
-template <typename T, int D>
-__device__ __forceinline__ void stv(T* __restrict__ p, int64_t f, const Vec<T, D>& r) {
-  if constexpr (D == 2) {
-    using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
-    V2 t;
-    t.x = r.v[0];
-    t.y = r.v[1];
-    *reinterpret_cast<V2*>(p + f * 2) = t;
-  } else {
-#pragma unroll
-    for (int i = 0; i < D; ++i) p[f * D + i] = r.v[i];
-  }
-}
-
-// one face row of the block-ELL product; In(c) returns the input vector at face c
-template <int D, typename T, class In>
-__device__ __forceinline__ Vec<T, D> spmv_row(const T* __restrict__ G, const int32_t* __restrict__ cols, int64_t nf,
-                                              int64_t f, const In& in) {
-  constexpr int DD = D * D, NS = 2 * D + 1;
-  int c[NS];
-  c[0] = (int)f;
-#pragma unroll
-  for (int s = 1; s < NS; ++s) c[s] = cols[(int64_t)(s - 1) * nf + f];
-  Vec<T, D> xv[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) xv[s] = in(c[s]);
-  Vec<T, D> w;
-#pragma unroll
-  for (int i = 0; i < D; ++i) w.v[i] = T(0);
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int j = 0; j < D; ++j) w.v[i] += G[(int64_t)(s * DD + i * D + j) * nf + f] * xv[s].v[j];
-  return w;
-}
-
-template <int M>
-__device__ __forceinline__ void block_sum(double (&v)[M]) {
-  __shared__ double sh[M][NT / 64];
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    double x = v[m];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[m] = x;
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m) v[m] = (sh[m][0] + sh[m][1]) + (sh[m][2] + sh[m][3]);
-  __syncthreads();
-}
-
-// every workgroup reduces the same partial records in the same order
-template <int M>
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk, int first, double (&v)[M]) {
-#pragma unroll
-  for (int m = 0; m < M; ++m) v[m] = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += NT)
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] += part[(int64_t)i * NPART + first + m];
-  block_sum<M>(v);
-}
-
-__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 template <typename T, int D>
 struct Plain {
@@ -164,103 +80,169 @@ struct Plain {
 };
 
 // ---------------------------------------------------------------------------
-// refinement residual: r_s = bs - G64 y (FP64), inner right-hand side r = (T) r_s,
-// inner iterate x = 0; partials: [0] r.r, [1] ||dsq r_s||^2 = ||S - G W||^2,
-// [2] ||S||^2, [3] r.r (BiCGStab also takes rhat = r).
+// Residual (replacement) kernel: r_s = bs - G64 y in FP64; r = (T) r_s; x = 0.
+// Partial fields: 0 = r.r (CG) or rhat.r (BiCGStab), 1 = ||dsq r_s||^2 =
+// ||S - G W||^2, 2 = ||S||^2, 3 = r.r.
+// mode 0 (start): iteration counters reset, new direction, rhat = r.
+// mode 1 (replacement): the iteration continues with its directions.
+// mode 2 (restart after a finite-precision breakdown, or any stop at an odd
+//   iteration): new direction from the next even iteration index, rhat = r.
 // ---------------------------------------------------------------------------
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_ir_residual(Part P, const double* __restrict__ G64,
                                                     const int32_t* __restrict__ cols, const double* __restrict__ y,
                                                     const double* __restrict__ bs, const double* __restrict__ dsq,
                                                     T* __restrict__ r, T* __restrict__ x, T* __restrict__ rhat,
-                                                    double* __restrict__ pa, KState* __restrict__ st) {
+                                                    double* __restrict__ part, KState* __restrict__ st, int mode,
+                                                    int bicg) {
+  // a replacement after a stop at an odd iteration (iteration limit) cannot
+  // keep its directions at parity 0: it becomes a restart
+  if (mode == 1 && (st->iters & 1)) mode = 2;
+  const bool init = mode != 1;
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
     Vec<double, D> w = spmv_row<D, double>(G64, cols, P.nf, f, Plain<double, D>{y});
-    Vec<T, D> rt, zero;
+    Vec<T, D> rt, zero, rh;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const double b = bs[f * D + i], sq = dsq[f * D + i];
       const double rs = b - w.v[i];
       rt.v[i] = (T)rs;
       zero.v[i] = T(0);
-      acc[0] += (double)rt.v[i] * (double)rt.v[i];
       acc[1] += (sq * rs) * (sq * rs);
       acc[2] += (sq * b) * (sq * b);
+      acc[3] += (double)rt.v[i] * (double)rt.v[i];
     }
     stv<T, D>(r, f, rt);
     stv<T, D>(x, f, zero);
-    if (rhat) stv<T, D>(rhat, f, rt);
+    if (bicg) {
+      if (init)
+        rh = rt;
+      else
+        rh = ldv<T, D>(rhat, f);
+      if (init) stv<T, D>(rhat, f, rt);
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[0] += (double)rh.v[i] * (double)rt.v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[0] += (double)rt.v[i] * (double)rt.v[i];
+    }
   }
-  block_sum<3>(acc);
+  block_sum<4>(acc);
   if (threadIdx.x == 0) {
-    pa[(int64_t)lb * NPART + 0] = acc[0];
-    pa[(int64_t)lb * NPART + 1] = acc[1];
-    pa[(int64_t)lb * NPART + 2] = acc[2];
-    pa[(int64_t)lb * NPART + 3] = acc[0];
+    part[lb] = acc[0];
+    part[(int64_t)1 * P.nblk + lb] = acc[1];
+    part[(int64_t)2 * P.nblk + lb] = acc[2];
+    part[(int64_t)3 * P.nblk + lb] = acc[3];
   }
   if (lead()) {
-    st->it[1] = 0;
-    st->rho[1] = 1.0;
-    st->alpha[1] = 1.0;
-    st->omega[1] = 1.0;
-    st->iters = 0;
-    st->done = 0;
+    if (mode == 0) {
+      st->it[1] = 0;
+      st->iters = 0;
+      st->it_first = 0;
+      st->nrun = 0;
+    } else if (mode == 2) {
+      const int e = (st->iters + 1) & ~1;
+      st->it[1] = e;
+      st->iters = e;
+      st->it_first = e;
+    }
+    st->it_rep = st->iters;
+    st->done = RUNNING;
   }
 }
 
-// common stopping logic of the first kernel of an iteration; rr = ||r||^2 of the
-// inner system, v1/v2 = true residual / ||S||^2 partial sums (first iteration only)
-__device__ __forceinline__ int stop_check(KState* st, int it, double rr, double v1, double v2, bool first,
-                                          double& thr2) {
-  if (first) {
-    const double ratio = v1 > 0.0 ? v2 * rr / v1 : 0.0;
-    thr2 = fmax(st->inner_tol2 * rr, 0.01 * st->outer_tol2 * ratio);
+// Stopping logic shared by the first kernel of each iteration.  rr is the
+// squared norm of the recursive residual; at the first iteration after a
+// replacement (fresh) the true residual and ||S|| come from partial fields 1, 2.
+// Replacements are requested only at even iterations so that the next
+// iteration starts a graph replay at parity 0.
+struct Decision {
+  int done;
+  double rr_rep, thr_rep, tgt;
+};
+
+__device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh, double rr, double tres2,
+                                           double snorm2) {
+  Decision d;
+  d.done = RUNNING;
+  if (fresh) {
+    d.rr_rep = rr;
+    d.thr_rep = st->rep_tol2 * rr;
+    d.tgt = tres2 > 0.0 ? 0.01 * st->tol2 * snorm2 * rr / tres2 : 0.0;
+    if (tres2 <= st->tol2 * snorm2) {
+      d.done = CONVERGED;
+      return d;
+    }
   } else {
-    thr2 = st->thr2;
+    d.rr_rep = st->rr_rep;
+    d.thr_rep = st->thr_rep;
+    d.tgt = st->tgt;
   }
-  if (first && v1 <= st->outer_tol2 * v2) return 2;
-  if (!isfinite(rr)) return 5;
-  if (it >= st->maxit) return 3;
-  if (rr <= thr2) return 1;
-  return 0;
+  if (!isfinite(rr))
+    d.done = NONFINITE;
+  else if (it >= st->maxit)
+    d.done = LIMIT;
+  else if (!fresh && !(it & 1) && (rr <= d.thr_rep || rr <= d.tgt))
+    d.done = REPLACE;
+  return d;
+}
+
+__device__ __forceinline__ void record_decision(KState* st, const Decision& d, bool fresh, int it, double rr,
+                                                double tres2, double snorm2) {
+  if (fresh) {
+    st->rr_rep = d.rr_rep;
+    st->thr_rep = d.thr_rep;
+    st->tgt = d.tgt;
+    st->tres2 = tres2;
+    st->snorm2 = snorm2;
+  }
+  st->iters = it;
+  st->last_rr = rr;
+  if (d.done) st->done = d.done;
 }
 
 // ---------------------------------------------------------------------------
-// CG on the scaled SPD system.  K1: w = G r, p = r + beta p, q = w + beta q
-// (q = G p without a second product), partial p.q.  K2: alpha = rho / p.q,
-// x += alpha p, r -= alpha q, partial r.r.
+// CG iteration, kernel 1 (parity par): partial fields of Pa: 0 = r.r (and
+// 1, 2 after a replacement); w = G r, p = r + beta p, q = w + beta q; Pb field
+// 0 = p.q.
 // ---------------------------------------------------------------------------
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                                 const T* __restrict__ r, T* __restrict__ p, T* __restrict__ q,
-                                                const double* __restrict__ pa, double* __restrict__ pb,
+                                                const double* __restrict__ Pa, double* __restrict__ Pb,
                                                 KState* __restrict__ st, int par) {
   if (st->done) return;
-  double v[3];
-  reduce_partials<3>(pa, P.nblk, 0, v);
   const int it = st->it[par ^ 1];
-  const bool first = it == 0;
-  const double rr = v[0];
-  double thr2;
-  const int done = stop_check(st, it, rr, v[1], v[2], first, thr2);
-  if (lead()) {
-    if (first) {
-      st->rr0 = rr;
-      st->tres2 = v[1];
-      st->snorm2 = v[2];
-      st->thr2 = thr2;
-    }
-    st->rho[par] = rr;
-    st->it[par] = it + 1;
-    st->iters = it;
-    st->last_rr = rr;
-    if (done) st->done = done;
+  const bool first = it == st->it_first;
+  const bool fresh = it == st->it_rep;
+  double rr, tres2 = 0.0, snorm2 = 0.0;
+  if (fresh) {
+    const int fl[3] = {0, 1, 2};
+    double v[3];
+    reduce_fields<3>(Pa, P.nblk, fl, v);
+    rr = v[0];
+    tres2 = v[1];
+    snorm2 = v[2];
+  } else {
+    const int fl[1] = {0};
+    double v[1];
+    reduce_fields<1>(Pa, P.nblk, fl, v);
+    rr = v[0];
   }
-  if (done) return;
-  const T beta = first ? T(0) : (T)(rr / st->rho[par ^ 1]);
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2);
+  if (lead()) {
+    record_decision(st, dec, fresh, it, rr, tres2, snorm2);
+    if (!dec.done) {
+      st->gam[par] = rr;
+      st->it[par] = it + 1;
+      st->nrun += 1;
+    }
+  }
+  if (dec.done) return;
+  const T beta = first ? T(0) : (T)(rr / st->gam[par ^ 1]);
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[1] = {0.0};
@@ -285,23 +267,25 @@ __global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G,
     for (int i = 0; i < D; ++i) acc[0] += (double)pi.v[i] * (double)qi.v[i];
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) pb[(int64_t)lb * NPART] = acc[0];
+  if (threadIdx.x == 0) Pb[lb] = acc[0];
 }
 
+// CG iteration, kernel 2: alpha = rho / p.q, x += alpha p, r -= alpha q; Pa field 0 = r.r
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_cg_update(Part P, T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p, const T* __restrict__ q,
-                                                  const double* __restrict__ pb, double* __restrict__ pa,
+                                                  const double* __restrict__ Pb, double* __restrict__ Pa,
                                                   KState* __restrict__ st, int par) {
   if (st->done) return;
+  const int fl[1] = {0};
   double v[1];
-  reduce_partials<1>(pb, P.nblk, 0, v);
+  reduce_fields<1>(Pb, P.nblk, fl, v);
   const double pq = v[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (lead()) st->done = isfinite(pq) ? 4 : 5;
+    if (lead()) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
     return;
   }
-  const double alpha = st->rho[par] / pq;
+  const double alpha = st->gam[par] / pq;
   const T ta = (T)alpha;
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
@@ -318,20 +302,20 @@ __global__ void __launch_bounds__(NT) k_cg_update(Part P, T* __restrict__ x, T* 
     stv<T, D>(r, f, ri);
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) pa[(int64_t)lb * NPART] = acc[0];
-  if (lead()) st->alpha[par] = alpha;
+  if (threadIdx.x == 0) Pa[lb] = acc[0];
+  if (lead()) st->alp[par] = alpha;
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab on the scaled system (non-symmetric G).  Three kernels per
+// BiCGStab on the scaled system (non-symmetric G), three kernels per
 // iteration; the direction p and the intermediate s are formed on the fly from
 // double-buffered vectors inside the products that consume them:
-//   B1: p_new = r + beta (p_old - omega v_old) gathered on the fly, v = G p_new,
-//       partial rhat.v
-//   B2: alpha = rho / rhat.v, s = r - alpha v gathered on the fly, t = G s,
-//       partials t.s, t.t
+//   B1: p_new = r + beta (p_old - omega v_old), v = G p_new, partial rhat.v
+//   B2: alpha = rho / rhat.v, s = r - alpha v, t = G s, partials t.s, t.t
 //   B3: omega = t.s / t.t, x += alpha p + omega s, r = s - omega t,
 //       partials rhat.r, r.r
+// Partial arrays: B1 reads Pa (fields 0 rhat.r, 3 r.r, 1/2 after a
+// replacement) and writes Pb; B2 reads Pb, writes Pc; B3 reads Pc, writes Pa.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 struct PNew {
@@ -368,33 +352,44 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
                                                const T* __restrict__ r, const T* __restrict__ rhat,
                                                const T* __restrict__ p_old, const T* __restrict__ v_old,
                                                T* __restrict__ p_new, T* __restrict__ v_new,
-                                               const double* __restrict__ pa, double* __restrict__ pb,
+                                               const double* __restrict__ Pa, double* __restrict__ Pb,
                                                KState* __restrict__ st, int par) {
   if (st->done) return;
-  double v[4];
-  reduce_partials<4>(pa, P.nblk, 0, v);
   const int it = st->it[par ^ 1];
-  const bool first = it == 0;
-  const double rho = v[0], rr = v[3];
-  double thr2;
-  int done = stop_check(st, it, rr, v[1], v[2], first, thr2);
-  if (!done && (!(rho != 0.0) || !isfinite(rho))) done = isfinite(rho) ? 4 : 5;
+  const bool first = it == st->it_first;
+  const bool fresh = it == st->it_rep;
+  double rho, rr, tres2 = 0.0, snorm2 = 0.0;
+  if (fresh) {
+    const int fl[4] = {0, 3, 1, 2};
+    double v[4];
+    reduce_fields<4>(Pa, P.nblk, fl, v);
+    rho = v[0];
+    rr = v[1];
+    tres2 = v[2];
+    snorm2 = v[3];
+  } else {
+    const int fl[2] = {0, 3};
+    double v[2];
+    reduce_fields<2>(Pa, P.nblk, fl, v);
+    rho = v[0];
+    rr = v[1];
+  }
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2);
+  int done = dec.done;
+  if (!done && (!(rho != 0.0) || !isfinite(rho))) done = isfinite(rho) ? BREAKDOWN : NONFINITE;
+  const double beta = first ? 0.0 : (rho / st->gam[par ^ 1]) * (st->alp[par ^ 1] / st->omg[par ^ 1]);
   if (lead()) {
-    if (first) {
-      st->rr0 = rr;
-      st->tres2 = v[1];
-      st->snorm2 = v[2];
-      st->thr2 = thr2;
+    record_decision(st, dec, fresh, it, rr, tres2, snorm2);
+    if (done) {
+      st->done = done;
+    } else {
+      st->gam[par] = rho;
+      st->it[par] = it + 1;
+      st->nrun += 1;
     }
-    st->rho[par] = rho;
-    st->it[par] = it + 1;
-    st->iters = it;
-    st->last_rr = rr;
-    if (done) st->done = done;
   }
   if (done) return;
-  const double beta = first ? 0.0 : (rho / st->rho[par ^ 1]) * (st->alpha[par ^ 1] / st->omega[par ^ 1]);
-  const PNew<T, D> in{r, p_old, v_old, (T)beta, (T)st->omega[par ^ 1], first};
+  const PNew<T, D> in{r, p_old, v_old, (T)beta, (T)st->omg[par ^ 1], first};
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[1] = {0.0};
@@ -407,23 +402,24 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
     for (int i = 0; i < D; ++i) acc[0] += (double)rh.v[i] * (double)w.v[i];
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) pb[(int64_t)lb * NPART] = acc[0];
+  if (threadIdx.x == 0) Pb[lb] = acc[0];
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_bicg_2(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                                const T* __restrict__ r, const T* __restrict__ v_new,
-                                               T* __restrict__ s, T* __restrict__ t, const double* __restrict__ pb,
-                                               double* __restrict__ pc, KState* __restrict__ st, int par) {
+                                               T* __restrict__ s, T* __restrict__ t, const double* __restrict__ Pb,
+                                               double* __restrict__ Pc, KState* __restrict__ st, int par) {
   if (st->done) return;
+  const int fl[1] = {0};
   double v[1];
-  reduce_partials<1>(pb, P.nblk, 0, v);
+  reduce_fields<1>(Pb, P.nblk, fl, v);
   const double rv = v[0];
   if (!(rv != 0.0) || !isfinite(rv)) {
-    if (lead()) st->done = isfinite(rv) ? 4 : 5;
+    if (lead()) st->done = isfinite(rv) ? BREAKDOWN : NONFINITE;
     return;
   }
-  const double alpha = st->rho[par] / rv;
+  const double alpha = st->gam[par] / rv;
   const SNew<T, D> in{r, v_new, (T)alpha};
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
@@ -441,28 +437,29 @@ __global__ void __launch_bounds__(NT) k_bicg_2(Part P, const T* __restrict__ G, 
   }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
-    pc[(int64_t)lb * NPART] = acc[0];
-    pc[(int64_t)lb * NPART + 1] = acc[1];
+    Pc[lb] = acc[0];
+    Pc[(int64_t)P.nblk + lb] = acc[1];
   }
-  if (lead()) st->alpha[par] = alpha;
+  if (lead()) st->alp[par] = alpha;
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __restrict__ r,
                                                const T* __restrict__ rhat, const T* __restrict__ p_new,
                                                const T* __restrict__ s, const T* __restrict__ t,
-                                               const double* __restrict__ pc, double* __restrict__ pa,
+                                               const double* __restrict__ Pc, double* __restrict__ Pa,
                                                KState* __restrict__ st, int par) {
   if (st->done) return;
+  const int fl[2] = {0, 1};
   double v[2];
-  reduce_partials<2>(pc, P.nblk, 0, v);
+  reduce_fields<2>(Pc, P.nblk, fl, v);
   const double ts = v[0], tt = v[1];
   if (!(tt > 0.0) || !isfinite(tt) || !isfinite(ts)) {
-    if (lead()) st->done = (isfinite(tt) && isfinite(ts)) ? 4 : 5;
+    if (lead()) st->done = (isfinite(tt) && isfinite(ts)) ? BREAKDOWN : NONFINITE;
     return;
   }
   const double omega = ts / tt;
-  const T ta = (T)st->alpha[par], to = (T)omega;
+  const T ta = (T)st->alp[par], to = (T)omega;
   const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[2] = {0.0, 0.0};
@@ -481,13 +478,13 @@ __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __r
   }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
-    pa[(int64_t)lb * NPART] = acc[0];
-    pa[(int64_t)lb * NPART + 3] = acc[1];
+    Pa[lb] = acc[0];
+    Pa[(int64_t)3 * P.nblk + lb] = acc[1];
   }
-  if (lead()) st->omega[par] = omega;
+  if (lead()) st->omg[par] = omega;
 }
 
-// y += x (FP64 accumulation of the inner correction)
+// y += x (FP64 accumulation of the correction)
 template <typename T>
 __global__ void __launch_bounds__(NT) k_ir_update(int64_t n, double* __restrict__ y, const T* __restrict__ x) {
   int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -497,31 +494,41 @@ __global__ void __launch_bounds__(NT) k_ir_update(int64_t n, double* __restrict_
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// vector slots of the workspace
+enum { V_X, V_P, V_R0, V_R1, V_W0, V_W1, V_S0, V_S1, V_RHAT, V_T, NVEC };
+
 struct KWs {
-  int64_t nf = 0;
-  int d = 0;
   Part part{};
-  void* vec[9] = {};          // x, r, rhat, p0, p1, v0, v1, s, t (each nf*d doubles)
-  double* pa = nullptr;
-  double* pb = nullptr;
-  double* pc = nullptr;
+  void* vec[NVEC] = {};  // each nf*d doubles
+  double* part3[3] = {};   // partial arrays, NFIELD x nblk each
   KState* st = nullptr;
-  KState* hst = nullptr;      // pinned [3]
+  KState* hst = nullptr;   // pinned [3]
   hipEvent_t ev[2] = {};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t exec[2][2] = {};  // [precision][method]
   int exec_m[2][2] = {};
   // scratch for kernel timing
-  void* tvec[3] = {};
+  void* tvec[NVEC] = {};
   double* tpart[2] = {};
   KState* tst = nullptr;
 };
 
+int max_blocks_cfg() {
+  static int v = [] {
+    const char* e = std::getenv("CRH_MAXBLK");
+    int m = e ? std::atoi(e) : MAXBLK / 2;
+    m = std::max(8, std::min(4096, m));
+    return m / 8 * 8;
+  }();
+  return v;
+}
+
 Part make_part(int64_t nf) {
   Part P;
   P.nf = nf;
-  const int64_t tiles = (nf + (int64_t)NT * MAXBLK - 1) / ((int64_t)NT * MAXBLK);
+  const int64_t mb = max_blocks_cfg();
+  const int64_t tiles = (nf + (int64_t)NT * mb - 1) / ((int64_t)NT * mb);
   P.chunk = std::max<int64_t>(1, tiles) * NT;
   int64_t nb = (nf + P.chunk - 1) / P.chunk;
   nb = (nb + 7) / 8 * 8;
@@ -533,32 +540,27 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
   w = (KWs*)s->kws;
   if (w) return CR_OK;
   w = new KWs();
-  w->nf = s->nf;
-  w->d = s->d;
+  s->kws = w;
   w->part = make_part(s->nf);
   const size_t vb = sizeof(double) * (size_t)s->nf * s->d;
   for (auto& v : w->vec) {
     v = dev_alloc(s, vb);
     if (!v) return CR_E_NOMEM;
   }
-  const size_t pbytes = sizeof(double) * (size_t)w->part.nblk * NPART;
-  w->pa = (double*)dev_alloc(s, pbytes);
-  w->pb = (double*)dev_alloc(s, pbytes);
-  w->pc = (double*)dev_alloc(s, pbytes);
-  w->st = (KState*)dev_alloc(s, sizeof(KState));
-  if (!w->pa || !w->pb || !w->pc || !w->st) return CR_E_NOMEM;
-  cr_status st = check_hip(hipHostMalloc((void**)&w->hst, 3 * sizeof(KState), hipHostMallocDefault), "pinned state");
-  if (st != CR_OK) return st;
-  for (auto& e : w->ev) {
-    st = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-    if (st != CR_OK) return st;
+  const size_t pbytes = sizeof(double) * (size_t)w->part.nblk * NFIELD;
+  for (auto& p : w->part3) {
+    p = (double*)dev_alloc(s, pbytes);
+    if (!p) return CR_E_NOMEM;
   }
-  st = check_hip(hipEventCreate(&w->t0), "event");
+  w->st = (KState*)dev_alloc(s, sizeof(KState));
+  if (!w->st) return CR_E_NOMEM;
+  cr_status st = check_hip(hipHostMalloc((void**)&w->hst, 3 * sizeof(KState), hipHostMallocDefault), "pinned state");
+  for (auto& e : w->ev)
+    if (st == CR_OK) st = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  if (st == CR_OK) st = check_hip(hipEventCreate(&w->t0), "event");
   if (st == CR_OK) st = check_hip(hipEventCreate(&w->t1), "event");
   if (st == CR_OK) st = check_hip(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking), "capture stream");
-  if (st != CR_OK) return st;
-  s->kws = w;
-  return CR_OK;
+  return st;
 }
 
 struct Launch {
@@ -573,78 +575,76 @@ void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
   KWs* w = L.w;
   const Part P = w->part;
   const T* G = std::is_same<T, float>::value ? (const T*)L.s->G32 : (const T*)L.s->G64;
-  T* x = (T*)w->vec[0];
-  T* r = (T*)w->vec[1];
-  T* rh = (T*)w->vec[2];
-  T* pv[2] = {(T*)w->vec[3], (T*)w->vec[4]};
-  T* vv[2] = {(T*)w->vec[5], (T*)w->vec[6]};
-  T* s = (T*)w->vec[7];
-  T* t = (T*)w->vec[8];
+  auto V = [&](int i) { return (T*)w->vec[i]; };
   const dim3 grid(P.nblk), blk(NT);
   for (int k = 0; k < npairs; ++k)
     for (int par = 0; par < 2; ++par) {
       if (L.method == CR_PCG) {
-        hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, stream, P, G, L.s->cols, r, pv[0], vv[0], w->pa, w->pb,
-                           w->st, par);
-        hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, P, x, r, pv[0], vv[0], w->pb, w->pa, w->st,
-                           par);
+        hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), V(V_P), V(V_W0),
+                           w->part3[0], w->part3[1], w->st, par);
+        hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, P, V(V_X), V(V_R0), V(V_P), V(V_W0),
+                           w->part3[1], w->part3[0], w->st, par);
       } else {
-        hipLaunchKernelGGL((k_bicg_1<D, T>), grid, blk, 0, stream, P, G, L.s->cols, r, rh, pv[par ^ 1], vv[par ^ 1],
-                           pv[par], vv[par], w->pa, w->pb, w->st, par);
-        hipLaunchKernelGGL((k_bicg_2<D, T>), grid, blk, 0, stream, P, G, L.s->cols, r, vv[par], s, t, w->pb, w->pc,
-                           w->st, par);
-        hipLaunchKernelGGL((k_bicg_3<D, T>), grid, blk, 0, stream, P, x, r, rh, pv[par], s, t, w->pc, w->pa, w->st,
-                           par);
+        T* pv[2] = {V(V_R1), V(V_W1)};  // p buffers
+        T* vv[2] = {V(V_S0), V(V_S1)};  // v buffers
+        hipLaunchKernelGGL((k_bicg_1<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), V(V_RHAT), pv[par ^ 1],
+                           vv[par ^ 1], pv[par], vv[par], w->part3[0], w->part3[1], w->st, par);
+        hipLaunchKernelGGL((k_bicg_2<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), vv[par], V(V_W0),
+                           V(V_T), w->part3[1], w->part3[2], w->st, par);
+        hipLaunchKernelGGL((k_bicg_3<D, T>), grid, blk, 0, stream, P, V(V_X), V(V_R0), V(V_RHAT), pv[par], V(V_W0),
+                           V(V_T), w->part3[2], w->part3[0], w->st, par);
       }
     }
 }
 
-void enqueue_iters_any(const Launch& L, hipStream_t stream, int npairs) {
-  const bool f32 = L.prec == CR_FP32_IR;
-  if (L.s->d == 2) {
+template <class F>
+void dispatch(const cr_system* s, int prec, F&& f) {
+  const bool f32 = prec == CR_FP32_IR;
+  if (s->d == 2) {
     if (f32)
-      enqueue_iters<2, float>(L, stream, npairs);
+      f(std::integral_constant<int, 2>(), float());
     else
-      enqueue_iters<2, double>(L, stream, npairs);
+      f(std::integral_constant<int, 2>(), double());
   } else {
     if (f32)
-      enqueue_iters<3, float>(L, stream, npairs);
+      f(std::integral_constant<int, 3>(), float());
     else
-      enqueue_iters<3, double>(L, stream, npairs);
+      f(std::integral_constant<int, 3>(), double());
   }
 }
 
-void enqueue_residual(const Launch& L) {
+void enqueue_iters_any(const Launch& L, hipStream_t stream, int npairs) {
+  dispatch(L.s, L.prec, [&](auto dc, auto tc) {
+    constexpr int D = decltype(dc)::value;
+    using T = decltype(tc);
+    enqueue_iters<D, T>(L, stream, npairs);
+  });
+}
+
+// residual (replacement) kernel
+void enqueue_residual(const Launch& L, int mode) {
   KWs* w = L.w;
+  cr_system* s = L.s;
   const Part P = w->part;
   const dim3 grid(P.nblk), blk(NT);
-  void* rh = L.method == CR_BICGSTAB ? w->vec[2] : nullptr;
-  const bool f32 = L.prec == CR_FP32_IR;
-  cr_system* s = L.s;
-#define CRH_RES(D, T)                                                                                        \
-  hipLaunchKernelGGL((k_ir_residual<D, T>), grid, blk, 0, s->stream, P, s->G64, s->cols, s->y, s->bs, s->dsq, \
-                     (T*)w->vec[1], (T*)w->vec[0], (T*)rh, w->pa, w->st)
-  if (s->d == 2) {
-    if (f32)
-      CRH_RES(2, float);
-    else
-      CRH_RES(2, double);
-  } else {
-    if (f32)
-      CRH_RES(3, float);
-    else
-      CRH_RES(3, double);
-  }
-#undef CRH_RES
+  const bool bicg = L.method == CR_BICGSTAB;
+  dispatch(s, L.prec, [&](auto dc, auto tc) {
+    constexpr int D = decltype(dc)::value;
+    using T = decltype(tc);
+    hipLaunchKernelGGL((k_ir_residual<D, T>), grid, blk, 0, s->stream, P, s->G64, s->cols, s->y, s->bs, s->dsq,
+                       (T*)w->vec[V_R0], (T*)w->vec[V_X], (T*)w->vec[V_RHAT], w->part3[0], w->st, mode,
+                       bicg ? 1 : 0);
+  });
 }
 
 void enqueue_update(const Launch& L) {
   const int64_t n = L.s->nf * L.s->d;
   const unsigned g = (unsigned)((n + NT - 1) / NT);
   if (L.prec == CR_FP32_IR)
-    hipLaunchKernelGGL(k_ir_update<float>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y, (const float*)L.w->vec[0]);
+    hipLaunchKernelGGL(k_ir_update<float>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y, (const float*)L.w->vec[V_X]);
   else
-    hipLaunchKernelGGL(k_ir_update<double>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y, (const double*)L.w->vec[0]);
+    hipLaunchKernelGGL(k_ir_update<double>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y,
+                       (const double*)L.w->vec[V_X]);
 }
 
 cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
@@ -678,8 +678,9 @@ cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   return CR_OK;
 }
 
-// Runs inner iterations until the device flag is set; returns the final state.
-cr_status run_inner(const Launch& L, int npairs, bool graph, int maxit, KState& out) {
+// Replays iteration blocks until the device flag is set (at most max_blocks
+// blocks, two in flight); returns the final state.
+cr_status run_inner(const Launch& L, int npairs, bool graph, int max_blocks, KState& out) {
   KWs* w = L.w;
   cr_system* s = L.s;
   hipGraphExec_t exec = nullptr;
@@ -687,31 +688,23 @@ cr_status run_inner(const Launch& L, int npairs, bool graph, int maxit, KState& 
     cr_status st = get_graph(L, npairs, exec);
     if (st != CR_OK) return st;
   }
-  auto launch = [&]() {
+  auto launch = [&](int slot) {
     if (graph)
       hipGraphLaunch(exec, s->stream);
     else
       enqueue_iters_any(L, s->stream, npairs);
+    hipMemcpyAsync(&w->hst[slot], w->st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
+    hipEventRecord(w->ev[slot], s->stream);
   };
-  const int per = 2 * npairs;
-  const int max_blocks = maxit / per + 3;
   int issued = 0, slot = 0;
-  for (int k = 0; k < 2 && issued < max_blocks; ++k) {
-    launch();
-    hipMemcpyAsync(&w->hst[issued & 1], w->st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
-    hipEventRecord(w->ev[issued & 1], s->stream);
-    ++issued;
-  }
+  for (int k = 0; k < 2 && issued < max_blocks; ++k) launch(issued++ & 1);
   cr_status st = check_hip(hipGetLastError(), "inner launch");
   if (st != CR_OK) return st;
   for (;;) {
     st = check_hip(hipEventSynchronize(w->ev[slot]), "inner poll");
     if (st != CR_OK) return st;
-    const int done = w->hst[slot].done;
-    if (done || issued >= max_blocks) break;
-    launch();
-    hipMemcpyAsync(&w->hst[slot], w->st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
-    hipEventRecord(w->ev[slot], s->stream);
+    if (w->hst[slot].done || issued >= max_blocks) break;
+    launch(slot);
     ++issued;
     slot ^= 1;
   }
@@ -719,22 +712,19 @@ cr_status run_inner(const Launch& L, int npairs, bool graph, int maxit, KState& 
   st = check_hip(hipStreamSynchronize(s->stream), "inner sync");
   if (st != CR_OK) return st;
   out = w->hst[2];
-  if (!out.done) out.done = 3;
   return CR_OK;
 }
 
-cr_status write_params(cr_system* s, KWs* w, double inner_tol, double tol, int maxit) {
+cr_status write_params(cr_system* s, KWs* w, double rep_tol, double tol, int maxit) {
   KState* h = &w->hst[2];
-  // only the parameter fields are sent; the kernels own the others
-  h->inner_tol2 = inner_tol * inner_tol;
-  h->outer_tol2 = tol * tol;
+  h->rep_tol2 = rep_tol * rep_tol;
+  h->tol2 = tol * tol;
   h->maxit = maxit;
-  const size_t off = offsetof(KState, inner_tol2);
+  const size_t off = offsetof(KState, rep_tol2);
   cr_status st = check_hip(hipMemcpyAsync((char*)w->st + off, (char*)h + off, sizeof(KState) - off,
                                           hipMemcpyHostToDevice, s->stream),
                            "solver parameters");
   if (st != CR_OK) return st;
-  // the staging slot is reused by the next poll: wait for the copy
   return check_hip(hipStreamSynchronize(s->stream), "solver parameters");
 }
 
@@ -748,132 +738,161 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   Launch L{s, w, o->precision, o->method};
   const int blk = o->check_every > 0 ? o->check_every : 32;
   const int npairs = std::max(1, (blk + 1) / 2);
+  const int per = 2 * npairs;
   const bool graph = o->use_graph != 0;
   const double tol = o->tol > 0 ? o->tol : 1e-10;
-  double inner_tol = o->inner_tol;
-  if (!(inner_tol > 0)) inner_tol = o->precision == CR_FP32_IR ? 1e-4 : 0.0;
-  const int maxit = o->maxit > 0 ? o->maxit : 100000;
-  const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
+  // reduction of the recursive residual between residual replacements
+  double rep = o->inner_tol;
+  if (!(rep > 0)) rep = o->precision == CR_FP32_IR ? 0.1 : 0.0;
+  const int maxit = o->maxit > 0 ? o->maxit : 1000000;
+  const int max_rep = o->max_outer > 0 ? o->max_outer : 400;
   if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, s->stream), "zero W");
     if (st != CR_OK) return st;
   }
-  int total = 0, outer = 0, reason = 0;
-  double rel = -1.0;
+  st = write_params(s, w, rep, tol, maxit);
+  if (st != CR_OK) return st;
+  enqueue_residual(L, 0);
+  int reps = 1, restarts = 0, reason = 0, iters = 0, fp32_iters = 0;
+  double rel = -1.0, prev_true = -1.0;
+  bool final_eval = false, fell_back = false;
+  // FP32 intervals between replacements are capped; a stalled FP32 interval
+  // or a replacement that does not halve the true residual switches the
+  // remaining iterations to FP64 (FP32 Krylov cannot make progress once the
+  // condition number times the FP32 unit roundoff approaches one).
+  const int fp32_cap_blocks = std::max(8, 6000 / per);
   for (;;) {
-    const bool last = outer >= max_outer || total >= maxit;
-    st = write_params(s, w, inner_tol, tol, last ? 0 : maxit - total);
-    if (st != CR_OK) return st;
-    enqueue_residual(L);
-    ++outer;
     KState ks;
-    st = run_inner(L, npairs, graph && !last, last ? 0 : maxit - total, ks);
+    const bool f32 = L.prec == CR_FP32_IR;
+    const int cap = final_eval ? 1 : (f32 ? fp32_cap_blocks : maxit / per + 3);
+    st = run_inner(L, npairs, graph && !final_eval, cap, ks);
     if (st != CR_OK) return st;
-    total += ks.iters;
+    if (f32) fp32_iters = ks.nrun;
+    iters = ks.nrun;
     rel = ks.snorm2 > 0 ? std::sqrt(ks.tres2 / ks.snorm2) : std::sqrt(ks.tres2);
-    if (ks.done == 2) {
+    if (ks.done == CONVERGED) {
       reason = 1;
       break;
     }
-    if (ks.done == 4 || ks.done == 5) {
+    if (ks.done == NONFINITE && !f32) {
       reason = ks.done;
       break;
     }
-    if (last) {
+    if (ks.done == BREAKDOWN && !f32 && (final_eval || restarts >= 8)) {
+      reason = ks.done;
+      break;
+    }
+    if (final_eval) {
       reason = 3;
       break;
     }
-    enqueue_update(L);
+    bool stall = false;
+    if (f32) {
+      stall = ks.done == RUNNING || ks.done == NONFINITE || (ks.done == BREAKDOWN && restarts >= 2) ||
+              (prev_true > 0.0 && ks.tres2 > 0.25 * prev_true);
+      prev_true = ks.tres2;
+    }
+    // fold the correction into y (unless it holds non-finite values) and
+    // recompute the residual in FP64
+    if (ks.done != NONFINITE) enqueue_update(L);
+    if (stall) {
+      L.prec = CR_FP64;
+      fell_back = true;
+      enqueue_residual(L, 2);
+    } else if (ks.done == BREAKDOWN) {
+      enqueue_residual(L, 2);
+      ++restarts;
+    } else {
+      enqueue_residual(L, 1);
+    }
+    ++reps;
+    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN) || reps > max_rep || iters >= maxit) final_eval = true;
   }
   st = check_hip(hipStreamSynchronize(s->stream), "solve sync");
   if (st != CR_OK) return st;
   s->has_solution = true;
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   if (info) {
-    info->iters = total;
-    info->outer_iters = outer;
+    info->iters = iters;
+    info->outer_iters = reps;
     info->rel_residual = rel;
     info->t_solve_ms = ms;
     info->reason = reason;
+    info->fp32_iters = o->precision == CR_FP32_IR ? fp32_iters : 0;
+    info->fp64_fallback = fell_back ? 1 : 0;
   }
   if (reason == 1) return CR_OK;
-  if (reason == 4) {
-    set_error("Krylov breakdown after %d iterations", total);
+  if (reason == BREAKDOWN) {
+    set_error("Krylov breakdown after %d iterations", iters);
     return CR_E_BREAKDOWN;
   }
-  if (reason == 5) {
-    set_error("non-finite Krylov scalar after %d iterations", total);
+  if (reason == NONFINITE) {
+    set_error("non-finite Krylov scalar after %d iterations", iters);
     return CR_E_NONFINITE;
   }
-  set_error("no convergence: relative residual %.3e after %d iterations, %d refinement passes", rel, total, outer);
+  set_error("no convergence: relative residual %.3e after %d iterations, %d residual evaluations", rel, iters, reps);
   return CR_E_NOCONV;
 }
 
+// Times the dominant kernel (SpMV fused with the CG direction updates) on
+// scratch vectors; its input r is never written, so every launch does
+// identical work.
 cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, double* bytes) {
   KWs* w = nullptr;
   cr_status st = ensure_ws(s, w);
   if (st != CR_OK) return st;
   const int d = s->d;
   const size_t vb = sizeof(double) * (size_t)s->nf * d;
+  const Part P = w->part;
   if (!w->tvec[0]) {
     for (auto& v : w->tvec) {
       v = dev_alloc(s, vb);
       if (!v) return CR_E_NOMEM;
     }
     for (auto& p : w->tpart) {
-      p = (double*)dev_alloc(s, sizeof(double) * (size_t)w->part.nblk * NPART);
+      p = (double*)dev_alloc(s, sizeof(double) * (size_t)P.nblk * NFIELD);
       if (!p) return CR_E_NOMEM;
     }
     w->tst = (KState*)dev_alloc(s, sizeof(KState));
     if (!w->tst) return CR_E_NOMEM;
   }
-  // scratch state: one record with r.r = 1, iteration 1 in flight, no stopping
-  std::vector<double> hp((size_t)w->part.nblk * NPART, 0.0);
+  // scratch state: iteration 1 in flight (not first, not fresh), r.r = 1,
+  // previous r.r = 1 (beta = 1), no stopping
+  std::vector<double> hp((size_t)P.nblk * NFIELD, 0.0);
   hp[0] = 1.0;
   KState ks{};
-  ks.rho[1] = 1.0;
+  ks.gam[1] = 1.0;
   ks.it[1] = 1;
-  ks.thr2 = 0.0;
-  ks.inner_tol2 = 0.0;
-  ks.outer_tol2 = 0.0;
+  ks.it_rep = -1;
+  ks.it_first = -1;
   ks.maxit = 1 << 30;
   st = check_hip(hipMemcpyAsync(w->tpart[0], hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, s->stream),
                  "timing partials");
   if (st == CR_OK) st = check_hip(hipMemcpyAsync(w->tst, &ks, sizeof ks, hipMemcpyHostToDevice, s->stream), "timing state");
-  if (st == CR_OK) st = check_hip(hipMemsetAsync(w->tvec[1], 0, vb, s->stream), "timing p");
-  if (st == CR_OK) st = check_hip(hipMemsetAsync(w->tvec[2], 0, vb, s->stream), "timing q");
+  for (int i = 0; i < NVEC && st == CR_OK; ++i)
+    st = check_hip(hipMemsetAsync(w->tvec[i], 0, vb, s->stream), "timing vectors");
   if (st != CR_OK) return st;
-  const Part P = w->part;
-  const bool f32 = precision == CR_FP32_IR;
-  // input vector: the scaled right-hand side, rounded to the working type
+  // input r: the scaled right-hand side rounded to the working type
   std::vector<double> hb((size_t)s->nf * d);
   st = check_hip(hipMemcpyAsync(hb.data(), s->bs, vb, hipMemcpyDeviceToHost, s->stream), "timing input");
   if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "timing input");
   if (st != CR_OK) return st;
-  if (f32) {
-    std::vector<float> hf(hb.begin(), hb.end());
-    st = check_hip(hipMemcpy(w->tvec[0], hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice), "timing input");
-  } else {
-    st = check_hip(hipMemcpy(w->tvec[0], hb.data(), vb, hipMemcpyHostToDevice), "timing input");
-  }
+  const bool f32 = precision == CR_FP32_IR;
+  std::vector<float> hf(hb.begin(), hb.end());
+  st = check_hip(hipMemcpy(w->tvec[V_R0], f32 ? (const void*)hf.data() : (const void*)hb.data(),
+                           f32 ? hf.size() * sizeof(float) : vb, hipMemcpyHostToDevice),
+                 "timing input");
   if (st != CR_OK) return st;
   const dim3 grid(P.nblk), blk(NT);
   auto launch = [&]() {
-#define CRH_T(D, T)                                                                                               \
-  hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, s->stream, P, (const T*)(f32 ? (const void*)s->G32 : (const void*)s->G64), \
-                     s->cols, (const T*)w->tvec[0], (T*)w->tvec[1], (T*)w->tvec[2], w->tpart[0], w->tpart[1], w->tst, 0)
-    if (d == 2) {
-      if (f32)
-        CRH_T(2, float);
-      else
-        CRH_T(2, double);
-    } else {
-      if (f32)
-        CRH_T(3, float);
-      else
-        CRH_T(3, double);
-    }
-#undef CRH_T
+    dispatch(s, precision, [&](auto dc, auto tc) {
+      constexpr int D = decltype(dc)::value;
+      using T = decltype(tc);
+      const T* G = std::is_same<T, float>::value ? (const T*)s->G32 : (const T*)s->G64;
+      auto V = [&](int i) { return (T*)w->tvec[i]; };
+      hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, s->stream, P, G, s->cols, V(V_R0), V(V_P), V(V_W0),
+                         w->tpart[0], w->tpart[1], w->tst, 0);
+    });
   };
   launch();  // warm-up
   hipEventRecord(w->t0, s->stream);
@@ -885,10 +904,12 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
   hipEventElapsedTime(&ms, w->t0, w->t1);
   if (avg_ms) *avg_ms = (double)ms / reps;
   if (bytes) {
+    // values and column indices of G, the gathered input r read once, p and q
+    // read and written
     const double vsz = f32 ? 4.0 : 8.0;
     const double nf = (double)s->nf;
     const double mat = nf * (2 * d + 1) * d * d * vsz + nf * 2 * d * 4.0;
-    const double vec = nf * d * vsz * (1 /* r gathered once */ + 2 /* p r/w */ + 2 /* q r/w */);
+    const double vec = nf * d * vsz * (1 + 2 + 2);
     *bytes = mat + vec;
   }
   return CR_OK;

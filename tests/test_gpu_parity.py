@@ -181,3 +181,19 @@ def test_error_paths(gpu):
     out = s.solve("pcg", "fp64", tol=1e-12, maxit=3, raise_on_error=False)
     assert out["status"] == -5 and out["iters"] <= 3
     s.close()
+
+
+@pytest.mark.parametrize("name", ["square16", "jitter12", "cube3"])
+def test_coupled_minres_baseline_parity(gpu, name):
+    """The GPU coupled-system baseline reaches the oracle's coupled solution."""
+    case = make_case(name)
+    print(f"case {name} coupled", flush=True)
+    P = oracle_problem(case)
+    U_o, P_o = cr.solve_coupled(P)
+    s = gpu_system(gpu, case)
+    U, Pk, info = s.coupled_solve(tol=1e-13, maxit=500000)
+    torch.cuda.synchronize()
+    assert info["rel_residual"] <= 1e-13
+    assert relerr(U.cpu().numpy(), U_o) <= 1e-10
+    assert relerr(Pk.cpu().numpy(), P_o) <= 1e-10
+    s.close()
