@@ -83,12 +83,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp32_ir", "fp64"],
+                    help="Krylov arithmetic of the timed path (the other one is reported beside it)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--n", type=int, default=512, help="cells per side (512 = the benchmark workload)")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--coupled-maxit", type=int, default=60000)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only build the system and time the dominant kernel (for counter collection)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run 20 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -103,6 +108,15 @@ def main():
 
     crh.load()
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        a = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 20}), flush=True)
+        return
     mu, nu, n = 1000.0, 1.0, args.n
     t0 = time.perf_counter()
     w = wl.square(n, mu=mu, nu=nu, jitter=0.2, seed=0, quad=3)
@@ -113,6 +127,13 @@ def main():
     log(f"topology + upload: {t_topo:.2f} s, {s.n_int_faces} interior faces")
     fbar = torch.from_numpy(w["fbar"]).cuda()
     stream = torch.cuda.current_stream()
+    if args.kernel_only:
+        s.eliminate(fbar)
+        ms_k, bytes_k = s.time_spmv(args.precision, reps=200)
+        print(json.dumps({"kernel": "k_cg_spmv", "precision": args.precision, "avg_us": ms_k * 1e3,
+                          "algorithmic_bytes": bytes_k, "GBps": bytes_k / (ms_k * 1e-3) / 1e9}), flush=True)
+        s.close()
+        return
 
     def step(record):
         e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
@@ -158,11 +179,12 @@ def main():
     U, P, J = s.recover(jump=True)
     torch.cuda.synchronize()
 
-    # FP64 Krylov variant of the same solve
+    # the other Krylov precision on the same solve
     other = "fp64" if args.precision == "fp32_ir" else "fp32_ir"
     s.eliminate(fbar)
     info64 = s.solve("pcg", other, tol=args.tol)
-    log(f"{other} solve: {info64['t_solve_ms']:.1f} ms, {info64['iters']} iterations")
+    log(f"{other} solve: {info64['t_solve_ms']:.1f} ms, {info64['iters']} iterations "
+        f"({info64['fp32_iters']} in FP32, fallback to FP64: {info64['fp64_fallback']})")
 
     coupled = None
     if not args.no_coupled:
@@ -192,7 +214,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32_ir" else "f64",
+        "dtype": "f32+f64" if args.precision == "fp32_ir" else "f64",
         "data": "synthetic",
         "config": {"workload": f"2D transient Stokes, unit square {n}x{n} cells x2 triangles, jitter 0.2h (seed 0), "
                                f"nu=1, mu=1/dt=1000, manufactured RHS; hybridised SPD system, Jacobi-scaled CG "
@@ -210,6 +232,7 @@ def main():
         "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "topology_host_s": round(t_topo, 3),
         f"{other}_time_to_tol_ms": round(info64["t_solve_ms"], 3), f"{other}_iters": info64["iters"],
+        f"{other}_fp32_iters": info64["fp32_iters"], f"{other}_fp64_fallback": info64["fp64_fallback"],
         "coupled_gpu": coupled,
         "speedup_vs_coupled": (round(coupled["time_ms"] / float(np.median([r['solve_ms'] for r in recs])), 2)
                                if coupled else None),
