@@ -210,6 +210,40 @@ cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_i
 cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t reps, double* avg_ms,
                        double* bytes_per_launch);
 
+/* Step a7 (serving): batched CG solves of many resident transient-Stokes
+ * systems.  Each kernel launch of a batch covers the rows of every active
+ * system (a block-diagonal batch, one grid); each system keeps its own partial
+ * sums, scalars and stop flag, so its iterates are bitwise those of cr_solve
+ * with the same options.  Systems join with cr_batch_add (their right-hand
+ * side set by cr_eliminate / cr_update_rhs) and leave when finished; their
+ * FP64 residual replacements are serviced between iteration blocks.  All
+ * systems of a batch live on the batch's stream and have the same dimension.
+ * Not thread-safe.  The batch owns only its own small tables (hipMalloc). */
+typedef struct cr_batch cr_batch;
+
+/* max_systems: capacity (1..4096). */
+cr_status cr_batch_create(void* hip_stream, int32_t max_systems, cr_batch** out);
+
+/* Start solving sys's current S (method CR_PCG; opts as for cr_solve, use_graph
+ * and check_every ignored).  Asynchronous.  Errors: CR_E_INVAL (system not
+ * eliminated, other stream or dimension, not transient Stokes, already in the
+ * batch), CR_E_NOMEM (batch full). */
+cr_status cr_batch_add(cr_batch* b, cr_system* sys, const cr_solve_opts* opts);
+
+/* Run n_iters iterations (rounded up to even) of every active system in shared
+ * launches, then service stops (replacement, restart, FP64 fallback, finish).
+ * *n_finished = systems that finished in this call.  Synchronises. */
+cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished);
+
+/* Pop one finished system (FIFO): *sys = NULL if none.  info and status (the
+ * cr_status cr_solve would have returned) may be NULL.  W is resident in sys. */
+cr_status cr_batch_pop(cr_batch* b, cr_system** sys, cr_solve_info* info, int32_t* status);
+
+/* Number of active and of finished-but-not-popped systems. */
+cr_status cr_batch_count(const cr_batch* b, int32_t* n_active, int32_t* n_finished);
+
+void cr_batch_destroy(cr_batch* b);
+
 void cr_destroy(cr_system* sys);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -27,7 +27,8 @@ CR_FP64, CR_FP32_IR = 0, 1
 # every function declared in include/crhyb.h
 EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recover", "cr_query_sizes",
            "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
-           "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version"]
+           "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
+           "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy"]
 
 
 class CRError(RuntimeError):
@@ -95,6 +96,12 @@ def load(path: str = LIB_PATH):
         "cr_coupled_solve": (I32, [P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P, P]),
         "cr_time_spmv": (I32, [P, I32, I32, C.POINTER(D), C.POINTER(D)]),
         "cr_destroy": (None, [P]),
+        "cr_batch_create": (I32, [P, I32, C.POINTER(P)]),
+        "cr_batch_add": (I32, [P, P, C.POINTER(SolveOpts)]),
+        "cr_batch_advance": (I32, [P, I32, C.POINTER(I32)]),
+        "cr_batch_pop": (I32, [P, C.POINTER(P), C.POINTER(SolveInfo), C.POINTER(I32)]),
+        "cr_batch_count": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
+        "cr_batch_destroy": (None, [P]),
         "cr_last_error": (C.c_char_p, []),
         "cr_version": (C.c_char_p, []),
     }
@@ -182,6 +189,74 @@ class TorchAllocator:
         return sum(self.live.values())
 
 
+def solve_opts(method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
+               check_every=0, graph=True, warm_start=False):
+    return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB}[method],
+                     {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
+                     int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)))
+
+
+def info_dict(st, info):
+    return dict(status=st, iters=info.iters, outer_iters=info.outer_iters, rel_residual=info.rel_residual,
+                t_solve_ms=info.t_solve_ms, reason=info.reason, fp32_iters=info.fp32_iters,
+                fp64_fallback=bool(info.fp64_fallback))
+
+
+class Batch:
+    """Batched CG solves of resident systems (cr_batch_*): shared launches over
+    all active systems, each system's iterates identical to a single solve."""
+
+    def __init__(self, max_systems=256, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = C.c_void_p()
+        _check(self.lib.cr_batch_create(C.c_void_p(handle), int(max_systems), C.byref(h)))
+        self.h = h
+        self._members = {}
+
+    def add(self, system, **opts):
+        o = solve_opts(**opts)
+        _check(self.lib.cr_batch_add(self.h, system.h, C.byref(o)))
+        self._members[system.h.value] = system
+
+    def advance(self, n_iters=32):
+        n = C.c_int32()
+        _check(self.lib.cr_batch_advance(self.h, int(n_iters), C.byref(n)))
+        return n.value
+
+    def pop(self):
+        """Next finished (system, info dict) or None."""
+        p = C.c_void_p()
+        info = SolveInfo()
+        st = C.c_int32()
+        _check(self.lib.cr_batch_pop(self.h, C.byref(p), C.byref(info), C.byref(st)))
+        if not p.value:
+            return None
+        return self._members.pop(p.value), info_dict(st.value, info)
+
+    def count(self):
+        a, f = C.c_int32(), C.c_int32()
+        _check(self.lib.cr_batch_count(self.h, C.byref(a), C.byref(f)))
+        return a.value, f.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class System:
     """One hybridised Crouzeix-Raviart system resident on the current GPU."""
 
@@ -235,14 +310,10 @@ class System:
 
     def solve(self, method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
               check_every=0, graph=True, warm_start=False, raise_on_error=True):
-        o = SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB}[method],
-                      {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
-                      int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)))
+        o = solve_opts(method, precision, tol, inner_tol, maxit, max_outer, check_every, graph, warm_start)
         info = SolveInfo()
         st = self.lib.cr_solve(self.h, C.byref(o), C.byref(info))
-        out = dict(status=st, iters=info.iters, outer_iters=info.outer_iters, rel_residual=info.rel_residual,
-                   t_solve_ms=info.t_solve_ms, reason=info.reason, fp32_iters=info.fp32_iters,
-                   fp64_fallback=bool(info.fp64_fallback))
+        out = info_dict(st, info)
         if raise_on_error:
             _check(st)
         return out

@@ -35,12 +35,17 @@
 // so an even number of iterations is captured once in a hipGraph and replayed.
 // A device flag stops all later kernels once the iteration has converged,
 // needs a residual replacement or failed, so replays past it are no-ops.
+//
+// The same CG kernel bodies run in batched form (one grid over the row ranges
+// of many systems, per-system partials, scalars and flags) for serving.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <type_traits>
+#include <vector>
 
 #include "internal.h"
 #include "rowkern.h"
@@ -51,7 +56,7 @@ namespace {
 constexpr int NFIELD = 4;  // fields of a partial record
 
 // done codes
-enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5 };
+enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5, STALL = 6 };
 
 struct KState {
   // per iteration parity
@@ -70,7 +75,7 @@ struct KState {
   // parameters written by the host
   double rep_tol2, tol2;
   int maxit;
-  int pad1;
+  int interval_cap;  // > 0: at most this many iterations between replacements (FP32)
 };
 
 template <typename T, int D>
@@ -78,6 +83,29 @@ struct Plain {
   const T* __restrict__ x;
   __device__ Vec<T, D> operator()(int64_t c) const { return ldv<T, D>(x, c); }
 };
+
+// Everything one CG solve of one system touches; passed by value to the
+// single-system kernels and read from a device table by the batched ones.
+struct CgSys {
+  Part P;
+  int boff;                  // first block of this system in a batched grid
+  int pad;
+  const void* G;             // matrix plane of the iteration precision
+  const int32_t* cols;
+  const double* G64;         // FP64 plane (residual)
+  double* y;                 // resident FP64 solution (scaled)
+  const double* bs;
+  const double* dsq;
+  void* x;
+  void* r;
+  void* p;
+  void* q;
+  double* Pa;                // partials: fields 0 r.r, 1 true residual^2, 2 ||S||^2
+  double* Pb;                // partials: field 0 p.q
+  KState* st;
+};
+
+__device__ __forceinline__ int logical_of(int b, int nblk) { return (b & 7) * (nblk >> 3) + (b >> 3); }
 
 // ---------------------------------------------------------------------------
 // Residual (replacement) kernel: r_s = bs - G64 y in FP64; r = (T) r_s; x = 0.
@@ -89,25 +117,23 @@ struct Plain {
 //   iteration): new direction from the next even iteration index, rhat = r.
 // ---------------------------------------------------------------------------
 template <int D, typename T>
-__global__ void __launch_bounds__(NT) k_ir_residual(Part P, const double* __restrict__ G64,
-                                                    const int32_t* __restrict__ cols, const double* __restrict__ y,
-                                                    const double* __restrict__ bs, const double* __restrict__ dsq,
-                                                    T* __restrict__ r, T* __restrict__ x, T* __restrict__ rhat,
-                                                    double* __restrict__ part, KState* __restrict__ st, int mode,
-                                                    int bicg) {
+__device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __restrict__ rhat, int mode, int bicg) {
+  const Part P = S.P;
+  KState* st = S.st;
   // a replacement after a stop at an odd iteration (iteration limit) cannot
   // keep its directions at parity 0: it becomes a restart
   if (mode == 1 && (st->iters & 1)) mode = 2;
   const bool init = mode != 1;
-  const int lb = logical_block(P.nblk);
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  T* __restrict__ r = (T*)S.r;
+  T* __restrict__ x = (T*)S.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
-    Vec<double, D> w = spmv_row<D, double>(G64, cols, P.nf, f, Plain<double, D>{y});
+    Vec<double, D> w = spmv_row<D, double>(S.G64, S.cols, P.nf, f, Plain<double, D>{S.y});
     Vec<T, D> rt, zero, rh;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const double b = bs[f * D + i], sq = dsq[f * D + i];
+      const double b = S.bs[f * D + i], sq = S.dsq[f * D + i];
       const double rs = b - w.v[i];
       rt.v[i] = (T)rs;
       zero.v[i] = T(0);
@@ -132,12 +158,12 @@ __global__ void __launch_bounds__(NT) k_ir_residual(Part P, const double* __rest
   }
   block_sum<4>(acc);
   if (threadIdx.x == 0) {
-    part[lb] = acc[0];
-    part[(int64_t)1 * P.nblk + lb] = acc[1];
-    part[(int64_t)2 * P.nblk + lb] = acc[2];
-    part[(int64_t)3 * P.nblk + lb] = acc[3];
+    S.Pa[lb] = acc[0];
+    S.Pa[(int64_t)1 * P.nblk + lb] = acc[1];
+    S.Pa[(int64_t)2 * P.nblk + lb] = acc[2];
+    S.Pa[(int64_t)3 * P.nblk + lb] = acc[3];
   }
-  if (lead()) {
+  if (threadIdx.x == 0 && lb == 0) {
     if (mode == 0) {
       st->it[1] = 0;
       st->iters = 0;
@@ -154,18 +180,23 @@ __global__ void __launch_bounds__(NT) k_ir_residual(Part P, const double* __rest
   }
 }
 
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ir_residual(CgSys S, T* __restrict__ rhat, int mode, int bicg) {
+  ir_residual_body<D, T>(S, logical_block(S.P.nblk), rhat, mode, bicg);
+}
+
 // Stopping logic shared by the first kernel of each iteration.  rr is the
 // squared norm of the recursive residual; at the first iteration after a
 // replacement (fresh) the true residual and ||S|| come from partial fields 1, 2.
 // Replacements are requested only at even iterations so that the next
-// iteration starts a graph replay at parity 0.
+// iteration starts at parity 0.
 struct Decision {
   int done;
   double rr_rep, thr_rep, tgt;
 };
 
 __device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh, double rr, double tres2,
-                                           double snorm2) {
+                                           double snorm2, bool f32) {
   Decision d;
   d.done = RUNNING;
   if (fresh) {
@@ -187,6 +218,8 @@ __device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh,
     d.done = LIMIT;
   else if (!fresh && !(it & 1) && (rr <= d.thr_rep || rr <= d.tgt))
     d.done = REPLACE;
+  else if (f32 && !fresh && !(it & 1) && st->interval_cap > 0 && it - st->it_rep >= st->interval_cap)
+    d.done = STALL;
   return d;
 }
 
@@ -205,16 +238,15 @@ __device__ __forceinline__ void record_decision(KState* st, const Decision& d, b
 }
 
 // ---------------------------------------------------------------------------
-// CG iteration, kernel 1 (parity par): partial fields of Pa: 0 = r.r (and
-// 1, 2 after a replacement); w = G r, p = r + beta p, q = w + beta q; Pb field
-// 0 = p.q.
+// CG iteration, kernel 1 (parity par): Pa fields 0 = r.r (and 1, 2 after a
+// replacement); w = G r, p = r + beta p, q = w + beta q (q = G p without a
+// second product); Pb field 0 = p.q.
 // ---------------------------------------------------------------------------
 template <int D, typename T>
-__global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
-                                                const T* __restrict__ r, T* __restrict__ p, T* __restrict__ q,
-                                                const double* __restrict__ Pa, double* __restrict__ Pb,
-                                                KState* __restrict__ st, int par) {
+__device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
+  KState* st = S.st;
   if (st->done) return;
+  const Part P = S.P;
   const int it = st->it[par ^ 1];
   const bool first = it == st->it_first;
   const bool fresh = it == st->it_rep;
@@ -222,18 +254,18 @@ __global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G,
   if (fresh) {
     const int fl[3] = {0, 1, 2};
     double v[3];
-    reduce_fields<3>(Pa, P.nblk, fl, v);
+    reduce_fields<3>(S.Pa, P.nblk, fl, v);
     rr = v[0];
     tres2 = v[1];
     snorm2 = v[2];
   } else {
     const int fl[1] = {0};
     double v[1];
-    reduce_fields<1>(Pa, P.nblk, fl, v);
+    reduce_fields<1>(S.Pa, P.nblk, fl, v);
     rr = v[0];
   }
-  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2);
-  if (lead()) {
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, std::is_same<T, float>::value);
+  if (threadIdx.x == 0 && lb == 0) {
     record_decision(st, dec, fresh, it, rr, tres2, snorm2);
     if (!dec.done) {
       st->gam[par] = rr;
@@ -243,11 +275,14 @@ __global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G,
   }
   if (dec.done) return;
   const T beta = first ? T(0) : (T)(rr / st->gam[par ^ 1]);
-  const int lb = logical_block(P.nblk);
+  const T* __restrict__ G = (const T*)S.G;
+  const T* __restrict__ r = (const T*)S.r;
+  T* __restrict__ p = (T*)S.p;
+  T* __restrict__ q = (T*)S.q;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[1] = {0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
-    Vec<T, D> w = spmv_row<D, T>(G, cols, P.nf, f, Plain<T, D>{r});
+    Vec<T, D> w = spmv_row<D, T>(G, S.cols, P.nf, f, Plain<T, D>{r});
     Vec<T, D> ri = ldv<T, D>(r, f), pi, qi;
     if (first) {
       pi = ri;
@@ -267,27 +302,29 @@ __global__ void __launch_bounds__(NT) k_cg_spmv(Part P, const T* __restrict__ G,
     for (int i = 0; i < D; ++i) acc[0] += (double)pi.v[i] * (double)qi.v[i];
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) Pb[lb] = acc[0];
+  if (threadIdx.x == 0) S.Pb[lb] = acc[0];
 }
 
 // CG iteration, kernel 2: alpha = rho / p.q, x += alpha p, r -= alpha q; Pa field 0 = r.r
 template <int D, typename T>
-__global__ void __launch_bounds__(NT) k_cg_update(Part P, T* __restrict__ x, T* __restrict__ r,
-                                                  const T* __restrict__ p, const T* __restrict__ q,
-                                                  const double* __restrict__ Pb, double* __restrict__ Pa,
-                                                  KState* __restrict__ st, int par) {
+__device__ __forceinline__ void cg_update_body(const CgSys& S, int lb, int par) {
+  KState* st = S.st;
   if (st->done) return;
+  const Part P = S.P;
   const int fl[1] = {0};
   double v[1];
-  reduce_fields<1>(Pb, P.nblk, fl, v);
+  reduce_fields<1>(S.Pb, P.nblk, fl, v);
   const double pq = v[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (lead()) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
+    if (threadIdx.x == 0 && lb == 0) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
     return;
   }
   const double alpha = st->gam[par] / pq;
   const T ta = (T)alpha;
-  const int lb = logical_block(P.nblk);
+  T* __restrict__ x = (T*)S.x;
+  T* __restrict__ r = (T*)S.r;
+  const T* __restrict__ p = (const T*)S.p;
+  const T* __restrict__ q = (const T*)S.q;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[1] = {0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
@@ -302,8 +339,49 @@ __global__ void __launch_bounds__(NT) k_cg_update(Part P, T* __restrict__ x, T* 
     stv<T, D>(r, f, ri);
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) Pa[lb] = acc[0];
-  if (lead()) st->alp[par] = alpha;
+  if (threadIdx.x == 0) S.Pa[lb] = acc[0];
+  if (threadIdx.x == 0 && lb == 0) st->alp[par] = alpha;
+}
+
+// y += x over the system's rows (FP64 accumulation of the correction)
+template <int D, typename T>
+__device__ __forceinline__ void ir_update_body(const CgSys& S, int lb) {
+  const Part P = S.P;
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  const T* __restrict__ x = (const T*)S.x;
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT)
+#pragma unroll
+    for (int i = 0; i < D; ++i) S.y[f * D + i] += (double)x[f * D + i];
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_cg_spmv(CgSys S, int par) {
+  cg_spmv_body<D, T>(S, logical_block(S.P.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_cg_update(CgSys S, int par) {
+  cg_update_body<D, T>(S, logical_block(S.P.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ir_update(CgSys S) {
+  ir_update_body<D, T>(S, logical_block(S.P.nblk));
+}
+
+// Batched forms: one grid over the row ranges of all systems of a batch;
+// bmap[block] is the table entry of the system that block belongs to.  Each
+// system's blocks start at a multiple of 8, so the XCD mapping of a system's
+// rows is the same as in its single-system launch.
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_cg_spmv_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap,
+                                                  int par) {
+  const CgSys S = tab[bmap[blockIdx.x]];
+  cg_spmv_body<D, T>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_cg_update_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap,
+                                                    int par) {
+  const CgSys S = tab[bmap[blockIdx.x]];
+  cg_update_body<D, T>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +452,7 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
     rho = v[0];
     rr = v[1];
   }
-  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2);
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, std::is_same<T, float>::value);
   int done = dec.done;
   if (!done && (!(rho != 0.0) || !isfinite(rho))) done = isfinite(rho) ? BREAKDOWN : NONFINITE;
   const double beta = first ? 0.0 : (rho / st->gam[par ^ 1]) * (st->alp[par ^ 1] / st->omg[par ^ 1]);
@@ -484,13 +562,6 @@ __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __r
   if (lead()) st->omg[par] = omega;
 }
 
-// y += x (FP64 accumulation of the correction)
-template <typename T>
-__global__ void __launch_bounds__(NT) k_ir_update(int64_t n, double* __restrict__ y, const T* __restrict__ x) {
-  int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i < n) y[i] += (double)x[i];
-}
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -563,44 +634,29 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
   return st;
 }
 
-struct Launch {
-  cr_system* s;
-  KWs* w;
-  int prec;    // CR_FP64 or CR_FP32_IR
-  int method;  // CR_PCG or CR_BICGSTAB
-};
-
-template <int D, typename T>
-void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
-  KWs* w = L.w;
-  const Part P = w->part;
-  const T* G = std::is_same<T, float>::value ? (const T*)L.s->G32 : (const T*)L.s->G64;
-  auto V = [&](int i) { return (T*)w->vec[i]; };
-  const dim3 grid(P.nblk), blk(NT);
-  for (int k = 0; k < npairs; ++k)
-    for (int par = 0; par < 2; ++par) {
-      if (L.method == CR_PCG) {
-        hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), V(V_P), V(V_W0),
-                           w->part3[0], w->part3[1], w->st, par);
-        hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, P, V(V_X), V(V_R0), V(V_P), V(V_W0),
-                           w->part3[1], w->part3[0], w->st, par);
-      } else {
-        T* pv[2] = {V(V_R1), V(V_W1)};  // p buffers
-        T* vv[2] = {V(V_S0), V(V_S1)};  // v buffers
-        hipLaunchKernelGGL((k_bicg_1<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), V(V_RHAT), pv[par ^ 1],
-                           vv[par ^ 1], pv[par], vv[par], w->part3[0], w->part3[1], w->st, par);
-        hipLaunchKernelGGL((k_bicg_2<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), vv[par], V(V_W0),
-                           V(V_T), w->part3[1], w->part3[2], w->st, par);
-        hipLaunchKernelGGL((k_bicg_3<D, T>), grid, blk, 0, stream, P, V(V_X), V(V_R0), V(V_RHAT), pv[par], V(V_W0),
-                           V(V_T), w->part3[2], w->part3[0], w->st, par);
-      }
-    }
+CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
+  CgSys S{};
+  S.P = w->part;
+  S.G = prec == CR_FP32_IR ? (const void*)s->G32 : (const void*)s->G64;
+  S.cols = s->cols;
+  S.G64 = s->G64;
+  S.y = s->y;
+  S.bs = s->bs;
+  S.dsq = s->dsq;
+  S.x = w->vec[V_X];
+  S.r = w->vec[V_R0];
+  S.p = w->vec[V_P];
+  S.q = w->vec[V_W0];
+  S.Pa = w->part3[0];
+  S.Pb = w->part3[1];
+  S.st = st;
+  return S;
 }
 
 template <class F>
-void dispatch(const cr_system* s, int prec, F&& f) {
+void dispatch(int d, int prec, F&& f) {
   const bool f32 = prec == CR_FP32_IR;
-  if (s->d == 2) {
+  if (d == 2) {
     if (f32)
       f(std::integral_constant<int, 2>(), float());
     else
@@ -613,38 +669,61 @@ void dispatch(const cr_system* s, int prec, F&& f) {
   }
 }
 
-void enqueue_iters_any(const Launch& L, hipStream_t stream, int npairs) {
-  dispatch(L.s, L.prec, [&](auto dc, auto tc) {
-    constexpr int D = decltype(dc)::value;
-    using T = decltype(tc);
-    enqueue_iters<D, T>(L, stream, npairs);
-  });
-}
+struct Launch {
+  cr_system* s;
+  KWs* w;
+  int prec;    // CR_FP64 or CR_FP32_IR
+  int method;  // CR_PCG or CR_BICGSTAB
+  KState* st;  // device state of this solve
+};
 
-// residual (replacement) kernel
-void enqueue_residual(const Launch& L, int mode) {
+void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
   KWs* w = L.w;
-  cr_system* s = L.s;
   const Part P = w->part;
   const dim3 grid(P.nblk), blk(NT);
-  const bool bicg = L.method == CR_BICGSTAB;
-  dispatch(s, L.prec, [&](auto dc, auto tc) {
+  dispatch(L.s->d, L.prec, [&](auto dc, auto tc) {
     constexpr int D = decltype(dc)::value;
     using T = decltype(tc);
-    hipLaunchKernelGGL((k_ir_residual<D, T>), grid, blk, 0, s->stream, P, s->G64, s->cols, s->y, s->bs, s->dsq,
-                       (T*)w->vec[V_R0], (T*)w->vec[V_X], (T*)w->vec[V_RHAT], w->part3[0], w->st, mode,
-                       bicg ? 1 : 0);
+    auto V = [&](int i) { return (T*)w->vec[i]; };
+    const T* G = std::is_same<T, float>::value ? (const T*)L.s->G32 : (const T*)L.s->G64;
+    const CgSys S = make_sys(L.s, w, L.prec, L.st);
+    for (int k = 0; k < npairs; ++k)
+      for (int par = 0; par < 2; ++par) {
+        if (L.method == CR_PCG) {
+          hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, stream, S, par);
+          hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, S, par);
+        } else {
+          T* pv[2] = {V(V_R1), V(V_W1)};  // p buffers
+          T* vv[2] = {V(V_S0), V(V_S1)};  // v buffers
+          hipLaunchKernelGGL((k_bicg_1<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), V(V_RHAT),
+                             pv[par ^ 1], vv[par ^ 1], pv[par], vv[par], w->part3[0], w->part3[1], L.st, par);
+          hipLaunchKernelGGL((k_bicg_2<D, T>), grid, blk, 0, stream, P, G, L.s->cols, V(V_R0), vv[par], V(V_W0),
+                             V(V_T), w->part3[1], w->part3[2], L.st, par);
+          hipLaunchKernelGGL((k_bicg_3<D, T>), grid, blk, 0, stream, P, V(V_X), V(V_R0), V(V_RHAT), pv[par],
+                             V(V_W0), V(V_T), w->part3[2], w->part3[0], L.st, par);
+        }
+      }
   });
 }
 
-void enqueue_update(const Launch& L) {
-  const int64_t n = L.s->nf * L.s->d;
-  const unsigned g = (unsigned)((n + NT - 1) / NT);
-  if (L.prec == CR_FP32_IR)
-    hipLaunchKernelGGL(k_ir_update<float>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y, (const float*)L.w->vec[V_X]);
-  else
-    hipLaunchKernelGGL(k_ir_update<double>, dim3(g), dim3(NT), 0, L.s->stream, n, L.s->y,
-                       (const double*)L.w->vec[V_X]);
+// residual (replacement) kernel for one system
+void enqueue_residual(cr_system* s, KWs* w, int prec, int method, KState* st, int mode, hipStream_t stream) {
+  const Part P = w->part;
+  dispatch(s->d, prec, [&](auto dc, auto tc) {
+    constexpr int D = decltype(dc)::value;
+    using T = decltype(tc);
+    hipLaunchKernelGGL((k_ir_residual<D, T>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st),
+                       (T*)w->vec[V_RHAT], mode, method == CR_BICGSTAB ? 1 : 0);
+  });
+}
+
+void enqueue_update(cr_system* s, KWs* w, int prec, KState* st, hipStream_t stream) {
+  const Part P = w->part;
+  dispatch(s->d, prec, [&](auto dc, auto tc) {
+    constexpr int D = decltype(dc)::value;
+    using T = decltype(tc);
+    hipLaunchKernelGGL((k_ir_update<D, T>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st));
+  });
 }
 
 cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
@@ -661,7 +740,7 @@ cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   hipGraph_t g = nullptr;
   cr_status st = check_hip(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal), "begin capture");
   if (st != CR_OK) return st;
-  enqueue_iters_any(L, w->cap, npairs);
+  enqueue_iters(L, w->cap, npairs);
   hipError_t le = hipGetLastError();
   st = check_hip(hipStreamEndCapture(w->cap, &g), "end capture");
   if (st != CR_OK) return st;
@@ -692,8 +771,8 @@ cr_status run_inner(const Launch& L, int npairs, bool graph, int max_blocks, KSt
     if (graph)
       hipGraphLaunch(exec, s->stream);
     else
-      enqueue_iters_any(L, s->stream, npairs);
-    hipMemcpyAsync(&w->hst[slot], w->st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
+      enqueue_iters(L, s->stream, npairs);
+    hipMemcpyAsync(&w->hst[slot], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
     hipEventRecord(w->ev[slot], s->stream);
   };
   int issued = 0, slot = 0;
@@ -708,25 +787,130 @@ cr_status run_inner(const Launch& L, int npairs, bool graph, int max_blocks, KSt
     ++issued;
     slot ^= 1;
   }
-  hipMemcpyAsync(&w->hst[2], w->st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
+  hipMemcpyAsync(&w->hst[2], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
   st = check_hip(hipStreamSynchronize(s->stream), "inner sync");
   if (st != CR_OK) return st;
   out = w->hst[2];
   return CR_OK;
 }
 
-cr_status write_params(cr_system* s, KWs* w, double rep_tol, double tol, int maxit) {
-  KState* h = &w->hst[2];
-  h->rep_tol2 = rep_tol * rep_tol;
-  h->tol2 = tol * tol;
-  h->maxit = maxit;
+// parameters of one solve, written into its device state
+void fill_params(KState& h, const cr_solve_opts* o, double& tol_out) {
+  const double tol = o->tol > 0 ? o->tol : 1e-10;
+  // reduction of the recursive residual between residual replacements
+  double rep = o->inner_tol;
+  if (!(rep > 0)) rep = o->precision == CR_FP32_IR ? 0.1 : 0.0;
+  h.rep_tol2 = rep * rep;
+  h.tol2 = tol * tol;
+  h.maxit = o->maxit > 0 ? o->maxit : 1000000;
+  // FP32 iterations between replacements are capped (checked in the FP32 kernels only)
+  h.interval_cap = 4000;
+  tol_out = tol;
+}
+
+cr_status write_params(KState* dst, KState* staging, const cr_solve_opts* o, hipStream_t stream) {
+  double tol;
+  fill_params(*staging, o, tol);
   const size_t off = offsetof(KState, rep_tol2);
-  cr_status st = check_hip(hipMemcpyAsync((char*)w->st + off, (char*)h + off, sizeof(KState) - off,
-                                          hipMemcpyHostToDevice, s->stream),
+  cr_status st = check_hip(hipMemcpyAsync((char*)dst + off, (char*)staging + off, sizeof(KState) - off,
+                                          hipMemcpyHostToDevice, stream),
                            "solver parameters");
   if (st != CR_OK) return st;
-  return check_hip(hipStreamSynchronize(s->stream), "solver parameters");
+  return check_hip(hipStreamSynchronize(stream), "solver parameters");
 }
+
+// Host side of one solve: reacts to each stop of the device iteration
+// (replacement, restart, FP32 stall -> FP64, limits) by enqueueing the FP64
+// correction and residual kernels.  Shared by single and batched solves, so a
+// system takes the same decisions at the same iterations in both.
+struct Ctl {
+  int prec = CR_FP64;
+  int method = CR_PCG;
+  int maxit = 0, max_rep = 400;
+  int reps = 1, restarts = 0, reason = 0, iters = 0, fp32_iters = 0;
+  double rel = -1.0, prev_true = -1.0;
+  bool fell_back = false, final_eval = false;
+
+  void init(const cr_solve_opts* o) {
+    prec = o->precision;
+    method = o->method;
+    maxit = o->maxit > 0 ? o->maxit : 1000000;
+    max_rep = o->max_outer > 0 ? o->max_outer : 400;
+  }
+
+  // returns true when the solve is finished (reason set)
+  template <class Upd, class Res>
+  bool step(const KState& ks, Upd&& update, Res&& residual) {
+    const bool f32 = prec == CR_FP32_IR;
+    if (f32) fp32_iters = ks.nrun;
+    iters = ks.nrun;
+    rel = ks.snorm2 > 0 ? std::sqrt(ks.tres2 / ks.snorm2) : std::sqrt(ks.tres2);
+    if (ks.done == CONVERGED) {
+      reason = 1;
+      return true;
+    }
+    if (ks.done == NONFINITE && !f32) {
+      reason = NONFINITE;
+      return true;
+    }
+    if (ks.done == BREAKDOWN && !f32 && (final_eval || restarts >= 8)) {
+      reason = BREAKDOWN;
+      return true;
+    }
+    if (final_eval) {
+      reason = 3;
+      return true;
+    }
+    bool stall = false;
+    if (f32) {
+      stall = ks.done == STALL || ks.done == NONFINITE || (ks.done == BREAKDOWN && restarts >= 2) ||
+              (ks.done == REPLACE && prev_true > 0.0 && ks.tres2 > 0.25 * prev_true);
+      if (ks.done == REPLACE) prev_true = ks.tres2;
+    }
+    // fold the correction into y (unless it holds non-finite values) and
+    // recompute the residual in FP64
+    if (ks.done != NONFINITE) update(prec);
+    if (stall) {
+      prec = CR_FP64;
+      fell_back = true;
+      residual(prec, 2);
+    } else if (ks.done == BREAKDOWN) {
+      residual(prec, 2);
+      ++restarts;
+    } else {
+      residual(prec, ks.done == STALL ? 2 : 1);
+    }
+    ++reps;
+    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN) || reps > max_rep || iters >= maxit) final_eval = true;
+    return false;
+  }
+
+  cr_status status() const {
+    if (reason == 1) return CR_OK;
+    if (reason == BREAKDOWN) {
+      set_error("Krylov breakdown after %d iterations", iters);
+      return CR_E_BREAKDOWN;
+    }
+    if (reason == NONFINITE) {
+      set_error("non-finite Krylov scalar after %d iterations", iters);
+      return CR_E_NONFINITE;
+    }
+    set_error("no convergence: relative residual %.3e after %d iterations, %d residual evaluations", rel, iters,
+              reps);
+    return CR_E_NOCONV;
+  }
+
+  void fill(cr_solve_info* info, double ms, int requested_prec) const {
+    if (!info) return;
+    info->iters = iters;
+    info->outer_iters = reps;
+    info->rel_residual = rel;
+    info->t_solve_ms = ms;
+    info->reason = reason;
+    info->fp32_iters = requested_prec == CR_FP32_IR ? fp32_iters : 0;
+    info->fp64_fallback = fell_back ? 1 : 0;
+  }
+};
 
 }  // namespace
 
@@ -735,103 +919,35 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   KWs* w = nullptr;
   cr_status st = ensure_ws(s, w);
   if (st != CR_OK) return st;
-  Launch L{s, w, o->precision, o->method};
+  Ctl c;
+  c.init(o);
   const int blk = o->check_every > 0 ? o->check_every : 32;
   const int npairs = std::max(1, (blk + 1) / 2);
   const int per = 2 * npairs;
   const bool graph = o->use_graph != 0;
-  const double tol = o->tol > 0 ? o->tol : 1e-10;
-  // reduction of the recursive residual between residual replacements
-  double rep = o->inner_tol;
-  if (!(rep > 0)) rep = o->precision == CR_FP32_IR ? 0.1 : 0.0;
-  const int maxit = o->maxit > 0 ? o->maxit : 1000000;
-  const int max_rep = o->max_outer > 0 ? o->max_outer : 400;
   if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, s->stream), "zero W");
     if (st != CR_OK) return st;
   }
-  st = write_params(s, w, rep, tol, maxit);
+  st = write_params(w->st, &w->hst[2], o, s->stream);
   if (st != CR_OK) return st;
-  enqueue_residual(L, 0);
-  int reps = 1, restarts = 0, reason = 0, iters = 0, fp32_iters = 0;
-  double rel = -1.0, prev_true = -1.0;
-  bool final_eval = false, fell_back = false;
-  // FP32 intervals between replacements are capped; a stalled FP32 interval
-  // or a replacement that does not halve the true residual switches the
-  // remaining iterations to FP64 (FP32 Krylov cannot make progress once the
-  // condition number times the FP32 unit roundoff approaches one).
-  const int fp32_cap_blocks = std::max(8, 6000 / per);
+  enqueue_residual(s, w, c.prec, c.method, w->st, 0, s->stream);
+  auto upd = [&](int prec) { enqueue_update(s, w, prec, w->st, s->stream); };
+  auto res = [&](int prec, int mode) { enqueue_residual(s, w, prec, c.method, w->st, mode, s->stream); };
   for (;;) {
     KState ks;
-    const bool f32 = L.prec == CR_FP32_IR;
-    const int cap = final_eval ? 1 : (f32 ? fp32_cap_blocks : maxit / per + 3);
-    st = run_inner(L, npairs, graph && !final_eval, cap, ks);
+    Launch L{s, w, c.prec, c.method, w->st};
+    st = run_inner(L, npairs, graph && !c.final_eval, c.final_eval ? 1 : c.maxit / per + 3, ks);
     if (st != CR_OK) return st;
-    if (f32) fp32_iters = ks.nrun;
-    iters = ks.nrun;
-    rel = ks.snorm2 > 0 ? std::sqrt(ks.tres2 / ks.snorm2) : std::sqrt(ks.tres2);
-    if (ks.done == CONVERGED) {
-      reason = 1;
-      break;
-    }
-    if (ks.done == NONFINITE && !f32) {
-      reason = ks.done;
-      break;
-    }
-    if (ks.done == BREAKDOWN && !f32 && (final_eval || restarts >= 8)) {
-      reason = ks.done;
-      break;
-    }
-    if (final_eval) {
-      reason = 3;
-      break;
-    }
-    bool stall = false;
-    if (f32) {
-      stall = ks.done == RUNNING || ks.done == NONFINITE || (ks.done == BREAKDOWN && restarts >= 2) ||
-              (prev_true > 0.0 && ks.tres2 > 0.25 * prev_true);
-      prev_true = ks.tres2;
-    }
-    // fold the correction into y (unless it holds non-finite values) and
-    // recompute the residual in FP64
-    if (ks.done != NONFINITE) enqueue_update(L);
-    if (stall) {
-      L.prec = CR_FP64;
-      fell_back = true;
-      enqueue_residual(L, 2);
-    } else if (ks.done == BREAKDOWN) {
-      enqueue_residual(L, 2);
-      ++restarts;
-    } else {
-      enqueue_residual(L, 1);
-    }
-    ++reps;
-    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN) || reps > max_rep || iters >= maxit) final_eval = true;
+    if (ks.done == RUNNING) ks.done = LIMIT;  // host cap reached
+    if (c.step(ks, upd, res)) break;
   }
   st = check_hip(hipStreamSynchronize(s->stream), "solve sync");
   if (st != CR_OK) return st;
   s->has_solution = true;
-  double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-  if (info) {
-    info->iters = iters;
-    info->outer_iters = reps;
-    info->rel_residual = rel;
-    info->t_solve_ms = ms;
-    info->reason = reason;
-    info->fp32_iters = o->precision == CR_FP32_IR ? fp32_iters : 0;
-    info->fp64_fallback = fell_back ? 1 : 0;
-  }
-  if (reason == 1) return CR_OK;
-  if (reason == BREAKDOWN) {
-    set_error("Krylov breakdown after %d iterations", iters);
-    return CR_E_BREAKDOWN;
-  }
-  if (reason == NONFINITE) {
-    set_error("non-finite Krylov scalar after %d iterations", iters);
-    return CR_E_NONFINITE;
-  }
-  set_error("no convergence: relative residual %.3e after %d iterations, %d residual evaluations", rel, iters, reps);
-  return CR_E_NOCONV;
+  c.fill(info, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count(),
+         o->precision);
+  return c.status();
 }
 
 // Times the dominant kernel (SpMV fused with the CG direction updates) on
@@ -883,15 +999,19 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
                            f32 ? hf.size() * sizeof(float) : vb, hipMemcpyHostToDevice),
                  "timing input");
   if (st != CR_OK) return st;
+  CgSys S = make_sys(s, w, precision, w->tst);
+  S.x = w->tvec[V_X];
+  S.r = w->tvec[V_R0];
+  S.p = w->tvec[V_P];
+  S.q = w->tvec[V_W0];
+  S.Pa = w->tpart[0];
+  S.Pb = w->tpart[1];
   const dim3 grid(P.nblk), blk(NT);
   auto launch = [&]() {
-    dispatch(s, precision, [&](auto dc, auto tc) {
+    dispatch(d, precision, [&](auto dc, auto tc) {
       constexpr int D = decltype(dc)::value;
       using T = decltype(tc);
-      const T* G = std::is_same<T, float>::value ? (const T*)s->G32 : (const T*)s->G64;
-      auto V = [&](int i) { return (T*)w->tvec[i]; };
-      hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, s->stream, P, G, s->cols, V(V_R0), V(V_P), V(V_W0),
-                         w->tpart[0], w->tpart[1], w->tst, 0);
+      hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, s->stream, S, 0);
     });
   };
   launch();  // warm-up
@@ -932,3 +1052,283 @@ void free_krylov(cr_system* s) {
 }
 
 }  // namespace crh
+
+// ---------------------------------------------------------------------------
+// Batched solves: the CG iterations of many resident systems advance in
+// shared launches (block-diagonal batch).  Each launch covers the row ranges of
+// all active systems of one precision; every system keeps its own partial
+// sums, scalars and stop flag, so its iterates are bitwise those of a single
+// solve.  Systems join (cr_batch_add) and leave (when finished) between
+// iteration blocks; replacements and restarts of one system are serviced with
+// that system's own single-system kernels.
+// ---------------------------------------------------------------------------
+namespace crh {
+namespace {
+
+struct BEntry {
+  cr_system* s = nullptr;
+  KWs* w = nullptr;
+  cr_solve_opts o{};
+  Ctl c;
+  bool active = false;
+  std::chrono::steady_clock::time_point t0;
+  cr_status status = CR_OK;
+  cr_solve_info info{};
+};
+
+}  // namespace
+}  // namespace crh
+
+struct cr_batch {
+  hipStream_t stream = nullptr;
+  int max_sys = 0;
+  int d = 0;
+  crh::KState* dst = nullptr;  // device [max_sys]
+  crh::KState* hst = nullptr;  // pinned [max_sys]
+  std::vector<crh::BEntry> e;
+  std::deque<int> finished;
+  crh::CgSys* dtab[2] = {};
+  int* dmap[2] = {};
+  crh::CgSys* htab[2] = {};
+  int* hmap[2] = {};
+  int nblocks[2] = {};
+  int64_t map_cap = 0;
+  bool dirty = true;
+};
+
+namespace crh {
+namespace {
+
+cr_status batch_rebuild(cr_batch* b) {
+  for (int pi = 0; pi < 2; ++pi) {
+    const int prec = pi ? CR_FP32_IR : CR_FP64;
+    int n = 0, blocks = 0;
+    for (int k = 0; k < b->max_sys; ++k) {
+      BEntry& en = b->e[k];
+      if (!en.active || en.c.prec != prec) continue;
+      CgSys S = make_sys(en.s, en.w, prec, b->dst + k);
+      S.boff = blocks;
+      if (blocks + S.P.nblk > b->map_cap) {
+        set_error("batch block table full");
+        return CR_E_NOMEM;
+      }
+      for (int j = 0; j < S.P.nblk; ++j) b->hmap[pi][blocks + j] = n;
+      blocks += S.P.nblk;
+      b->htab[pi][n++] = S;
+    }
+    b->nblocks[pi] = blocks;
+    if (n) {
+      cr_status st = check_hip(
+          hipMemcpyAsync(b->dtab[pi], b->htab[pi], sizeof(CgSys) * n, hipMemcpyHostToDevice, b->stream), "batch table");
+      if (st == CR_OK)
+        st = check_hip(hipMemcpyAsync(b->dmap[pi], b->hmap[pi], sizeof(int) * blocks, hipMemcpyHostToDevice, b->stream),
+                       "batch map");
+      if (st != CR_OK) return st;
+    }
+  }
+  b->dirty = false;
+  return CR_OK;
+}
+
+}  // namespace
+}  // namespace crh
+
+using namespace crh;
+
+extern "C" {
+
+cr_status cr_batch_create(void* hip_stream, int32_t max_systems, cr_batch** out) {
+  clear_error();
+  if (!out || max_systems < 1 || max_systems > 4096) {
+    set_error("cr_batch_create: need an output pointer and 1 <= max_systems <= 4096");
+    return CR_E_INVAL;
+  }
+  *out = nullptr;
+  cr_batch* b = new cr_batch();
+  b->stream = (hipStream_t)hip_stream;
+  b->max_sys = max_systems;
+  b->e.resize(max_systems);
+  b->map_cap = (int64_t)max_systems * max_blocks_cfg() + 8;
+  cr_status st = check_hip(hipMalloc((void**)&b->dst, sizeof(KState) * max_systems), "batch state");
+  if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hst, sizeof(KState) * max_systems, hipHostMallocDefault), "batch state");
+  for (int pi = 0; pi < 2 && st == CR_OK; ++pi) {
+    st = check_hip(hipMalloc((void**)&b->dtab[pi], sizeof(CgSys) * max_systems), "batch table");
+    if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmap[pi], sizeof(int) * b->map_cap), "batch map");
+    if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->htab[pi], sizeof(CgSys) * max_systems, hipHostMallocDefault), "batch table");
+    if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmap[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
+  }
+  if (st != CR_OK) {
+    cr_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return CR_OK;
+}
+
+cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
+  clear_error();
+  if (!b || !s || !o) {
+    set_error("NULL argument");
+    return CR_E_INVAL;
+  }
+  if (!s->eliminated || s->stream != b->stream) {
+    set_error("cr_batch_add needs an eliminated system on the batch's stream");
+    return CR_E_INVAL;
+  }
+  if (o->method != CR_PCG || !(s->params.mu > 0.0 && s->params.problem == CR_STOKES)) {
+    set_error("batched solves run CG on transient Stokes systems");
+    return CR_E_INVAL;
+  }
+  if (o->precision != CR_FP64 && o->precision != CR_FP32_IR) {
+    set_error("unknown precision %d", o->precision);
+    return CR_E_INVAL;
+  }
+  if (b->d && s->d != b->d) {
+    set_error("all systems of a batch have the same dimension");
+    return CR_E_INVAL;
+  }
+  for (const BEntry& en : b->e)
+    if (en.active && en.s == s) {
+      set_error("system already in the batch");
+      return CR_E_INVAL;
+    }
+  int k = -1;
+  for (int i = 0; i < b->max_sys; ++i)
+    if (!b->e[i].active && !b->e[i].s) {
+      k = i;
+      break;
+    }
+  if (k < 0) {
+    set_error("batch full (%d systems)", b->max_sys);
+    return CR_E_NOMEM;
+  }
+  KWs* w = nullptr;
+  cr_status st = ensure_ws(s, w);
+  if (st != CR_OK) return st;
+  BEntry& en = b->e[k];
+  en = BEntry();
+  en.s = s;
+  en.w = w;
+  en.o = *o;
+  en.c.init(o);
+  en.t0 = std::chrono::steady_clock::now();
+  if (!o->warm_start || !s->has_solution) {
+    st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, b->stream), "zero W");
+    if (st != CR_OK) return st;
+  }
+  st = write_params(b->dst + k, b->hst + k, o, b->stream);
+  if (st != CR_OK) return st;
+  enqueue_residual(s, w, en.c.prec, CR_PCG, b->dst + k, 0, b->stream);
+  st = check_hip(hipGetLastError(), "batch add");
+  if (st != CR_OK) return st;
+  en.active = true;
+  b->d = s->d;
+  b->dirty = true;
+  return CR_OK;
+}
+
+cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
+  clear_error();
+  if (!b || n_iters < 1) {
+    set_error("cr_batch_advance: NULL batch or n_iters < 1");
+    return CR_E_INVAL;
+  }
+  cr_status st = CR_OK;
+  if (b->dirty) st = batch_rebuild(b);
+  if (st != CR_OK) return st;
+  const int npairs = (n_iters + 1) / 2;
+  bool any = false;
+  for (int pi = 0; pi < 2; ++pi) any = any || b->nblocks[pi] > 0;
+  if (any) {
+    for (int k = 0; k < npairs; ++k)
+      for (int par = 0; par < 2; ++par)
+        for (int pi = 0; pi < 2; ++pi) {
+          if (!b->nblocks[pi]) continue;
+          dispatch(b->d, pi ? CR_FP32_IR : CR_FP64, [&](auto dc, auto tc) {
+            constexpr int D = decltype(dc)::value;
+            using T = decltype(tc);
+            hipLaunchKernelGGL((k_cg_spmv_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                               b->dmap[pi], par);
+            hipLaunchKernelGGL((k_cg_update_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                               b->dmap[pi], par);
+          });
+        }
+  }
+  st = check_hip(hipMemcpyAsync(b->hst, b->dst, sizeof(KState) * b->max_sys, hipMemcpyDeviceToHost, b->stream),
+                 "batch state");
+  if (st == CR_OK) st = check_hip(hipStreamSynchronize(b->stream), "batch advance");
+  if (st != CR_OK) return st;
+  int nfin = 0;
+  for (int k = 0; k < b->max_sys; ++k) {
+    BEntry& en = b->e[k];
+    if (!en.active) continue;
+    const KState ks = b->hst[k];
+    if (ks.done == RUNNING) continue;
+    const int prec0 = en.c.prec;
+    auto upd = [&](int prec) { enqueue_update(en.s, en.w, prec, b->dst + k, b->stream); };
+    auto res = [&](int prec, int mode) { enqueue_residual(en.s, en.w, prec, CR_PCG, b->dst + k, mode, b->stream); };
+    if (en.c.step(ks, upd, res)) {
+      en.active = false;
+      en.s->has_solution = true;
+      en.c.fill(&en.info,
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - en.t0).count(),
+                en.o.precision);
+      en.status = en.c.status();
+      b->finished.push_back(k);
+      b->dirty = true;
+      ++nfin;
+    } else if (en.c.prec != prec0) {
+      b->dirty = true;
+    }
+  }
+  st = check_hip(hipGetLastError(), "batch service");
+  if (n_finished) *n_finished = nfin;
+  return st;
+}
+
+cr_status cr_batch_pop(cr_batch* b, cr_system** sys, cr_solve_info* info, int32_t* status) {
+  clear_error();
+  if (!b || !sys) {
+    set_error("NULL argument");
+    return CR_E_INVAL;
+  }
+  *sys = nullptr;
+  if (b->finished.empty()) return CR_OK;
+  const int k = b->finished.front();
+  b->finished.pop_front();
+  BEntry& en = b->e[k];
+  *sys = en.s;
+  if (info) *info = en.info;
+  if (status) *status = en.status;
+  en = BEntry();
+  return CR_OK;
+}
+
+cr_status cr_batch_count(const cr_batch* b, int32_t* n_active, int32_t* n_finished) {
+  clear_error();
+  if (!b) {
+    set_error("NULL batch");
+    return CR_E_INVAL;
+  }
+  int a = 0;
+  for (const BEntry& en : b->e) a += en.active ? 1 : 0;
+  if (n_active) *n_active = a;
+  if (n_finished) *n_finished = (int32_t)b->finished.size();
+  return CR_OK;
+}
+
+void cr_batch_destroy(cr_batch* b) {
+  if (!b) return;
+  if (b->stream || b->dst) hipStreamSynchronize(b->stream);
+  if (b->dst) hipFree(b->dst);
+  if (b->hst) hipHostFree(b->hst);
+  for (int pi = 0; pi < 2; ++pi) {
+    if (b->dtab[pi]) hipFree(b->dtab[pi]);
+    if (b->dmap[pi]) hipFree(b->dmap[pi]);
+    if (b->htab[pi]) hipHostFree(b->htab[pi]);
+    if (b->hmap[pi]) hipHostFree(b->hmap[pi]);
+  }
+  delete b;
+}
+
+}  // extern "C"

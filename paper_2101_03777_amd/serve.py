@@ -1,0 +1,162 @@
+"""Continuous-batching server for transient-Stokes time-step requests.
+
+Sessions (a mesh, a time step dt, a force and a number of backward-Euler steps)
+arrive over time.  A session is admitted when the device-memory budget and a
+batch slot allow; its hybridised system (topology, elimination, G) is built
+once and stays resident for all its steps.  Every step is a request:
+
+  step 1:  cr_assemble + cr_eliminate (mu = 1/dt), then solve, then recover;
+  step k:  cr_update_rhs with u_prev = U of step k-1 (same G), solve from the
+           previous W (warm start), recover.
+
+All admitted systems iterate together in one cr_batch: each iteration block is
+one set of launches covering every active system, systems join as they are
+admitted or start their next step and leave as they converge, so requests that
+arrive while others are on the GPU overlap with them on the device.  Latency of
+a request runs from its issue (arrival for step 1, completion of the previous
+step otherwise) to the moment its U and P are on the device.
+
+All device work runs in the HIP library; this module only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+from ._binding import Batch, System
+
+# device bytes per element of a resident 2D system with its Krylov workspace
+# (element data ~304 B, per-face data and ten Krylov vectors ~496 B per face,
+# about 1.5 faces per element), used to decide admission before the system exists
+BYTES_PER_ELEMENT_2D = 1100
+
+
+class Session:
+    def __init__(self, sid, coords, elems, dt, nu, fbar, steps, arrival):
+        self.sid = sid
+        self.coords = coords
+        self.elems = elems
+        self.dt = float(dt)
+        self.nu = float(nu)
+        self.fbar = fbar
+        self.steps = int(steps)
+        self.arrival = float(arrival)
+        self.sys = None
+        self.fdev = None
+        self.done_steps = 0
+        self.req_t0 = None
+        self.bytes = 0
+        self.admitted_at = None
+
+    @property
+    def estimate(self):
+        return BYTES_PER_ELEMENT_2D * len(self.elems)
+
+
+class Server:
+    def __init__(self, hbm_budget=8 << 30, max_active=128, precision="fp32_ir", tol=1e-9, iters_per_advance=32,
+                 inner_tol=0.0):
+        import torch
+        self.torch = torch
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.opts = dict(method="pcg", precision=precision, tol=tol, inner_tol=inner_tol)
+        self.iters = int(iters_per_advance)
+        self.batch = Batch(max_systems=max_active)
+
+    def _admit(self, s, now):
+        torch = self.torch
+        s.sys = System(s.coords, s.elems, mu=1.0 / s.dt, nu=s.nu)
+        s.fdev = torch.from_numpy(np.ascontiguousarray(s.fbar)).cuda()
+        s.sys.eliminate(s.fdev)
+        self.batch.add(s.sys, **self.opts, warm_start=False)
+        s.bytes = s.sys._alloc.bytes_in_use if s.sys._alloc else s.estimate
+        s.admitted_at = now
+
+    def run(self, sessions, on_result=None, time_limit=None):
+        """Replay the arrivals in wall-clock time; return latency/throughput stats.
+
+        on_result(session, step_index, U, P, info) is called for every
+        finished request with device tensors U [n_faces, 2] and P [n_elements].
+        """
+        arr = sorted(sessions, key=lambda s: s.arrival)
+        queue = collections.deque()
+        owner = {}
+        latencies, waits, records = [], [], []
+        in_use = 0
+        n_active = 0
+        peak_active = 0
+        peak_bytes = 0
+        nxt = 0
+        total = sum(s.steps for s in arr)
+        done = 0
+        t0 = time.perf_counter()
+        while done < total:
+            now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit:
+                break
+            while nxt < len(arr) and arr[nxt].arrival <= now:
+                arr[nxt].req_t0 = arr[nxt].arrival
+                queue.append(arr[nxt])
+                nxt += 1
+            # admission by memory budget and batch capacity, in arrival order
+            while queue and n_active < self.max_active:
+                s = queue[0]
+                if s.estimate > self.budget:
+                    raise ValueError(f"session {s.sid} needs {s.estimate} bytes, above the budget {self.budget}")
+                if in_use + s.estimate > self.budget:
+                    break
+                queue.popleft()
+                self._admit(s, time.perf_counter() - t0)
+                owner[s.sys.h.value] = s
+                waits.append(s.admitted_at - s.arrival)
+                in_use += s.bytes
+                n_active += 1
+            peak_active = max(peak_active, n_active)
+            peak_bytes = max(peak_bytes, in_use)
+            if n_active == 0:
+                if nxt < len(arr):
+                    time.sleep(max(0.0, min(0.01, arr[nxt].arrival - (time.perf_counter() - t0))))
+                    continue
+                break
+            self.batch.advance(self.iters)
+            while True:
+                item = self.batch.pop()
+                if item is None:
+                    break
+                sysobj, info = item
+                s = owner[sysobj.h.value]
+                U, P = s.sys.recover()
+                self.torch.cuda.current_stream().synchronize()
+                t_done = time.perf_counter() - t0
+                latencies.append(t_done - s.req_t0)
+                records.append(dict(sid=s.sid, step=s.done_steps, latency=t_done - s.req_t0, iters=info["iters"],
+                                    status=info["status"], rel_residual=info["rel_residual"],
+                                    fp64_fallback=info["fp64_fallback"], n_elements=len(s.elems)))
+                if on_result is not None:
+                    on_result(s, s.done_steps, U, P, info)
+                s.done_steps += 1
+                done += 1
+                if s.done_steps < s.steps:
+                    s.sys.update_rhs(s.fdev, U)
+                    self.batch.add(s.sys, **self.opts, warm_start=True)
+                    s.req_t0 = t_done
+                else:
+                    del owner[s.sys.h.value]
+                    s.sys.close()
+                    s.sys = None
+                    in_use -= s.bytes
+                    n_active -= 1
+        wall = time.perf_counter() - t0
+        lat = np.array(latencies) if latencies else np.zeros(1)
+        return dict(requests=done, sessions=len(arr), wall_s=wall, solves_per_s=done / wall if wall > 0 else 0.0,
+                    p50_ms=1e3 * float(np.percentile(lat, 50)), p99_ms=1e3 * float(np.percentile(lat, 99)),
+                    mean_ms=1e3 * float(lat.mean()), max_queue_wait_ms=1e3 * float(max(waits) if waits else 0.0),
+                    peak_active=peak_active, peak_bytes=int(peak_bytes), budget_bytes=self.budget,
+                    failed=sum(1 for r in records if r["status"] != 0),
+                    fp64_fallbacks=sum(1 for r in records if r["fp64_fallback"]), records=records)
+
+    def close(self):
+        self.batch.close()

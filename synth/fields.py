@@ -140,6 +140,8 @@ class Manufactured:
         self._p = sp.lambdify(X, p, modules="numpy", cse=True)
         self._f = sp.lambdify(X, f, modules="numpy", cse=True)
         self._g = sp.lambdify(X, [g for row in grad for g in row], modules="numpy", cse=True)
+        # the pieces of f separately, for forces with other coefficients
+        self._parts = sp.lambdify(X, u + lap + [sp.diff(p, x) for x in X], modules="numpy", cse=True)
 
     def _eval(self, fn, pts, k):
         cols = [pts[:, i] for i in range(self.dim)]
@@ -157,6 +159,15 @@ class Manufactured:
 
     def f(self, pts):
         return self._eval(self._f, pts, self.dim)
+
+    def force(self, mu, nu):
+        """f = mu u - nu Lap u + grad p for other coefficients than the constructor's."""
+        d = self.dim
+
+        def fn(pts):
+            v = self._eval(self._parts, pts, 3 * d)
+            return mu * v[:, :d] - nu * v[:, d:2 * d] + v[:, 2 * d:]
+        return fn
 
     def grad_u(self, pts):
         return self._eval(self._g, pts, self.dim * self.dim).reshape(-1, self.dim, self.dim)

@@ -78,3 +78,30 @@ def ns_square(n, nu=0.01, seed=0, quad=3):
 
 def ns256():
     return ns_square(256)
+
+
+def serving_sessions(n_requests=2000, seed=1, n_min=32, n_max=512, rate=20.0, dt_range=(1e-3, 1e-1),
+                     max_steps=20, quad=2, nu=1.0):
+    """Transient-Stokes serving workload: sessions arrive as a Poisson process
+    (rate per second); each has an N x N x 2 mesh with N log-uniform in
+    [n_min, n_max], a time step dt uniform in dt_range (mu = 1/dt), 1 to
+    max_steps backward-Euler steps, and the force of one seeded manufactured
+    velocity.  Sessions are drawn until their steps total n_requests.
+    Returns a list of dicts (n, dt, steps, arrival, coords, elems, fbar)."""
+    rng = np.random.default_rng(seed)
+    man = Manufactured(2, seed=seed, mu=1.0, nu=nu)
+    meshes = {}
+    out = []
+    total, t = 0, 0.0
+    while total < n_requests:
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        dt = float(rng.uniform(*dt_range))
+        steps = int(min(rng.integers(1, max_steps + 1), n_requests - total))
+        t += float(rng.exponential(1.0 / rate))
+        if n not in meshes:
+            meshes[n] = square_mesh(n)
+        coords, elems = meshes[n]
+        fbar = element_means(coords, elems, man.force(1.0 / dt, nu), n=quad)
+        out.append(dict(n=n, dt=dt, steps=steps, arrival=t, coords=coords, elems=elems, fbar=fbar, nu=nu))
+        total += steps
+    return out

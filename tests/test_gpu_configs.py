@@ -1,0 +1,266 @@
+"""GPU tests at the benchmark workloads' sizes and for the time-stepping / serving rows.
+
+Full-size workloads are checked through properties the oracle can evaluate
+row by row (its own element matrices, no global solve):
+  * the coupled residual R - A U - D^t P on sampled faces and D_K U_K on every
+    element, for the U, P the GPU recovers (Section 3.1, eq. syslin);
+  * G on sampled faces against the oracle's element-by-element elimination
+    (Section 3.2 item 5);
+  * the copy mismatch equals the hybridised residual (a consequence of the
+    recovery relations of Section 3.2 item 4).
+Smaller meshes are compared with the oracle's direct solution element by
+element.  Batched and served solves are compared bitwise with single solves.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import synth.workloads as wl
+from oracle import cr
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def coupled_rows(P, U, Pk, faces):
+    """Rows (f, i) of R - A U - D^t P for the given faces, from the oracle's element
+    matrices of the two elements of each face; and D_K U_K for every element."""
+    m = P.mesh
+    d = P.d
+    Ul = cr.local_face_values(m, U).reshape(m.ne, -1)
+    div = (P.D * Ul).sum(axis=1)
+    res = np.zeros((len(faces), d))
+    scale = np.zeros(len(faces))
+    for n, f in enumerate(faces):
+        for k in m.face_elems[f]:
+            j = int(np.nonzero(m.elem_face[k] == f)[0][0])
+            rows = slice(j * d, (j + 1) * d)
+            loc = P.R[k][rows] - P.A[k][rows] @ Ul[k] - P.D[k][rows] * Pk[k]
+            res[n] += loc
+            scale[n] = max(scale[n], np.abs(P.R[k][rows]).max(), np.abs(P.A[k][rows] @ Ul[k]).max())
+    return res, div
+
+
+def sampled_G_rows(P, G, faces):
+    """Max deviation of the GPU's G rows from the oracle's elimination of the two
+    elements of each sampled face (general inverse, no Kronecker shortcut)."""
+    m = P.mesh
+    d = P.d
+    worst, scale = 0.0, 0.0
+    for f in faces:
+        ref = {}
+        for k in m.face_elems[f]:
+            Ak, Dk, Rk, gk, idx = cr.restrict(P, k)
+            Ck = np.diag(np.repeat(m.sign[k], d)[idx])
+            Ai = np.linalg.inv(Ak)
+            l = Ai @ Dk
+            Gk = Ck @ (Ai - np.outer(l, l) / (Dk @ l)) @ Ck if k != P.k0 else Ck @ Ai @ Ck
+            for a, ga in enumerate(gk):
+                if ga // d != f:
+                    continue
+                for b_, gb in enumerate(gk):
+                    ref[(ga, gb)] = ref.get((ga, gb), 0.0) + Gk[a, b_]
+        for (ga, gb), v in ref.items():
+            worst = max(worst, abs(G[ga, gb] - v))
+            scale = max(scale, abs(v))
+    return worst, scale
+
+
+def test_c2_full_size_certificate(gpu):
+    """512x512x2 jittered transient Stokes (the benchmark workload), FP64 Krylov to 1e-10."""
+    w = wl.square512j()
+    print("C2 inputs ready", flush=True)
+    s = gpu.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    s.eliminate(dev(w["fbar"]))
+    info = s.solve("pcg", "fp64", tol=1e-10)
+    assert info["rel_residual"] <= 1e-10
+    U, Pk, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+    G, S = s.export_G()
+    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+    rng = np.random.default_rng(0)
+    faces = rng.choice(P.mesh.nf, 300, replace=False)
+    worst, scale = sampled_G_rows(P, G, faces[:100])
+    assert worst <= 1e-10 * scale
+    # copy mismatch == hybridised residual
+    W = s.export_W().ravel()
+    r = np.linalg.norm(S - G @ W)
+    assert abs(J.item() - r) <= 1e-6 * r + 1e-12 * np.linalg.norm(S)
+    assert r <= 1.000001e-10 * np.linalg.norm(S)
+    Uh, Ph = U.cpu().numpy(), Pk.cpu().numpy()
+    res, div = coupled_rows(P, Uh, Ph, faces)
+    R = P.R
+    assert np.abs(res).max() <= 1e-8 * np.abs(R).max()
+    # U takes each face from one copy, so D_K U_K = D_K (copy mismatch): bounded by the solve tolerance
+    assert np.abs(div).max() <= 100 * 1e-10 * np.abs(P.D).max() * np.abs(Uh).max()
+    s.close()
+
+
+def test_c3_full_size_certificate(gpu):
+    """64^3 cubes x6 Kuhn tetrahedra (1,572,864 elements) transient Stokes, FP64 Krylov."""
+    w = wl.cube64()
+    print("C3 inputs ready", flush=True)
+    s = gpu.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    s.eliminate(dev(w["fbar"]))
+    info = s.solve("pcg", "fp64", tol=1e-9)
+    assert info["rel_residual"] <= 1e-9
+    U, Pk, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+    faces = np.random.default_rng(1).choice(P.mesh.nf, 200, replace=False)
+    Uh, Ph = U.cpu().numpy(), Pk.cpu().numpy()
+    res, div = coupled_rows(P, Uh, Ph, faces)
+    assert np.abs(res).max() <= 1e-7 * np.abs(P.R).max()
+    assert np.abs(div).max() <= 100 * 1e-9 * np.abs(P.D).max() * np.abs(Uh).max()
+    s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+def test_c3_small_parity(gpu, precision, bar):
+    """3D Kuhn mesh 5^3 x 6 against the oracle's direct coupled solve."""
+    w = wl.cube(5, mu=100.0)
+    s = gpu.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    s.eliminate(dev(w["fbar"]))
+    s.solve("pcg", precision, tol=1e-13)
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+    Uo, Po = cr.solve_coupled(P)
+    assert relerr(U.cpu().numpy(), Uo) <= bar
+    assert relerr(Pk.cpu().numpy(), Po) <= bar
+    s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+def test_c4_ns_newton_step_parity(gpu, precision, bar):
+    """Steady Navier-Stokes Newton step (nu = 0.01, seeded divergence-free
+    linearisation velocity) on 24x24x2, BiCGStab, against the oracle."""
+    w = wl.ns_square(24, nu=0.01, seed=0)
+    s = gpu.System(w["coords"], w["elems"], 0.0, w["nu"], problem="ns")
+    s.eliminate(dev(w["fbar"]), None, dev(w["ulin"]))
+    info = s.solve("bicgstab", precision, tol=1e-12, maxit=400000)
+    assert info["rel_residual"] <= 1e-12
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    P = cr.make_problem(w["coords"], w["elems"], 0.0, w["nu"], w["fbar"], ulin=w["ulin"])
+    Uo, Po = cr.solve_coupled(P)
+    assert relerr(U.cpu().numpy(), Uo) <= bar
+    assert relerr(Pk.cpu().numpy(), Po) <= bar
+    s.close()
+
+
+def test_c4_full_size_reports_outcome(gpu):
+    """256x256x2 steady NS Newton step: BiCGStab with Jacobi scaling either reaches
+    1e-9 or stops with a clean status (no convergence / breakdown) and a finite
+    best iterate whose residual the info reports."""
+    w = wl.ns256()
+    s = gpu.System(w["coords"], w["elems"], 0.0, w["nu"], problem="ns")
+    s.eliminate(dev(w["fbar"]), None, dev(w["ulin"]))
+    info = s.solve("bicgstab", "fp64", tol=1e-9, maxit=60000, raise_on_error=False)
+    print("C4 256x256 BiCGStab:", info, flush=True)
+    assert info["status"] in (0, -5, -6)
+    assert np.isfinite(info["rel_residual"])
+    if info["status"] == 0:
+        assert info["rel_residual"] <= 1e-9
+    U, Pk = s.recover()
+    assert torch.isfinite(U).all() and torch.isfinite(Pk).all()
+    s.close()
+
+
+def test_multistep_update_rhs_parity(gpu):
+    """Three backward-Euler steps with cr_update_rhs (same G, u_prev = previous U)
+    against the oracle's coupled solves with the same previous velocity."""
+    coords, elems = synth.square_mesh(12, jitter=0.2, seed=5)
+    man = synth.Manufactured(2, seed=5, mu=1.0, nu=1.0)
+    mu, nu = 50.0, 1.0
+    fbar = synth.element_means(coords, elems, man.force(mu, nu), n=4)
+    s = gpu.System(coords, elems, mu, nu)
+    s.eliminate(dev(fbar))
+    uo = None
+    for step in range(3):
+        if step > 0:
+            s.update_rhs(dev(fbar), U)
+        s.solve("pcg", "fp64", tol=1e-13, warm_start=step > 0)
+        U, Pk = s.recover()
+        torch.cuda.synchronize()
+        P = cr.make_problem(coords, elems, mu, nu, fbar, u_prev=uo)
+        uo, po = cr.solve_coupled(P)
+        assert relerr(U.cpu().numpy(), uo) <= 1e-10
+        assert relerr(Pk.cpu().numpy(), po) <= 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_batch_bitwise_equals_single(gpu, precision):
+    systems = []
+    for n, mu in [(8, 300.0), (12, 50.0), (20, 1000.0), (33, 10.0)]:
+        co, el = synth.square_mesh(n, jitter=0.2, seed=n)
+        fb = np.random.default_rng(n).normal(size=(len(el), 2))
+        s = gpu.System(co, el, mu, 1.0)
+        s.eliminate(dev(fb))
+        systems.append(s)
+    solo = []
+    for s in systems:
+        info = s.solve("pcg", precision, tol=1e-11)
+        solo.append((s.export_W(), info["iters"]))
+    b = gpu.Batch(8)
+    for s in systems:
+        b.add(s, method="pcg", precision=precision, tol=1e-11)
+    got = {}
+    while len(got) < len(systems):
+        b.advance(16)
+        while (r := b.pop()) is not None:
+            got[r[0].h.value] = (r[0].export_W(), r[1]["iters"], r[1]["status"])
+    for s, (W, it) in zip(systems, solo):
+        Wb, itb, st = got[s.h.value]
+        assert st == 0 and itb == it
+        assert np.array_equal(W, Wb)
+    assert b.count() == (0, 0)
+    b.close()
+    for s in systems:
+        s.close()
+
+
+def test_serving_mix_equals_solo(gpu):
+    """Requests served in a continuous batch give the same U and P as the same
+    session run alone, step by step (bitwise: same kernels, same decisions)."""
+    from paper_2101_03777_amd.serve import Server, Session
+    ss = wl.serving_sessions(40, seed=3, n_min=8, n_max=40, rate=400.0, max_steps=5)
+    sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"], d["arrival"])
+                for i, d in enumerate(ss)]
+    served = {}
+
+    def keep(sess, step, U, P, info):
+        served[(sess.sid, step)] = (U.cpu().numpy(), P.cpu().numpy(), info["status"])
+
+    srv = Server(hbm_budget=64 << 20, max_active=6, precision="fp32_ir", tol=1e-9)
+    stats = srv.run(sessions, on_result=keep)
+    srv.close()
+    print({k: v for k, v in stats.items() if k != "records"}, flush=True)
+    assert stats["requests"] == sum(d["steps"] for d in ss) == len(served)
+    assert stats["failed"] == 0
+    assert stats["peak_active"] <= 6
+    for i, d in enumerate(ss):
+        s = gpu.System(d["coords"], d["elems"], 1.0 / d["dt"], d["nu"])
+        f = dev(d["fbar"])
+        s.eliminate(f)
+        for step in range(d["steps"]):
+            if step > 0:
+                s.update_rhs(f, U)
+            s.solve("pcg", "fp32_ir", tol=1e-9, warm_start=step > 0)
+            U, Pk = s.recover()
+            Us, Ps, st = served[(i, step)]
+            assert st == 0
+            assert np.array_equal(U.cpu().numpy(), Us), (i, step)
+            assert np.array_equal(Pk.cpu().numpy(), Ps), (i, step)
+        s.close()
