@@ -78,6 +78,31 @@ def cpu_oracle_baseline(ne_target, mu, nu, n_sample=128):
                        f"by element count to {ne_target} elements (sparse LU grows faster, so this favours the CPU)")}
 
 
+def run_serving(args):
+    """Continuous-batching serving run: transient-Stokes time-step requests of
+    sessions arriving as a Poisson process (N x N x 2 meshes, N log-uniform in
+    [32, 512], dt uniform in [1e-3, 1e-1], 1 to 20 steps per session), admitted by
+    a device-memory budget, solved to 1e-9 in one shared batch."""
+    import synth.workloads as wl
+    from paper_2101_03777_amd.serve import Server, Session
+    t0 = time.perf_counter()
+    ss = wl.serving_sessions(args.serve_requests, seed=1, rate=args.serve_rate)
+    log(f"serving inputs: {len(ss)} sessions, {sum(d['steps'] for d in ss)} requests, "
+        f"{time.perf_counter() - t0:.1f} s")
+    sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"], d["arrival"])
+                for i, d in enumerate(ss)]
+    srv = Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_active=128, precision=args.serve_precision,
+                 tol=1e-9)
+    st = srv.run(sessions)
+    srv.close()
+    recs = st.pop("records")
+    st.update(precision=args.serve_precision, tol=1e-9, arrival_rate_sessions_per_s=args.serve_rate,
+              total_iterations=int(sum(r["iters"] for r in recs)),
+              workload="transient Stokes time steps, N x N x 2 meshes, N log-uniform in [32, 512], dt uniform in "
+                       "[1e-3, 1e-1] (mu = 1/dt), 1-20 steps per session, Poisson session arrivals, seed 1")
+    return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +115,11 @@ def main():
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--coupled-maxit", type=int, default=60000)
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="time-step requests of the serving run (0: skip; the full workload has 2000)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="session arrivals per second (Poisson)")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0, help="device-memory budget for admission")
+    ap.add_argument("--serve-precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     ap.add_argument("--kernel-only", action="store_true",
                     help="only build the system and time the dominant kernel (for counter collection)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -198,6 +228,12 @@ def main():
         log(f"coupled MINRES: {ci['t_solve_ms']:.1f} ms, {ci['iters']} iterations, "
             f"residual {ci['rel_residual']:.2e}, converged={ci['status'] == 0}")
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args)
+        log(f"serving: {serving['requests']} requests, {serving['solves_per_s']:.1f} solves/s, "
+            f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_oracle_baseline(len(w["elems"]), mu, nu)
@@ -236,6 +272,7 @@ def main():
         "coupled_gpu": coupled,
         "speedup_vs_coupled": (round(coupled["time_ms"] / float(np.median([r['solve_ms'] for r in recs])), 2)
                                if coupled else None),
+        "serving": serving,
     }
     s.close()
     print(json.dumps(out), flush=True)
