@@ -62,6 +62,13 @@ enum { CR_RCM = 0, CR_NATURAL = 1 };
 enum { CR_PCG = 0, CR_BICGSTAB = 1 };
 /* arithmetic of the Krylov iterations (cr_solve_opts.precision) */
 enum { CR_FP64 = 0, CR_FP32_IR = 1 };
+/* how the Krylov iterations apply G (cr_solve_opts.operator_form):
+ * CR_OP_AUTO: element factors for CG on transient Stokes, assembled rows otherwise;
+ * CR_OP_ASSEMBLED: the assembled block rows of G (Section 3.2 item 5);
+ * CR_OP_ELEMENT: G = sum_K H_K G_K H_K^t applied from the element factors of
+ *   G_K (Section 3.2 items 4-5), without reading the assembled G (CG on
+ *   transient Stokes only). */
+enum { CR_OP_AUTO = 0, CR_OP_ASSEMBLED = 1, CR_OP_ELEMENT = 2 };
 
 typedef struct cr_system cr_system;
 
@@ -132,6 +139,7 @@ typedef struct {
   int32_t check_every; /* iterations per convergence poll (rounded up to even); <= 0: automatic */
   int32_t use_graph;   /* 1: replay the iteration block as a captured hipGraph */
   int32_t warm_start;  /* 1: start from the resident W of the previous solve, 0: from W = 0 */
+  int32_t operator_form; /* CR_OP_AUTO, CR_OP_ASSEMBLED or CR_OP_ELEMENT */
 } cr_solve_opts;
 
 typedef struct {
@@ -147,7 +155,8 @@ typedef struct {
 /* Step a4: Krylov solve of G W = S; W stays resident on the device.
  * PCG applies when mu > 0 and the problem is Stokes (G symmetric positive
  * definite, Section 3.2 item 6); BiCGStab otherwise.  Jacobi preconditioning
- * is applied as the symmetric scaling |diag G|^{-1/2} G |diag G|^{-1/2}.
+ * is applied as the symmetric scaling Ds G Ds with one scale per face,
+ * Ds_f = (mean over the d components of |diag G|)^{-1/2}.
  * CR_FP32_IR runs the Krylov recurrences in FP32 with FP64 residual
  * replacements; if the FP32 iterations stop reducing the FP64 residual, the
  * remaining iterations run in FP64 (reported in cr_solve_info.fp64_fallback).
@@ -204,11 +213,14 @@ cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_i
 /* Average device time of the dominant Krylov kernel (SpMV fused with the CG
  * direction updates) over reps back-to-back launches on the system's stream,
  * measured with HIP events, on scratch copies of the state (the resident
- * solution is untouched).  precision as in cr_solve_opts.  Also returns the
- * algorithmic bytes one launch moves (matrix values and column indices, the
- * gathered input vector once, and the fused vector reads/writes).  Synchronises. */
-cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t reps, double* avg_ms,
-                       double* bytes_per_launch);
+ * solution is untouched).  precision and operator_form as in cr_solve_opts.
+ * Also returns the algorithmic bytes one launch moves: the operator data once
+ * (assembled: values and column indices of G; element form: element factors,
+ * element gather indices, face-to-element table), the gathered input vector
+ * once, and the fused vector reads/writes.  Synchronises.
+ * Errors: CR_E_INVAL (not eliminated, reps < 1, element form unavailable). */
+cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t operator_form, int32_t reps,
+                       double* avg_ms, double* bytes_per_launch);
 
 /* Step a7 (serving): batched CG solves of many resident transient-Stokes
  * systems.  Each kernel launch of a batch covers the rows of every active

@@ -23,6 +23,8 @@ CR_STOKES, CR_NS_NEWTON = 0, 1
 CR_RCM, CR_NATURAL = 0, 1
 CR_PCG, CR_BICGSTAB = 0, 1
 CR_FP64, CR_FP32_IR = 0, 1
+CR_OP_AUTO, CR_OP_ASSEMBLED, CR_OP_ELEMENT = 0, 1, 2
+_OPFORM = {"auto": CR_OP_AUTO, "assembled": CR_OP_ASSEMBLED, "element": CR_OP_ELEMENT}
 
 # every function declared in include/crhyb.h
 EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recover", "cr_query_sizes",
@@ -58,7 +60,7 @@ class Allocator(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("maxit", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32), ("warm_start", C.c_int32)]
+                ("use_graph", C.c_int32), ("warm_start", C.c_int32), ("operator_form", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -94,7 +96,7 @@ def load(path: str = LIB_PATH):
         "cr_topology": (I32, [C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(I64), P, C.POINTER(I64),
                               C.POINTER(I64), P]),
         "cr_coupled_solve": (I32, [P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P, P]),
-        "cr_time_spmv": (I32, [P, I32, I32, C.POINTER(D), C.POINTER(D)]),
+        "cr_time_spmv": (I32, [P, I32, I32, I32, C.POINTER(D), C.POINTER(D)]),
         "cr_destroy": (None, [P]),
         "cr_batch_create": (I32, [P, I32, C.POINTER(P)]),
         "cr_batch_add": (I32, [P, P, C.POINTER(SolveOpts)]),
@@ -190,10 +192,11 @@ class TorchAllocator:
 
 
 def solve_opts(method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-               check_every=0, graph=True, warm_start=False):
+               check_every=0, graph=True, warm_start=False, operator="auto"):
     return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB}[method],
                      {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
-                     int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)))
+                     int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)),
+                     _OPFORM[operator])
 
 
 def info_dict(st, info):
@@ -309,8 +312,9 @@ class System:
         _check(self.lib.cr_update_rhs(self.h, _ptr(f), _ptr(up)))
 
     def solve(self, method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-              check_every=0, graph=True, warm_start=False, raise_on_error=True):
-        o = solve_opts(method, precision, tol, inner_tol, maxit, max_outer, check_every, graph, warm_start)
+              check_every=0, graph=True, warm_start=False, raise_on_error=True, operator="auto"):
+        o = solve_opts(method, precision, tol, inner_tol, maxit, max_outer, check_every, graph, warm_start,
+                       operator)
         info = SolveInfo()
         st = self.lib.cr_solve(self.h, C.byref(o), C.byref(info))
         out = info_dict(st, info)
@@ -330,7 +334,7 @@ class System:
         torch = self._torch
         U = torch.empty((self.n_int_faces, self.dim), dtype=torch.float64, device="cuda")
         P = torch.empty((self.n_elements,), dtype=torch.float64, device="cuda")
-        o = SolveOpts(0, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0)
+        o = SolveOpts(0, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0, CR_OP_AUTO)
         info = SolveInfo()
         st = self.lib.cr_coupled_solve(self.h, C.byref(o), C.byref(info), _ptr(U), _ptr(P))
         if raise_on_error:
@@ -362,10 +366,10 @@ class System:
         _check(self.lib.cr_interior_faces(self.h, _ptr(fv)))
         return fv
 
-    def time_spmv(self, precision="fp32_ir", reps=50):
+    def time_spmv(self, precision="fp32_ir", reps=50, operator="auto"):
         ms, by = C.c_double(), C.c_double()
-        _check(self.lib.cr_time_spmv(self.h, {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], int(reps),
-                                     C.byref(ms), C.byref(by)))
+        _check(self.lib.cr_time_spmv(self.h, {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision],
+                                     _OPFORM[operator], int(reps), C.byref(ms), C.byref(by)))
         return ms.value, by.value
 
     def close(self):

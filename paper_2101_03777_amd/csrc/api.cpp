@@ -217,6 +217,13 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
   if (st == CR_OK) st = alloc_n(s, s->G64, nslot * d * d * nf);
   if (st == CR_OK) st = alloc_n(s, s->G32, nslot * d * d * nf);
   if (st == CR_OK) st = alloc_n(s, s->dsq, nvec);
+  if (st == CR_OK && !ns && s->params.mu > 0.0) {
+    // element-factor form of the scaled operator (transient Stokes CG)
+    const size_t nplanes = (size_t)d1 * (d1 + 1) / 2 + (size_t)d1 * d;
+    st = alloc_n(s, s->efo64, nplanes * ne);
+    if (st == CR_OK) st = alloc_n(s, s->efo32, nplanes * ne);
+    if (st == CR_OK) st = alloc_n(s, s->egat, (size_t)d1 * ne);
+  }
   if (st == CR_OK) st = alloc_n(s, s->bs, nvec);
   if (st == CR_OK) st = alloc_n(s, s->y, nvec);
   if (st == CR_OK) st = alloc_n(s, s->fbar, (size_t)ne * d);
@@ -431,7 +438,8 @@ cr_status cr_interior_faces(const cr_system* s, int32_t* face_vertices) {
   return CR_OK;
 }
 
-cr_status cr_time_spmv(cr_system* s, int32_t precision, int32_t reps, double* avg_ms, double* bytes) {
+cr_status cr_time_spmv(cr_system* s, int32_t precision, int32_t operator_form, int32_t reps, double* avg_ms,
+                       double* bytes) {
   clear_error();
   if (!s || !s->eliminated || reps < 1) {
     set_error("cr_time_spmv needs an eliminated system and reps >= 1");
@@ -441,7 +449,7 @@ cr_status cr_time_spmv(cr_system* s, int32_t precision, int32_t reps, double* av
     set_error("unknown precision %d", precision);
     return CR_E_INVAL;
   }
-  return run_time_spmv(s, precision, reps, avg_ms, bytes);
+  return run_time_spmv(s, precision, operator_form, reps, avg_ms, bytes);
 }
 
 cr_status cr_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {

@@ -16,6 +16,7 @@
 
 #include "internal.h"
 #include "geometry.h"
+#include "rowkern.h"
 
 namespace crh {
 namespace {
@@ -635,16 +636,69 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
       ++slot;
     }
   }
+  // one Jacobi scale per face, sqrt of the mean |diagonal| over its d components
+  double dsum = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
 #pragma unroll
     for (int ip = 0; ip < D; ++ip) G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
     const double dg = fabs(diag[i][i]);
     if (!(dg > 0.0) || !isfinite(dg)) report(err, ERR_ZERODIAG, f);
-    const double sq = sqrt(dg);
+    dsum += dg;
+  }
+  const double sq = sqrt(dsum / D);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
     dsq[f * D + i] = sq;
     bs[f * D + i] = Sf[i] / sq;
   }
+}
+
+// Element factors of the scaled Stokes operator (EfoLayout, rowkern.h) from
+// the Stokes pack and the face scales, one thread per element; FP64 and an
+// FP32 rounding.  egat[l] is the face of local face l, or any interior face of
+// the element for an exterior one (its weights are zero).
+template <int D>
+__global__ void __launch_bounds__(BS) k_efo_build(int64_t ne, const double* __restrict__ pack,
+                                                  const int32_t* __restrict__ eface,
+                                                  const uint32_t* __restrict__ eflags,
+                                                  const double* __restrict__ dsq, double* __restrict__ F64,
+                                                  float* __restrict__ F32, int32_t* __restrict__ egat) {
+  using L = EfoLayout<D>;
+  constexpr int N = D + 1;
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  StokesFactors<D> F;
+  load_stokes_pack<D>(pack, ne, k, F);
+  const uint32_t fl = eflags[k];
+  int32_t fc[N], any = -1;
+  double wl[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    fc[l] = eface[(int64_t)l * ne + k];
+    const bool in = interior(fl, l);
+    if (in && any < 0) any = fc[l];
+    wl[l] = in ? csign(fl, l) / dsq[(int64_t)fc[l] * D] : 0.0;
+  }
+  const double rb = sqrt(F.invB);
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int l = j; l < N; ++l) {
+      const double v = wl[j] * wl[l] * F.Si[j][l];
+      F64[(int64_t)L::tri(j, l) * ne + k] = v;
+      F32[(int64_t)L::tri(j, l) * ne + k] = (float)v;
+    }
+#pragma unroll
+  for (int l = 0; l < N; ++l)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double v = wl[l] * F.V[l][i] * rb;
+      F64[(int64_t)L::vh(l, i) * ne + k] = v;
+      F32[(int64_t)L::vh(l, i) * ne + k] = (float)v;
+    }
+#pragma unroll
+  for (int l = 0; l < N; ++l) egat[(int64_t)l * ne + k] = interior(fl, l) ? fc[l] : any;
 }
 
 // scale G by dsq on both sides and round a copy to FP32
@@ -885,6 +939,9 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL((k_face_assemble<2, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    if (s->efo64)
+      hipLaunchKernelGGL(k_efo_build<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->eface, s->eflags,
+                         s->dsq, s->efo64, s->efo32, s->egat);
   } else {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
@@ -895,6 +952,9 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL((k_face_assemble<3, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    if (s->efo64)
+      hipLaunchKernelGGL(k_efo_build<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->eface, s->eflags,
+                         s->dsq, s->efo64, s->efo32, s->egat);
   }
   st = check_hip(hipGetLastError(), "eliminate launch");
   if (st != CR_OK) return st;

@@ -84,7 +84,11 @@ struct cr_system {
   double* lam = nullptr;       // [ne] lambda of M1 elements (mu == 0)
   double* G64 = nullptr;       // [(2d+1)*d*d][nf] scaled G, FP64
   float* G32 = nullptr;        // same, rounded to FP32
-  double* dsq = nullptr;       // [nf*d] sqrt|diag G|
+  double* dsq = nullptr;       // [nf*d] face scale sqrt(mean_i |G_(f,i),(f,i)|), same for all i
+  // element-factor form of the scaled Stokes operator (layout in rowkern.h)
+  double* efo64 = nullptr;     // [EfoLayout::NF][ne]
+  float* efo32 = nullptr;      // same, rounded to FP32
+  int32_t* egat = nullptr;     // [d+1][ne] face read for local face j (an interior one)
   double* bs = nullptr;        // [nf*d] S / dsq
   double* y = nullptr;         // [nf*d] dsq * W (resident solution, scaled)
   double* fbar = nullptr;      // [ne*d] internal element order
@@ -113,7 +117,7 @@ cr_status run_recover(cr_system* s, double* U, double* P, double* jump);
 
 // Krylov (krylov.hip)
 cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info);
-cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, double* bytes);
+cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double* avg_ms, double* bytes);
 void free_krylov(cr_system* s);
 
 // coupled baseline (coupled.hip)

@@ -18,10 +18,20 @@
 // Krylov space is not lost as it would be by restarting an inner solve.  The
 // solve stops on the FP64 residual ||S - G W|| <= tol ||S||.
 //
-// CG (symmetric positive definite G) runs two kernels per iteration: the
-// product w = G r fused with the direction updates p = r + beta p and
-// q = w + beta q (q = G p without a second product) and the partial p.q; then
-// alpha = rho / p.q, x += alpha p, r -= alpha q and the partial r.r.
+// Operator forms.  The assembled form reads the block-ELL rows of the scaled
+// G.  The element form (transient Stokes) applies G = sum_K H_K G_K H_K^t
+// from per-element factors of G_K (a symmetric (d+1)x(d+1) matrix and a
+// (d+1) x d rank-one factor), about a fifth of the bytes of the assembled rows
+// in 3D and two fifths in 2D.
+//
+// CG (symmetric positive definite G) runs two kernels per iteration.
+// Assembled form: the product w = G r fused with the direction updates
+// p = r + beta p and q = w + beta q (q = G p without a second product) and
+// the partial p.q; then alpha = rho / p.q, x += alpha p, r -= alpha q and the
+// partial r.r.  Element form: an element kernel forms p on the element's faces
+// and its contribution G_K p_K (and p.Gp as a sum of element terms), a face
+// kernel sums the two contributions of each face into q and updates x and r;
+// q is never stored.
 // BiCGStab (non-symmetric G) uses three kernels per iteration.  A Krylov
 // breakdown caused by rounding (p.q <= 0, rho = 0, ...) triggers a restart
 // from the FP64 residual with a fresh direction.
@@ -87,9 +97,10 @@ struct Plain {
 // Everything one CG solve of one system touches; passed by value to the
 // single-system kernels and read from a device table by the batched ones.
 struct CgSys {
-  Part P;
-  int boff;                  // first block of this system in a batched grid
-  int pad;
+  Part P;                    // face rows
+  Part PE;                   // elements (element-centric kernels)
+  int boff;                  // first face block of this system in a batched grid
+  int boffE;                 // first element block of this system in a batched grid
   const void* G;             // matrix plane of the iteration precision
   const int32_t* cols;
   const double* G64;         // FP64 plane (residual)
@@ -103,7 +114,26 @@ struct CgSys {
   double* Pa;                // partials: fields 0 r.r, 1 true residual^2, 2 ||S||^2
   double* Pb;                // partials: field 0 p.q
   KState* st;
+  // element-factor form (transient Stokes)
+  void* p1;                  // second direction buffer (element-centric CG)
+  void* tq;                  // [ne][d+1][d] element contributions w_K
+  const uint32_t* eflags;
+  const void* F;             // factors of the iteration precision
+  const double* F64;         // FP64 factors (residual)
+  const int32_t* egat;
+  const int32_t* fel;
+  const int32_t* floc;
+  int64_t ne;
 };
+
+// One row of the scaled operator: OP 1 = element factors, OP 0 = assembled block-ELL rows.
+template <int D, typename T, int OP, class In>
+__device__ __forceinline__ Vec<T, D> op_row(const CgSys& S, const void* G, const void* F, int64_t f, const In& in) {
+  if constexpr (OP == 1)
+    return efo_row<D, T>(Efo<T>{(const T*)F, S.egat, S.fel, S.floc, S.ne}, S.P.nf, f, in);
+  else
+    return spmv_row<D, T>((const T*)G, S.cols, S.P.nf, f, in);
+}
 
 __device__ __forceinline__ int logical_of(int b, int nblk) { return (b & 7) * (nblk >> 3) + (b >> 3); }
 
@@ -116,7 +146,7 @@ __device__ __forceinline__ int logical_of(int b, int nblk) { return (b & 7) * (n
 // mode 2 (restart after a finite-precision breakdown, or any stop at an odd
 //   iteration): new direction from the next even iteration index, rhat = r.
 // ---------------------------------------------------------------------------
-template <int D, typename T>
+template <int D, typename T, int OP>
 __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __restrict__ rhat, int mode, int bicg) {
   const Part P = S.P;
   KState* st = S.st;
@@ -129,7 +159,7 @@ __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __re
   T* __restrict__ x = (T*)S.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
-    Vec<double, D> w = spmv_row<D, double>(S.G64, S.cols, P.nf, f, Plain<double, D>{S.y});
+    Vec<double, D> w = op_row<D, double, OP>(S, S.G64, S.F64, f, Plain<double, D>{S.y});
     Vec<T, D> rt, zero, rh;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -180,9 +210,9 @@ __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __re
   }
 }
 
-template <int D, typename T>
+template <int D, typename T, int OP>
 __global__ void __launch_bounds__(NT) k_ir_residual(CgSys S, T* __restrict__ rhat, int mode, int bicg) {
-  ir_residual_body<D, T>(S, logical_block(S.P.nblk), rhat, mode, bicg);
+  ir_residual_body<D, T, OP>(S, logical_block(S.P.nblk), rhat, mode, bicg);
 }
 
 // Stopping logic shared by the first kernel of each iteration.  rr is the
@@ -242,29 +272,32 @@ __device__ __forceinline__ void record_decision(KState* st, const Decision& d, b
 // replacement); w = G r, p = r + beta p, q = w + beta q (q = G p without a
 // second product); Pb field 0 = p.q.
 // ---------------------------------------------------------------------------
-template <int D, typename T>
-__device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
+// Start of a CG iteration (parity par), shared by both operator forms: reduces
+// r.r (and after a replacement the true residual and ||S||) from the face
+// partials Pa, applies the stopping logic (the workgroup with logical index 0
+// records it) and returns false if the iteration does not run; else sets beta
+// and whether this iteration starts a new direction.
+__device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f32, double& beta, bool& first) {
   KState* st = S.st;
-  if (st->done) return;
-  const Part P = S.P;
+  if (st->done) return false;
   const int it = st->it[par ^ 1];
-  const bool first = it == st->it_first;
+  first = it == st->it_first;
   const bool fresh = it == st->it_rep;
   double rr, tres2 = 0.0, snorm2 = 0.0;
   if (fresh) {
     const int fl[3] = {0, 1, 2};
     double v[3];
-    reduce_fields<3>(S.Pa, P.nblk, fl, v);
+    reduce_fields<3>(S.Pa, S.P.nblk, fl, v);
     rr = v[0];
     tres2 = v[1];
     snorm2 = v[2];
   } else {
     const int fl[1] = {0};
     double v[1];
-    reduce_fields<1>(S.Pa, P.nblk, fl, v);
+    reduce_fields<1>(S.Pa, S.P.nblk, fl, v);
     rr = v[0];
   }
-  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, std::is_same<T, float>::value);
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, f32);
   if (threadIdx.x == 0 && lb == 0) {
     record_decision(st, dec, fresh, it, rr, tres2, snorm2);
     if (!dec.done) {
@@ -273,16 +306,25 @@ __device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
       st->nrun += 1;
     }
   }
-  if (dec.done) return;
-  const T beta = first ? T(0) : (T)(rr / st->gam[par ^ 1]);
-  const T* __restrict__ G = (const T*)S.G;
+  if (dec.done) return false;
+  beta = first ? 0.0 : rr / st->gam[par ^ 1];
+  return true;
+}
+
+template <int D, typename T, int OP>
+__device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
+  double beta_d;
+  bool first;
+  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first)) return;
+  const Part P = S.P;
+  const T beta = (T)beta_d;
   const T* __restrict__ r = (const T*)S.r;
   T* __restrict__ p = (T*)S.p;
   T* __restrict__ q = (T*)S.q;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   double acc[1] = {0.0};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
-    Vec<T, D> w = spmv_row<D, T>(G, S.cols, P.nf, f, Plain<T, D>{r});
+    Vec<T, D> w = op_row<D, T, OP>(S, S.G, S.F, f, Plain<T, D>{r});
     Vec<T, D> ri = ldv<T, D>(r, f), pi, qi;
     if (first) {
       pi = ri;
@@ -354,9 +396,9 @@ __device__ __forceinline__ void ir_update_body(const CgSys& S, int lb) {
     for (int i = 0; i < D; ++i) S.y[f * D + i] += (double)x[f * D + i];
 }
 
-template <int D, typename T>
+template <int D, typename T, int OP>
 __global__ void __launch_bounds__(NT) k_cg_spmv(CgSys S, int par) {
-  cg_spmv_body<D, T>(S, logical_block(S.P.nblk), par);
+  cg_spmv_body<D, T, OP>(S, logical_block(S.P.nblk), par);
 }
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_cg_update(CgSys S, int par) {
@@ -371,17 +413,157 @@ __global__ void __launch_bounds__(NT) k_ir_update(CgSys S) {
 // bmap[block] is the table entry of the system that block belongs to.  Each
 // system's blocks start at a multiple of 8, so the XCD mapping of a system's
 // rows is the same as in its single-system launch.
-template <int D, typename T>
+template <int D, typename T, int OP>
 __global__ void __launch_bounds__(NT) k_cg_spmv_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap,
                                                   int par) {
   const CgSys S = tab[bmap[blockIdx.x]];
-  cg_spmv_body<D, T>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
+  cg_spmv_body<D, T, OP>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
 }
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_cg_update_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap,
                                                     int par) {
   const CgSys S = tab[bmap[blockIdx.x]];
   cg_update_body<D, T>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
+}
+
+// ---------------------------------------------------------------------------
+// CG with the element-factor operator, element-centric (two kernels per
+// iteration, no stored q):
+//   E1, one thread per element (parity par): after cg_head, the new direction
+//     p = r + beta p_old on the element's d+1 faces (gathered; both elements of
+//     a face compute bit-identical values), w_K = G~_K p_K (its contribution
+//     to G~ p, stored per element), and the partial p.G~p = sum_K p_K.w_K
+//     (each term >= 0 up to rounding: every G~_K is positive semi-definite);
+//     the owner element (C = +1) of each face stores p there.
+//   E2, one thread per face: q = w_K + w_L over the face's two elements (owner
+//     first), alpha = rho / p.G~p, x += alpha p, r -= alpha q, partial r.r.
+// p alternates between two buffers by parity.  w is stored [element][local
+// face][component] so that E2 reads each side as one short vector.
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
+  using L = EfoLayout<D>;
+  constexpr int N = L::N;
+  double beta_d;
+  bool first;
+  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first)) return;
+  const T beta = (T)beta_d;
+  const T* __restrict__ F = (const T*)S.F;
+  const T* __restrict__ r = (const T*)S.r;
+  const T* __restrict__ pold = (const T*)(par ? S.p : S.p1);
+  T* __restrict__ pnew = (T*)(par ? S.p1 : S.p);
+  T* __restrict__ tq = (T*)S.tq;
+  const int64_t ne = S.ne;
+  const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(ne, lo + S.PE.chunk);
+  double acc[1] = {0.0};
+  for (int64_t K = lo + threadIdx.x; K < hi; K += NT) {
+    int32_t g[N];
+    Vec<T, D> pn[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) g[l] = S.egat[(int64_t)l * ne + K];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      pn[l] = ldv<T, D>(r, g[l]);
+      if (!first) {
+        const Vec<T, D> po = ldv<T, D>(pold, g[l]);
+#pragma unroll
+        for (int i = 0; i < D; ++i) pn[l].v[i] = pn[l].v[i] + beta * po.v[i];
+      }
+    }
+    T vh[N][D];
+    T t = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        vh[l][i] = F[(int64_t)L::vh(l, i) * ne + K];
+        t += vh[l][i] * pn[l].v[i];
+      }
+    T sh[L::NSYM];
+#pragma unroll
+    for (int c = 0; c < L::NSYM; ++c) sh[c] = F[(int64_t)c * ne + K];
+    Vec<T, D> w[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        T a = -vh[j][i] * t;
+#pragma unroll
+        for (int l = 0; l < N; ++l) a += sh[L::sym(j, l)] * pn[l].v[i];
+        w[j].v[i] = a;
+        acc[0] += (double)pn[j].v[i] * (double)a;
+      }
+#pragma unroll
+    for (int j = 0; j < N; ++j) stv<T, D>(tq, K * N + j, w[j]);
+    const uint32_t fl = S.eflags[K];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (((fl >> j) & 1u) && !((fl >> (8 + j)) & 1u)) stv<T, D>(pnew, g[j], pn[j]);
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) S.Pb[lb] = acc[0];
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
+  constexpr int N = D + 1;
+  KState* st = S.st;
+  if (st->done) return;
+  const int fl0[1] = {0};
+  double v[1];
+  reduce_fields<1>(S.Pb, S.PE.nblk, fl0, v);
+  const double pq = v[0];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (threadIdx.x == 0 && lb == 0) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
+    return;
+  }
+  const double alpha = st->gam[par] / pq;
+  const T ta = (T)alpha;
+  const Part P = S.P;
+  T* __restrict__ x = (T*)S.x;
+  T* __restrict__ r = (T*)S.r;
+  const T* __restrict__ p = (const T*)(par ? S.p1 : S.p);
+  const T* __restrict__ tq = (const T*)S.tq;
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const int64_t K = S.fel[f], Lr = S.fel[P.nf + f];
+    const int lc = S.floc[f];
+    const Vec<T, D> wk = ldv<T, D>(tq, K * N + (lc & 0xff));
+    const Vec<T, D> wl = ldv<T, D>(tq, Lr * N + ((lc >> 8) & 0xff));
+    Vec<T, D> xi = ldv<T, D>(x, f), ri = ldv<T, D>(r, f), pi = ldv<T, D>(p, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const T qi = wk.v[i] + wl.v[i];
+      xi.v[i] += ta * pi.v[i];
+      ri.v[i] -= ta * qi;
+      acc[0] += (double)ri.v[i] * (double)ri.v[i];
+    }
+    stv<T, D>(x, f, xi);
+    stv<T, D>(r, f, ri);
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) S.Pa[lb] = acc[0];
+  if (threadIdx.x == 0 && lb == 0) st->alp[par] = alpha;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ec1(CgSys S, int par) {
+  ec1_body<D, T>(S, logical_block(S.PE.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ec2(CgSys S, int par) {
+  ec2_body<D, T>(S, logical_block(S.P.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ec1_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap, int par) {
+  const CgSys S = tab[bmap[blockIdx.x]];
+  ec1_body<D, T>(S, logical_of((int)blockIdx.x - S.boffE, S.PE.nblk), par);
+}
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_ec2_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap, int par) {
+  const CgSys S = tab[bmap[blockIdx.x]];
+  ec2_body<D, T>(S, logical_of((int)blockIdx.x - S.boff, S.P.nblk), par);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,18 +751,21 @@ __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __r
 enum { V_X, V_P, V_R0, V_R1, V_W0, V_W1, V_S0, V_S1, V_RHAT, V_T, NVEC };
 
 struct KWs {
-  Part part{};
+  Part part{};           // face rows
+  Part epart{};          // elements
   void* vec[NVEC] = {};  // each nf*d doubles
+  void* tq = nullptr;    // element contributions, ne*(d+1)*d doubles
   double* part3[3] = {};   // partial arrays, NFIELD x nblk each
   KState* st = nullptr;
   KState* hst = nullptr;   // pinned [3]
   hipEvent_t ev[2] = {};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipStream_t cap = nullptr;
-  hipGraphExec_t exec[2][2] = {};  // [precision][method]
-  int exec_m[2][2] = {};
+  hipGraphExec_t exec[2][2][2] = {};  // [precision][method][operator form]
+  int exec_m[2][2][2] = {};
   // scratch for kernel timing
   void* tvec[NVEC] = {};
+  void* ttq = nullptr;
   double* tpart[2] = {};
   KState* tst = nullptr;
 };
@@ -613,12 +798,17 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
   w = new KWs();
   s->kws = w;
   w->part = make_part(s->nf);
+  w->epart = make_part(s->ne);
   const size_t vb = sizeof(double) * (size_t)s->nf * s->d;
   for (auto& v : w->vec) {
     v = dev_alloc(s, vb);
     if (!v) return CR_E_NOMEM;
   }
-  const size_t pbytes = sizeof(double) * (size_t)w->part.nblk * NFIELD;
+  if (s->efo64) {
+    w->tq = dev_alloc(s, sizeof(double) * (size_t)s->ne * (s->d + 1) * s->d);
+    if (!w->tq) return CR_E_NOMEM;
+  }
+  const size_t pbytes = sizeof(double) * (size_t)std::max(w->part.nblk, w->epart.nblk) * NFIELD;
   for (auto& p : w->part3) {
     p = (double*)dev_alloc(s, pbytes);
     if (!p) return CR_E_NOMEM;
@@ -637,6 +827,10 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
 CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
   CgSys S{};
   S.P = w->part;
+  S.PE = w->epart;
+  S.p1 = w->vec[V_W1];
+  S.tq = w->tq;
+  S.eflags = s->eflags;
   S.G = prec == CR_FP32_IR ? (const void*)s->G32 : (const void*)s->G64;
   S.cols = s->cols;
   S.G64 = s->G64;
@@ -650,7 +844,37 @@ CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
   S.Pa = w->part3[0];
   S.Pb = w->part3[1];
   S.st = st;
+  S.F = prec == CR_FP32_IR ? (const void*)s->efo32 : (const void*)s->efo64;
+  S.F64 = s->efo64;
+  S.egat = s->egat;
+  S.fel = s->fel;
+  S.floc = s->floc;
+  S.ne = s->ne;
   return S;
+}
+
+// Operator form of a solve: the element factors (built for transient Stokes)
+// serve CG; the assembled rows serve BiCGStab and explicit requests.
+cr_status resolve_op(const cr_system* s, const cr_solve_opts* o, int& op) {
+  const bool have = s->efo64 != nullptr && o->method == CR_PCG;
+  switch (o->operator_form) {
+    case CR_OP_AUTO:
+      op = have ? 1 : 0;
+      return CR_OK;
+    case CR_OP_ASSEMBLED:
+      op = 0;
+      return CR_OK;
+    case CR_OP_ELEMENT:
+      if (!have) {
+        set_error("the element-factor operator needs CG on a transient Stokes system");
+        return CR_E_INVAL;
+      }
+      op = 1;
+      return CR_OK;
+    default:
+      set_error("unknown operator_form %d", o->operator_form);
+      return CR_E_INVAL;
+  }
 }
 
 template <class F>
@@ -669,28 +893,44 @@ void dispatch(int d, int prec, F&& f) {
   }
 }
 
+// dispatch with the operator form as a third compile-time argument
+template <class F>
+void dispatch_op(int d, int prec, int op, F&& f) {
+  dispatch(d, prec, [&](auto dc, auto tc) {
+    if (op)
+      f(dc, tc, std::integral_constant<int, 1>());
+    else
+      f(dc, tc, std::integral_constant<int, 0>());
+  });
+}
+
 struct Launch {
   cr_system* s;
   KWs* w;
   int prec;    // CR_FP64 or CR_FP32_IR
   int method;  // CR_PCG or CR_BICGSTAB
   KState* st;  // device state of this solve
+  int op;      // operator form (1: element factors)
 };
 
 void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
   KWs* w = L.w;
   const Part P = w->part;
   const dim3 grid(P.nblk), blk(NT);
-  dispatch(L.s->d, L.prec, [&](auto dc, auto tc) {
+  dispatch_op(L.s->d, L.prec, L.op, [&](auto dc, auto tc, auto oc) {
     constexpr int D = decltype(dc)::value;
+    constexpr int OP = decltype(oc)::value;
     using T = decltype(tc);
     auto V = [&](int i) { return (T*)w->vec[i]; };
     const T* G = std::is_same<T, float>::value ? (const T*)L.s->G32 : (const T*)L.s->G64;
     const CgSys S = make_sys(L.s, w, L.prec, L.st);
     for (int k = 0; k < npairs; ++k)
       for (int par = 0; par < 2; ++par) {
-        if (L.method == CR_PCG) {
-          hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, stream, S, par);
+        if constexpr (OP == 1) {
+          hipLaunchKernelGGL((k_ec1<D, T>), dim3(w->epart.nblk), blk, 0, stream, S, par);
+          hipLaunchKernelGGL((k_ec2<D, T>), grid, blk, 0, stream, S, par);
+        } else if (L.method == CR_PCG) {
+          hipLaunchKernelGGL((k_cg_spmv<D, T, 0>), grid, blk, 0, stream, S, par);
           hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, S, par);
         } else {
           T* pv[2] = {V(V_R1), V(V_W1)};  // p buffers
@@ -707,12 +947,14 @@ void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
 }
 
 // residual (replacement) kernel for one system
-void enqueue_residual(cr_system* s, KWs* w, int prec, int method, KState* st, int mode, hipStream_t stream) {
+void enqueue_residual(cr_system* s, KWs* w, int prec, int method, int op, KState* st, int mode,
+                      hipStream_t stream) {
   const Part P = w->part;
-  dispatch(s->d, prec, [&](auto dc, auto tc) {
+  dispatch_op(s->d, prec, op, [&](auto dc, auto tc, auto oc) {
     constexpr int D = decltype(dc)::value;
+    constexpr int OP = decltype(oc)::value;
     using T = decltype(tc);
-    hipLaunchKernelGGL((k_ir_residual<D, T>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st),
+    hipLaunchKernelGGL((k_ir_residual<D, T, OP>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st),
                        (T*)w->vec[V_RHAT], mode, method == CR_BICGSTAB ? 1 : 0);
   });
 }
@@ -728,14 +970,16 @@ void enqueue_update(cr_system* s, KWs* w, int prec, KState* st, hipStream_t stre
 
 cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   KWs* w = L.w;
-  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method == CR_BICGSTAB ? 1 : 0;
-  if (w->exec[pi][mi] && w->exec_m[pi][mi] == npairs) {
-    out = w->exec[pi][mi];
+  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method == CR_BICGSTAB ? 1 : 0, oi = L.op ? 1 : 0;
+  hipGraphExec_t& ex = w->exec[pi][mi][oi];
+  int& exm = w->exec_m[pi][mi][oi];
+  if (ex && exm == npairs) {
+    out = ex;
     return CR_OK;
   }
-  if (w->exec[pi][mi]) {
-    hipGraphExecDestroy(w->exec[pi][mi]);
-    w->exec[pi][mi] = nullptr;
+  if (ex) {
+    hipGraphExecDestroy(ex);
+    ex = nullptr;
   }
   hipGraph_t g = nullptr;
   cr_status st = check_hip(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -749,11 +993,11 @@ cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
     hipGraphDestroy(g);
     return st;
   }
-  st = check_hip(hipGraphInstantiate(&w->exec[pi][mi], g, nullptr, nullptr, 0), "graph instantiate");
+  st = check_hip(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
   hipGraphDestroy(g);
   if (st != CR_OK) return st;
-  w->exec_m[pi][mi] = npairs;
-  out = w->exec[pi][mi];
+  exm = npairs;
+  out = ex;
   return CR_OK;
 }
 
@@ -919,6 +1163,9 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   KWs* w = nullptr;
   cr_status st = ensure_ws(s, w);
   if (st != CR_OK) return st;
+  int op = 0;
+  st = resolve_op(s, o, op);
+  if (st != CR_OK) return st;
   Ctl c;
   c.init(o);
   const int blk = o->check_every > 0 ? o->check_every : 32;
@@ -931,12 +1178,12 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   }
   st = write_params(w->st, &w->hst[2], o, s->stream);
   if (st != CR_OK) return st;
-  enqueue_residual(s, w, c.prec, c.method, w->st, 0, s->stream);
+  enqueue_residual(s, w, c.prec, c.method, op, w->st, 0, s->stream);
   auto upd = [&](int prec) { enqueue_update(s, w, prec, w->st, s->stream); };
-  auto res = [&](int prec, int mode) { enqueue_residual(s, w, prec, c.method, w->st, mode, s->stream); };
+  auto res = [&](int prec, int mode) { enqueue_residual(s, w, prec, c.method, op, w->st, mode, s->stream); };
   for (;;) {
     KState ks;
-    Launch L{s, w, c.prec, c.method, w->st};
+    Launch L{s, w, c.prec, c.method, w->st, op};
     st = run_inner(L, npairs, graph && !c.final_eval, c.final_eval ? 1 : c.maxit / per + 3, ks);
     if (st != CR_OK) return st;
     if (ks.done == RUNNING) ks.done = LIMIT;  // host cap reached
@@ -953,9 +1200,15 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
 // Times the dominant kernel (SpMV fused with the CG direction updates) on
 // scratch vectors; its input r is never written, so every launch does
 // identical work.
-cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, double* bytes) {
+cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double* avg_ms, double* bytes) {
   KWs* w = nullptr;
   cr_status st = ensure_ws(s, w);
+  if (st != CR_OK) return st;
+  cr_solve_opts o{};
+  o.method = CR_PCG;
+  o.operator_form = form;
+  int op = 0;
+  st = resolve_op(s, &o, op);
   if (st != CR_OK) return st;
   const int d = s->d;
   const size_t vb = sizeof(double) * (size_t)s->nf * d;
@@ -966,8 +1219,12 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
       if (!v) return CR_E_NOMEM;
     }
     for (auto& p : w->tpart) {
-      p = (double*)dev_alloc(s, sizeof(double) * (size_t)P.nblk * NFIELD);
+      p = (double*)dev_alloc(s, sizeof(double) * (size_t)std::max(P.nblk, w->epart.nblk) * NFIELD);
       if (!p) return CR_E_NOMEM;
+    }
+    if (s->efo64) {
+      w->ttq = dev_alloc(s, sizeof(double) * (size_t)s->ne * (d + 1) * d);
+      if (!w->ttq) return CR_E_NOMEM;
     }
     w->tst = (KState*)dev_alloc(s, sizeof(KState));
     if (!w->tst) return CR_E_NOMEM;
@@ -1006,12 +1263,18 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
   S.q = w->tvec[V_W0];
   S.Pa = w->tpart[0];
   S.Pb = w->tpart[1];
-  const dim3 grid(P.nblk), blk(NT);
+  S.p1 = w->tvec[V_W1];
+  S.tq = w->ttq;
+  const dim3 grid(op ? w->epart.nblk : P.nblk), blk(NT);
   auto launch = [&]() {
-    dispatch(d, precision, [&](auto dc, auto tc) {
+    dispatch_op(d, precision, op, [&](auto dc, auto tc, auto oc) {
       constexpr int D = decltype(dc)::value;
+      constexpr int OP = decltype(oc)::value;
       using T = decltype(tc);
-      hipLaunchKernelGGL((k_cg_spmv<D, T>), grid, blk, 0, s->stream, S, 0);
+      if constexpr (OP == 1)
+        hipLaunchKernelGGL((k_ec1<D, T>), grid, blk, 0, s->stream, S, 0);
+      else
+        hipLaunchKernelGGL((k_cg_spmv<D, T, 0>), grid, blk, 0, s->stream, S, 0);
     });
   };
   launch();  // warm-up
@@ -1024,13 +1287,20 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
   hipEventElapsedTime(&ms, w->t0, w->t1);
   if (avg_ms) *avg_ms = (double)ms / reps;
   if (bytes) {
-    // values and column indices of G, the gathered input r read once, p and q
-    // read and written
     const double vsz = f32 ? 4.0 : 8.0;
-    const double nf = (double)s->nf;
-    const double mat = nf * (2 * d + 1) * d * d * vsz + nf * 2 * d * 4.0;
-    const double vec = nf * d * vsz * (1 + 2 + 2);
-    *bytes = mat + vec;
+    const double nf = (double)s->nf, ne = (double)s->ne;
+    const int d1 = d + 1;
+    if (op) {
+      // element-centric kernel: element factors, gather indices and flags read
+      // once; r and the previous p read once (gathered); the new p written
+      // once (by the owner elements); w_K written once
+      *bytes = ne * (d1 * (d1 + 1) / 2 + d1 * d) * vsz + ne * (d1 + 1) * 4.0 + nf * d * vsz * 3 +
+               ne * d1 * d * vsz;
+    } else {
+      // values and column indices of G read once, the gathered input r read
+      // once, p and q read and written
+      *bytes = nf * (2 * d + 1) * d * d * vsz + nf * 2 * d * 4.0 + nf * d * vsz * (1 + 2 + 2);
+    }
   }
   return CR_OK;
 }
@@ -1038,9 +1308,10 @@ cr_status run_time_spmv(cr_system* s, int precision, int reps, double* avg_ms, d
 void free_krylov(cr_system* s) {
   KWs* w = (KWs*)s->kws;
   if (!w) return;
-  for (auto& row : w->exec)
-    for (auto& e : row)
-      if (e) hipGraphExecDestroy(e);
+  for (auto& a : w->exec)
+    for (auto& b : a)
+      for (auto& e : b)
+        if (e) hipGraphExecDestroy(e);
   for (auto& e : w->ev)
     if (e) hipEventDestroy(e);
   if (w->t0) hipEventDestroy(w->t0);
@@ -1070,6 +1341,7 @@ struct BEntry {
   KWs* w = nullptr;
   cr_solve_opts o{};
   Ctl c;
+  int op = 0;
   bool active = false;
   std::chrono::steady_clock::time_point t0;
   cr_status status = CR_OK;
@@ -1083,15 +1355,19 @@ struct cr_batch {
   hipStream_t stream = nullptr;
   int max_sys = 0;
   int d = 0;
+  int op = -1;  // operator form shared by all systems of the batch
   crh::KState* dst = nullptr;  // device [max_sys]
   crh::KState* hst = nullptr;  // pinned [max_sys]
   std::vector<crh::BEntry> e;
   std::deque<int> finished;
   crh::CgSys* dtab[2] = {};
-  int* dmap[2] = {};
+  int* dmap[2] = {};   // face block -> table entry
+  int* dmapE[2] = {};  // element block -> table entry
   crh::CgSys* htab[2] = {};
   int* hmap[2] = {};
+  int* hmapE[2] = {};
   int nblocks[2] = {};
+  int nblocksE[2] = {};
   int64_t map_cap = 0;
   bool dirty = true;
 };
@@ -1102,27 +1378,35 @@ namespace {
 cr_status batch_rebuild(cr_batch* b) {
   for (int pi = 0; pi < 2; ++pi) {
     const int prec = pi ? CR_FP32_IR : CR_FP64;
-    int n = 0, blocks = 0;
+    int n = 0, blocks = 0, eblocks = 0;
     for (int k = 0; k < b->max_sys; ++k) {
       BEntry& en = b->e[k];
       if (!en.active || en.c.prec != prec) continue;
       CgSys S = make_sys(en.s, en.w, prec, b->dst + k);
       S.boff = blocks;
-      if (blocks + S.P.nblk > b->map_cap) {
+      S.boffE = eblocks;
+      if (blocks + S.P.nblk > b->map_cap || eblocks + S.PE.nblk > b->map_cap) {
         set_error("batch block table full");
         return CR_E_NOMEM;
       }
       for (int j = 0; j < S.P.nblk; ++j) b->hmap[pi][blocks + j] = n;
+      for (int j = 0; j < S.PE.nblk; ++j) b->hmapE[pi][eblocks + j] = n;
       blocks += S.P.nblk;
+      eblocks += S.PE.nblk;
       b->htab[pi][n++] = S;
     }
     b->nblocks[pi] = blocks;
+    b->nblocksE[pi] = eblocks;
     if (n) {
       cr_status st = check_hip(
           hipMemcpyAsync(b->dtab[pi], b->htab[pi], sizeof(CgSys) * n, hipMemcpyHostToDevice, b->stream), "batch table");
       if (st == CR_OK)
         st = check_hip(hipMemcpyAsync(b->dmap[pi], b->hmap[pi], sizeof(int) * blocks, hipMemcpyHostToDevice, b->stream),
                        "batch map");
+      if (st == CR_OK)
+        st = check_hip(
+            hipMemcpyAsync(b->dmapE[pi], b->hmapE[pi], sizeof(int) * eblocks, hipMemcpyHostToDevice, b->stream),
+            "batch map");
       if (st != CR_OK) return st;
     }
   }
@@ -1154,8 +1438,10 @@ cr_status cr_batch_create(void* hip_stream, int32_t max_systems, cr_batch** out)
   for (int pi = 0; pi < 2 && st == CR_OK; ++pi) {
     st = check_hip(hipMalloc((void**)&b->dtab[pi], sizeof(CgSys) * max_systems), "batch table");
     if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmap[pi], sizeof(int) * b->map_cap), "batch map");
+    if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmapE[pi], sizeof(int) * b->map_cap), "batch map");
     if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->htab[pi], sizeof(CgSys) * max_systems, hipHostMallocDefault), "batch table");
     if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmap[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
+    if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmapE[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
   }
   if (st != CR_OK) {
     cr_batch_destroy(b);
@@ -1202,8 +1488,17 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
     set_error("batch full (%d systems)", b->max_sys);
     return CR_E_NOMEM;
   }
+  int op = 0;
+  cr_status st = resolve_op(s, o, op);
+  if (st != CR_OK) return st;
+  int n_act = 0;
+  for (const BEntry& en : b->e) n_act += en.active ? 1 : 0;
+  if (n_act && b->op >= 0 && op != b->op) {
+    set_error("all systems of a batch use the same operator form");
+    return CR_E_INVAL;
+  }
   KWs* w = nullptr;
-  cr_status st = ensure_ws(s, w);
+  st = ensure_ws(s, w);
   if (st != CR_OK) return st;
   BEntry& en = b->e[k];
   en = BEntry();
@@ -1211,6 +1506,7 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
   en.w = w;
   en.o = *o;
   en.c.init(o);
+  en.op = op;
   en.t0 = std::chrono::steady_clock::now();
   if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, b->stream), "zero W");
@@ -1218,11 +1514,12 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
   }
   st = write_params(b->dst + k, b->hst + k, o, b->stream);
   if (st != CR_OK) return st;
-  enqueue_residual(s, w, en.c.prec, CR_PCG, b->dst + k, 0, b->stream);
+  enqueue_residual(s, w, en.c.prec, CR_PCG, op, b->dst + k, 0, b->stream);
   st = check_hip(hipGetLastError(), "batch add");
   if (st != CR_OK) return st;
   en.active = true;
   b->d = s->d;
+  b->op = op;
   b->dirty = true;
   return CR_OK;
 }
@@ -1244,13 +1541,21 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
       for (int par = 0; par < 2; ++par)
         for (int pi = 0; pi < 2; ++pi) {
           if (!b->nblocks[pi]) continue;
-          dispatch(b->d, pi ? CR_FP32_IR : CR_FP64, [&](auto dc, auto tc) {
+          dispatch_op(b->d, pi ? CR_FP32_IR : CR_FP64, b->op, [&](auto dc, auto tc, auto oc) {
             constexpr int D = decltype(dc)::value;
+            constexpr int OP = decltype(oc)::value;
             using T = decltype(tc);
-            hipLaunchKernelGGL((k_cg_spmv_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
-                               b->dmap[pi], par);
-            hipLaunchKernelGGL((k_cg_update_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
-                               b->dmap[pi], par);
+            if constexpr (OP == 1) {
+              hipLaunchKernelGGL((k_ec1_b<D, T>), dim3(b->nblocksE[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                                 b->dmapE[pi], par);
+              hipLaunchKernelGGL((k_ec2_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                                 b->dmap[pi], par);
+            } else {
+              hipLaunchKernelGGL((k_cg_spmv_b<D, T, 0>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                                 b->dmap[pi], par);
+              hipLaunchKernelGGL((k_cg_update_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+                                 b->dmap[pi], par);
+            }
           });
         }
   }
@@ -1266,7 +1571,9 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
     if (ks.done == RUNNING) continue;
     const int prec0 = en.c.prec;
     auto upd = [&](int prec) { enqueue_update(en.s, en.w, prec, b->dst + k, b->stream); };
-    auto res = [&](int prec, int mode) { enqueue_residual(en.s, en.w, prec, CR_PCG, b->dst + k, mode, b->stream); };
+    auto res = [&](int prec, int mode) {
+      enqueue_residual(en.s, en.w, prec, CR_PCG, en.op, b->dst + k, mode, b->stream);
+    };
     if (en.c.step(ks, upd, res)) {
       en.active = false;
       en.s->has_solution = true;
@@ -1325,8 +1632,10 @@ void cr_batch_destroy(cr_batch* b) {
   for (int pi = 0; pi < 2; ++pi) {
     if (b->dtab[pi]) hipFree(b->dtab[pi]);
     if (b->dmap[pi]) hipFree(b->dmap[pi]);
+    if (b->dmapE[pi]) hipFree(b->dmapE[pi]);
     if (b->htab[pi]) hipHostFree(b->htab[pi]);
     if (b->hmap[pi]) hipHostFree(b->hmap[pi]);
+    if (b->hmapE[pi]) hipHostFree(b->hmapE[pi]);
   }
   delete b;
 }

@@ -84,6 +84,80 @@ __device__ __forceinline__ Vec<T, D> spmv_row(const T* __restrict__ G, const int
   return w;
 }
 
+// ---------------------------------------------------------------------------
+// Element-factor form of the scaled Stokes operator Ds G Ds (Ds = 1/dsq, one
+// scale per face).  G = sum_K H_K G_K H_K^t with, for Stokes,
+//   G_K[(j,i),(l,i')] = c_j c_l (delta_ii' (S_K^{-1})_jl - V_ji V_li' / B_K)
+// (Section 3.2 items 4-5; A^_K = S_K (x) I_d), so the scaled element matrix is
+//   delta_ii' Sh_jl - Vh_ji Vh_li',   Sh_jl = c_j c_l (S_K^{-1})_jl / (s_j s_l),
+//                                     Vh_ji = c_j V_ji sqrt(1/B_K) / s_j,
+// with s_j the scale of local face j.  Per element that is N(N+1)/2 + N D
+// numbers (12 in 2D, 22 in 3D) instead of the (2d+1) d^2 numbers per face of
+// the assembled rows.  Rows of exterior faces are zero.  A face row sums the
+// row of its local face in its two elements; the element data of each
+// element is read by its d+1 faces, mostly from cache.
+// ---------------------------------------------------------------------------
+template <int D>
+struct EfoLayout {
+  static constexpr int N = D + 1;
+  static constexpr int NSYM = N * (N + 1) / 2;
+  static constexpr int NF = NSYM + N * D;  // planes per element
+  // packed upper triangle (row-major) index of (a, b), a <= b
+  __host__ __device__ static constexpr int tri(int a, int b) { return a * N - a * (a - 1) / 2 + (b - a); }
+  __host__ __device__ static constexpr int sym(int j, int l) { return j <= l ? tri(j, l) : tri(l, j); }
+  __host__ __device__ static constexpr int vh(int l, int i) { return NSYM + l * D + i; }
+};
+
+template <typename T>
+struct Efo {
+  const T* __restrict__ F;           // [NF][ne]
+  const int32_t* __restrict__ egat;  // [N][ne] face read for local face l (zero weight if exterior)
+  const int32_t* __restrict__ fel;   // [2][nf] the two elements of a face
+  const int32_t* __restrict__ floc;  // [nf] local index in the first | in the second << 8
+  int64_t ne;
+};
+
+template <int D, typename T, class In>
+__device__ __forceinline__ Vec<T, D> efo_row(const Efo<T>& E, int64_t nf, int64_t f, const In& in) {
+  using L = EfoLayout<D>;
+  constexpr int N = L::N;
+  const int lc = E.floc[f];
+  Vec<T, D> w;
+#pragma unroll
+  for (int i = 0; i < D; ++i) w.v[i] = T(0);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int64_t K = E.fel[(int64_t)side * nf + f];
+    const int j = (lc >> (8 * side)) & 0xff;
+    Vec<T, D> xv[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) xv[l] = in(E.egat[(int64_t)l * E.ne + K]);
+    T vh[N][D];
+    T t = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        vh[l][i] = E.F[(int64_t)L::vh(l, i) * E.ne + K];
+        t += vh[l][i] * xv[l].v[i];
+      }
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const T sh = E.F[(int64_t)L::sym(j, l) * E.ne + K];
+#pragma unroll
+      for (int i = 0; i < D; ++i) w.v[i] += sh * xv[l].v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T vj = vh[0][i];
+#pragma unroll
+      for (int l = 1; l < N; ++l) vj = j == l ? vh[l][i] : vj;
+      w.v[i] -= vj * t;
+    }
+  }
+  return w;
+}
+
 template <int M>
 __device__ __forceinline__ void block_sum(double (&v)[M]) {
   __shared__ double sh[M][NT / 64];

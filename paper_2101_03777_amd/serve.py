@@ -28,9 +28,10 @@ import numpy as np
 from ._binding import Batch, System
 
 # device bytes per element of a resident 2D system with its Krylov workspace
-# (element data ~304 B, per-face data and ten Krylov vectors ~496 B per face,
+# (element data ~510 B including the operator factors and the per-element Krylov
+# contributions, per-face data and ten Krylov vectors ~496 B per face,
 # about 1.5 faces per element), used to decide admission before the system exists
-BYTES_PER_ELEMENT_2D = 1100
+BYTES_PER_ELEMENT_2D = 1300
 
 
 class Session:

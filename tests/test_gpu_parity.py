@@ -119,15 +119,16 @@ def test_jump_equals_residual_random_W(gpu):
     s.close()
 
 
+@pytest.mark.parametrize("operator", ["element", "assembled"])
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
 @pytest.mark.parametrize("name", ["square16", "jitter12", "cube3"])
-def test_pcg_solution_parity(gpu, name, precision, bar):
+def test_pcg_solution_parity(gpu, name, precision, bar, operator):
     case = make_case(name)
-    print(f"case {name} {precision}", flush=True)
+    print(f"case {name} {precision} {operator}", flush=True)
     P = oracle_problem(case)
     U_o, P_o = cr.solve_coupled(P)
     s = gpu_system(gpu, case)
-    info = s.solve("pcg", precision, tol=1e-13, check_every=8)
+    info = s.solve("pcg", precision, tol=1e-13, check_every=8, operator=operator)
     assert info["rel_residual"] <= 1e-13
     U, Pk = s.recover()
     torch.cuda.synchronize()
@@ -151,6 +152,33 @@ def test_bicgstab_solution_parity(gpu, name, precision, bar):
     assert relerr(U.cpu().numpy(), U_o) <= bar
     assert relerr(Pk.cpu().numpy(), P_o) <= bar
     s.close()
+
+
+@pytest.mark.parametrize("name", ["jitter12", "cube3"])
+def test_operator_forms_agree(gpu, name):
+    """The element-factor operator and the assembled rows apply the same G:
+    solves to 1e-13 with either form give the same W up to the conditioning of G,
+    and the element form is refused where it does not exist (BiCGStab, mu = 0)."""
+    case = make_case(name)
+    s = gpu_system(gpu, case)
+    a = s.solve("pcg", "fp64", tol=1e-13, check_every=8, operator="element")
+    Wa = s.export_W()
+    b = s.solve("pcg", "fp64", tol=1e-13, check_every=8, operator="assembled")
+    Wb = s.export_W()
+    assert a["rel_residual"] <= 1e-13 and b["rel_residual"] <= 1e-13
+    assert relerr(Wa, Wb) <= 1e-10
+    # each form's FP64 residual certifies the other's solution: warm start from W_a
+    # with the assembled form stops at once
+    s.import_W(Wa)
+    c = s.solve("pcg", "fp64", tol=1e-12, warm_start=True, operator="assembled")
+    assert c["iters"] == 0
+    with pytest.raises(gpu.CRError):
+        s.solve("bicgstab", "fp64", tol=1e-10, operator="element")
+    s.close()
+    st = gpu_system(gpu, make_case("steady10"))
+    with pytest.raises(gpu.CRError):
+        st.solve("pcg", "fp64", tol=1e-10, operator="element")
+    st.close()
 
 
 def test_graph_and_plain_launches_agree(gpu):
