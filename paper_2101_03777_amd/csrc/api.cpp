@@ -188,7 +188,10 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
         enb[(size_t)j * ne + k] = -1;
       }
     }
-    if (c == params->k0) fl |= F_K0;
+    if (c == params->k0) {
+      fl |= F_K0;
+      s->k0i = k;
+    }
     if (t.m1[c]) fl |= F_M1;
     eflags[k] = fl;
   }
@@ -223,6 +226,9 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
     st = alloc_n(s, s->efo64, nplanes * ne);
     if (st == CR_OK) st = alloc_n(s, s->efo32, nplanes * ne);
     if (st == CR_OK) st = alloc_n(s, s->egat, (size_t)d1 * ne);
+    if (st == CR_OK) st = alloc_n(s, s->bs1, nvec);
+    if (st == CR_OK) st = alloc_n(s, s->zy, nvec);
+    if (st == CR_OK) st = alloc_n(s, s->k0t, (size_t)1);
   }
   if (st == CR_OK) st = alloc_n(s, s->bs, nvec);
   if (st == CR_OK) st = alloc_n(s, s->y, nvec);

@@ -654,12 +654,38 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
   }
 }
 
+// l = A^_K^{-1} D_K and 1/B_K of K0 (the pack stores zeros for K0), from its
+// geometry and the stored inverse: D_K = -a restricted to interior faces.
+template <int D>
+__device__ __forceinline__ void k0_schur(const double* __restrict__ ecoord, int64_t ne, int64_t k, uint32_t fl,
+                                         StokesFactors<D>& F) {
+  constexpr int N = D + 1;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  double B = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) v -= F.Si[j][l] * (interior(fl, l) ? g.a[l][i] : 0.0);
+      F.V[j][i] = v;
+      B -= (interior(fl, j) ? g.a[j][i] : 0.0) * v;
+    }
+  F.invB = 1.0 / B;
+}
+
 // Element factors of the scaled Stokes operator (EfoLayout, rowkern.h) from
 // the Stokes pack and the face scales, one thread per element; FP64 and an
 // FP32 rounding.  egat[l] is the face of local face l, or any interior face of
-// the element for an exterior one (its weights are zero).
+// the element for an exterior one (its weights are zero).  K0 gets its Schur
+// term like every other element: the operator of the element form is
+// G' = G - u u^t / B_K0 with u = C_K0 l_K0, whose null vector is z
+// (C_K z_K = -D_K on every element).
 template <int D>
 __global__ void __launch_bounds__(BS) k_efo_build(int64_t ne, const double* __restrict__ pack,
+                                                  const double* __restrict__ ecoord,
                                                   const int32_t* __restrict__ eface,
                                                   const uint32_t* __restrict__ eflags,
                                                   const double* __restrict__ dsq, double* __restrict__ F64,
@@ -671,6 +697,7 @@ __global__ void __launch_bounds__(BS) k_efo_build(int64_t ne, const double* __re
   StokesFactors<D> F;
   load_stokes_pack<D>(pack, ne, k, F);
   const uint32_t fl = eflags[k];
+  if (fl & F_K0) k0_schur<D>(ecoord, ne, k, fl, F);
   int32_t fc[N], any = -1;
   double wl[N];
 #pragma unroll
@@ -699,6 +726,79 @@ __global__ void __launch_bounds__(BS) k_efo_build(int64_t ne, const double* __re
     }
 #pragma unroll
   for (int l = 0; l < N; ++l) egat[(int64_t)l * ne + k] = interior(fl, l) ? fc[l] : any;
+}
+
+// Null vector of G' in scaled variables: zy_f = dsq_f a_{K,f}, K the owner
+// (C = +1) element of face f.
+template <int D>
+__global__ void __launch_bounds__(BS) k_zvec(int64_t nf, int64_t ne, const int32_t* __restrict__ fel,
+                                             const int32_t* __restrict__ floc, const double* __restrict__ ecoord,
+                                             const double* __restrict__ dsq, double* __restrict__ zy) {
+  const int64_t f = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (f >= nf) return;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, fel[f], g);
+  const int j = floc[f] & 0xff;
+#pragma unroll
+  for (int i = 0; i < D; ++i) zy[f * D + i] = dsq[f * D + i] * g.a[j][i];
+}
+
+// Right-hand side of the element form: S' = S - u (l_K0^t R_K0) / B_K0, a
+// change on the faces of K0 only (bs1 holds a copy of the scaled S).  One thread.
+template <int D>
+__global__ void k_k0_rhs(int64_t ne, int64_t k, const double* __restrict__ pack, const double* __restrict__ ecoord,
+                         const int32_t* __restrict__ eface, const uint32_t* __restrict__ eflags,
+                         const double* __restrict__ RK, const double* __restrict__ dsq, double* __restrict__ bs1) {
+  constexpr int N = D + 1;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  StokesFactors<D> F;
+  load_stokes_pack<D>(pack, ne, k, F);
+  const uint32_t fl = eflags[k];
+  k0_schur<D>(ecoord, ne, k, fl, F);
+  double rho = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      if (interior(fl, j)) rho += F.V[j][i] * RK[(int64_t)(j * D + i) * ne + k];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (!interior(fl, j)) continue;
+    const int64_t f = eface[(int64_t)j * ne + k];
+#pragma unroll
+    for (int i = 0; i < D; ++i) bs1[f * D + i] -= csign(fl, j) * F.V[j][i] * rho * F.invB / dsq[f * D + i];
+  }
+}
+
+// Gauge shift: for a solution W' of G' W' = S', W = W' + t z solves G W = S
+// with t = -P_K0(W'), P_K0(W') = l^t (R - C W') / B at K0.  One thread writes t.
+template <int D>
+__global__ void k_k0_gauge(int64_t ne, int64_t k, const double* __restrict__ pack, const double* __restrict__ ecoord,
+                           const int32_t* __restrict__ eface, const uint32_t* __restrict__ eflags,
+                           const double* __restrict__ RK, const double* __restrict__ y,
+                           const double* __restrict__ dsq, double* __restrict__ t) {
+  constexpr int N = D + 1;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  StokesFactors<D> F;
+  load_stokes_pack<D>(pack, ne, k, F);
+  const uint32_t fl = eflags[k];
+  k0_schur<D>(ecoord, ne, k, fl, F);
+  double p = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (!interior(fl, j)) continue;
+    const int64_t f = eface[(int64_t)j * ne + k];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      p += F.V[j][i] * (RK[(int64_t)(j * D + i) * ne + k] - csign(fl, j) * y[f * D + i] / dsq[f * D + i]);
+  }
+  t[0] = -p * F.invB;
+}
+
+__global__ void __launch_bounds__(BS) k_gauge_axpy(int64_t n, const double* __restrict__ t,
+                                                   const double* __restrict__ zy, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) y[i] += t[0] * zy[i];
 }
 
 // scale G by dsq on both sides and round a copy to FP32
@@ -909,6 +1009,32 @@ static cr_status gather_inputs(cr_system* s, const double* f_mean, const double*
   return check_hip(hipGetLastError(), "gather inputs");
 }
 
+// S' of the element form from the current S
+static cr_status k0_rhs(cr_system* s) {
+  cr_status st = check_hip(hipMemcpyAsync(s->bs1, s->bs, sizeof(double) * s->nf * s->d, hipMemcpyDeviceToDevice,
+                                          s->stream), "element-form right-hand side");
+  if (st != CR_OK) return st;
+  if (s->d == 2)
+    hipLaunchKernelGGL(k_k0_rhs<2>, dim3(1), dim3(64), 0, s->stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
+                       s->eflags, s->RK, s->dsq, s->bs1);
+  else
+    hipLaunchKernelGGL(k_k0_rhs<3>, dim3(1), dim3(64), 0, s->stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
+                       s->eflags, s->RK, s->dsq, s->bs1);
+  return check_hip(hipGetLastError(), "element-form right-hand side");
+}
+
+cr_status enqueue_gauge_fix(cr_system* s, hipStream_t stream) {
+  if (s->d == 2)
+    hipLaunchKernelGGL(k_k0_gauge<2>, dim3(1), dim3(64), 0, stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
+                       s->eflags, s->RK, s->y, s->dsq, s->k0t);
+  else
+    hipLaunchKernelGGL(k_k0_gauge<3>, dim3(1), dim3(64), 0, stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
+                       s->eflags, s->RK, s->y, s->dsq, s->k0t);
+  const int64_t n = s->nf * s->d;
+  hipLaunchKernelGGL(k_gauge_axpy, dim3(nblocks(n, BS)), dim3(BS), 0, stream, n, s->k0t, s->zy, s->y);
+  return check_hip(hipGetLastError(), "gauge shift");
+}
+
 cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin) {
   const int d = s->d;
   const bool ns = s->params.problem == CR_NS_NEWTON;
@@ -940,8 +1066,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
     if (s->efo64)
-      hipLaunchKernelGGL(k_efo_build<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->eface, s->eflags,
-                         s->dsq, s->efo64, s->efo32, s->egat);
+      hipLaunchKernelGGL(k_efo_build<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->ecoord, s->eface,
+                         s->eflags, s->dsq, s->efo64, s->efo32, s->egat);
   } else {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
@@ -953,11 +1079,21 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
     if (s->efo64)
-      hipLaunchKernelGGL(k_efo_build<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->eface, s->eflags,
-                         s->dsq, s->efo64, s->efo32, s->egat);
+      hipLaunchKernelGGL(k_efo_build<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->ecoord, s->eface,
+                         s->eflags, s->dsq, s->efo64, s->efo32, s->egat);
   }
   st = check_hip(hipGetLastError(), "eliminate launch");
   if (st != CR_OK) return st;
+  if (s->efo64) {
+    if (d == 2)
+      hipLaunchKernelGGL(k_zvec<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->ecoord,
+                         s->dsq, s->zy);
+    else
+      hipLaunchKernelGGL(k_zvec<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->ecoord,
+                         s->dsq, s->zy);
+    st = k0_rhs(s);
+    if (st != CR_OK) return st;
+  }
   st = read_err(s, "cr_eliminate");
   if (st != CR_OK) return st;
   st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * d, s->stream), "zero W");
@@ -986,7 +1122,9 @@ cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_pre
     hipLaunchKernelGGL(k_face_rhs<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->sK, s->dsq,
                        s->bs);
   }
-  return check_hip(hipGetLastError(), "update_rhs launch");
+  st = check_hip(hipGetLastError(), "update_rhs launch");
+  if (st == CR_OK && s->efo64) st = k0_rhs(s);
+  return st;
 }
 
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {

@@ -89,6 +89,13 @@ struct cr_system {
   double* efo64 = nullptr;     // [EfoLayout::NF][ne]
   float* efo32 = nullptr;      // same, rounded to FP32
   int32_t* egat = nullptr;     // [d+1][ne] face read for local face j (an interior one)
+  // The element form carries the Schur term of K0 as well (pressure gauge
+  // moved out of G, see krylov.hip): its right-hand side, the null vector of
+  // that operator in scaled variables, and the gauge shift of the last solve.
+  double* bs1 = nullptr;       // [nf*d]
+  double* zy = nullptr;        // [nf*d]
+  double* k0t = nullptr;       // [1]
+  int64_t k0i = 0;             // internal id of K0
   double* bs = nullptr;        // [nf*d] S / dsq
   double* y = nullptr;         // [nf*d] dsq * W (resident solution, scaled)
   double* fbar = nullptr;      // [ne*d] internal element order
@@ -114,6 +121,9 @@ cr_status check_hip(hipError_t e, const char* what);
 cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin);
 cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_prev);
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump);
+// Maps a solution of the element-form system (with the K0 Schur term) to the
+// solution of G W = S: y += t zy with t = -(K0 pressure of that solution).
+cr_status enqueue_gauge_fix(cr_system* s, hipStream_t stream);
 
 // Krylov (krylov.hip)
 cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info);
