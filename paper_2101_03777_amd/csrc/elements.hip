@@ -631,8 +631,9 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int ip = 0; ip < D; ++ip)
+        for (int ip = 0; ip < D; ++ip) {
           G[(int64_t)(slot * DD + i * D + ip) * nf + f] = in ? c * src.g(j, i, l, ip) : 0.0;
+        }
       ++slot;
     }
   }
@@ -641,7 +642,9 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
 #pragma unroll
   for (int i = 0; i < D; ++i) {
 #pragma unroll
-    for (int ip = 0; ip < D; ++ip) G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
+    for (int ip = 0; ip < D; ++ip) {
+      G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
+    }
     const double dg = fabs(diag[i][i]);
     if (!(dg > 0.0) || !isfinite(dg)) report(err, ERR_ZERODIAG, f);
     dsum += dg;

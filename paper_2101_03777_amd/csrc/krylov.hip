@@ -75,7 +75,7 @@
 namespace crh {
 namespace {
 
-constexpr int NFIELD = 4;  // fields of a partial record
+constexpr int NFIELD = 6;  // fields of a partial record
 
 // done codes
 enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5, STALL = 6 };
@@ -94,6 +94,10 @@ struct KState {
   int nrun;        // iterations executed since the start of the solve
   int pad0;
   double rr_rep, thr_rep, tgt, tres2, snorm2, last_rr;
+  // BiCGStab(2) scalars of the iteration with each parity, each written by one
+  // kernel and read by later ones: rho after the even and the odd BiCG step,
+  // beta and alpha of both steps, omega_2 of the minimal-residual step
+  double rho_a[2], beta1[2], alpha1[2], rho_b[2], beta2[2], alpha2[2], omega2[2];
   // parameters written by the host
   double rep_tol2, tol2;
   int maxit;
@@ -759,10 +763,292 @@ __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __r
 }
 
 // ---------------------------------------------------------------------------
+// BiCGStab(2) on the scaled non-symmetric system: per iteration two BiCG steps
+// followed by a minimal-residual step over a polynomial of degree two, which
+// (unlike the degree-one step of BiCGStab) can damp both signs of a real
+// indefinite spectrum.  Five kernels per iteration, four products with G,
+// each product fed on the fly with the linear combination it acts on:
+//   E1: rho1 = rhat.r, beta1 = alpha rho1 / rho0 (rho0 = -omega2 rho_prev);
+//       u1 = r - beta1 u, v = G u1; partial rhat.v
+//   E2: alpha1 = rho1 / rhat.v; r1 = r - alpha1 v, s = G r1; x += alpha1 u1;
+//       partial rhat.s
+//   E3: beta2 = alpha1 rhat.s / rho1; v1 = s - beta2 v, w = G v1; partial rhat.w
+//   E4: alpha2 = rhat.s / rhat.w; u2 = r1 - beta2 u1, r2 = r1 - alpha2 v1,
+//       s2 = s - alpha2 w, t = G s2; partials r2.s2, s2.s2, s2.t, t.t, r2.t
+//   E5: omega1, omega2 minimise |r2 - omega1 s2 - omega2 t|;
+//       x += omega1 r2 + omega2 s2 + alpha2 u2, r = r2 - omega1 s2 - omega2 t,
+//       u = u2 - omega1 v1 - omega2 w; partials rhat.r, r.r
+// rhat is the fixed shadow residual (reset to r at a restart).
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+struct AxpyIn {
+  const T* __restrict__ a;
+  const T* __restrict__ b;
+  T coef;
+  bool only_a;
+  __device__ Vec<T, D> operator()(int64_t c) const {
+    Vec<T, D> x = ldv<T, D>(a, c);
+    if (only_a) return x;
+    const Vec<T, D> y = ldv<T, D>(b, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) x.v[i] -= coef * y.v[i];
+    return x;
+  }
+};
+
+struct B2Vecs {
+  void* x;
+  void* r;
+  void* r1;
+  void* u;
+  void* u1;
+  void* v;
+  void* v1;
+  void* s;
+  void* s2;
+  void* w;
+  void* t;
+  void* rhat;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void rowrange(const Part& P, int& lb, int64_t& lo, int64_t& hi) {
+  lb = logical_block(P.nblk);
+  lo = (int64_t)lb * P.chunk;
+  hi = min(P.nf, lo + P.chunk);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_b2_1(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
+                                             B2Vecs V, const double* __restrict__ Pa, double* __restrict__ Pb,
+                                             KState* __restrict__ st, int par) {
+  if (st->done) return;
+  const int it = st->it[par ^ 1];
+  const bool first = it == st->it_first;
+  const bool fresh = it == st->it_rep;
+  double rho1, rr, tres2 = 0.0, snorm2 = 0.0;
+  if (fresh) {
+    const int fl[4] = {0, 3, 1, 2};
+    double v[4];
+    reduce_fields<4>(Pa, P.nblk, fl, v);
+    rho1 = v[0];
+    rr = v[1];
+    tres2 = v[2];
+    snorm2 = v[3];
+  } else {
+    const int fl[2] = {0, 3};
+    double v[2];
+    reduce_fields<2>(Pa, P.nblk, fl, v);
+    rho1 = v[0];
+    rr = v[1];
+  }
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, std::is_same<T, float>::value);
+  int done = dec.done;
+  if (!done && (!(rho1 != 0.0) || !isfinite(rho1))) done = isfinite(rho1) ? BREAKDOWN : NONFINITE;
+  double beta1 = 0.0;
+  if (!first) {
+    const double rho0 = -st->omega2[par ^ 1] * st->rho_b[par ^ 1];
+    beta1 = st->alpha2[par ^ 1] * rho1 / rho0;
+  }
+  if (lead()) {
+    record_decision(st, dec, fresh, it, rr, tres2, snorm2);
+    if (done) {
+      st->done = done;
+    } else {
+      st->rho_a[par] = rho1;
+      st->beta1[par] = beta1;
+      st->it[par] = it + 1;
+      st->nrun += 1;
+    }
+  }
+  if (done) return;
+  const AxpyIn<T, D> in{(const T*)V.r, (const T*)V.u, (T)beta1, first};
+  int lb;
+  int64_t lo, hi;
+  rowrange<D, T>(P, lb, lo, hi);
+  const T* __restrict__ rhat = (const T*)V.rhat;
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<T, D> vv = spmv_row<D, T>(G, cols, P.nf, f, in);
+    stv<T, D>((T*)V.u1, f, in(f));
+    stv<T, D>((T*)V.v, f, vv);
+    const Vec<T, D> rh = ldv<T, D>(rhat, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[0] += (double)rh.v[i] * (double)vv.v[i];
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) Pb[lb] = acc[0];
+}
+
+// E2 and E4 share the breakdown test of a denominator from one partial field
+__device__ __forceinline__ bool b2_denominator(const double* __restrict__ part, int nblk, KState* st, double& val) {
+  const int fl[1] = {0};
+  double v[1];
+  reduce_fields<1>(part, nblk, fl, v);
+  val = v[0];
+  if (!(val != 0.0) || !isfinite(val)) {
+    if (lead()) st->done = isfinite(val) ? BREAKDOWN : NONFINITE;
+    return false;
+  }
+  return true;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_b2_2(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
+                                             B2Vecs V, const double* __restrict__ Pb, double* __restrict__ Pc,
+                                             KState* __restrict__ st, int par) {
+  if (st->done) return;
+  double g1;
+  if (!b2_denominator(Pb, P.nblk, st, g1)) return;
+  const double alpha1 = st->rho_a[par] / g1;
+  const AxpyIn<T, D> in{(const T*)V.r, (const T*)V.v, (T)alpha1, false};
+  int lb;
+  int64_t lo, hi;
+  rowrange<D, T>(P, lb, lo, hi);
+  const T ta = (T)alpha1;
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<T, D> ss = spmv_row<D, T>(G, cols, P.nf, f, in);
+    stv<T, D>((T*)V.r1, f, in(f));
+    stv<T, D>((T*)V.s, f, ss);
+    Vec<T, D> xi = ldv<T, D>((const T*)V.x, f);
+    const Vec<T, D> ui = ldv<T, D>((const T*)V.u1, f), rh = ldv<T, D>((const T*)V.rhat, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      xi.v[i] += ta * ui.v[i];
+      acc[0] += (double)rh.v[i] * (double)ss.v[i];
+    }
+    stv<T, D>((T*)V.x, f, xi);
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) Pc[lb] = acc[0];
+  if (lead()) st->alpha1[par] = alpha1;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_b2_3(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
+                                             B2Vecs V, const double* __restrict__ Pc, double* __restrict__ Pb,
+                                             KState* __restrict__ st, int par) {
+  if (st->done) return;
+  double rho2;
+  if (!b2_denominator(Pc, P.nblk, st, rho2)) return;
+  const double beta2 = st->alpha1[par] * rho2 / st->rho_a[par];
+  const AxpyIn<T, D> in{(const T*)V.s, (const T*)V.v, (T)beta2, false};
+  int lb;
+  int64_t lo, hi;
+  rowrange<D, T>(P, lb, lo, hi);
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<T, D> ww = spmv_row<D, T>(G, cols, P.nf, f, in);
+    stv<T, D>((T*)V.v1, f, in(f));
+    stv<T, D>((T*)V.w, f, ww);
+    const Vec<T, D> rh = ldv<T, D>((const T*)V.rhat, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[0] += (double)rh.v[i] * (double)ww.v[i];
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) Pb[lb] = acc[0];
+  if (lead()) {
+    st->rho_b[par] = rho2;
+    st->beta2[par] = beta2;
+  }
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_b2_4(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
+                                             B2Vecs V, const double* __restrict__ Pb, double* __restrict__ Pc,
+                                             KState* __restrict__ st, int par) {
+  if (st->done) return;
+  double g2;
+  if (!b2_denominator(Pb, P.nblk, st, g2)) return;
+  const double alpha2 = st->rho_b[par] / g2;
+  const T ta = (T)alpha2, tb = (T)st->beta2[par];
+  const AxpyIn<T, D> in{(const T*)V.s, (const T*)V.w, ta, false};
+  int lb;
+  int64_t lo, hi;
+  rowrange<D, T>(P, lb, lo, hi);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<T, D> tt = spmv_row<D, T>(G, cols, P.nf, f, in);
+    const Vec<T, D> s2 = in(f);
+    Vec<T, D> r1 = ldv<T, D>((const T*)V.r1, f), u1 = ldv<T, D>((const T*)V.u1, f);
+    const Vec<T, D> v1 = ldv<T, D>((const T*)V.v1, f);
+    Vec<T, D> u2;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      u2.v[i] = r1.v[i] - tb * u1.v[i];
+      r1.v[i] -= ta * v1.v[i];  // r2
+      acc[0] += (double)r1.v[i] * (double)s2.v[i];
+      acc[1] += (double)s2.v[i] * (double)s2.v[i];
+      acc[2] += (double)s2.v[i] * (double)tt.v[i];
+      acc[3] += (double)tt.v[i] * (double)tt.v[i];
+      acc[4] += (double)r1.v[i] * (double)tt.v[i];
+    }
+    stv<T, D>((T*)V.u, f, u2);
+    stv<T, D>((T*)V.r1, f, r1);
+    stv<T, D>((T*)V.s2, f, s2);
+    stv<T, D>((T*)V.t, f, tt);
+  }
+  block_sum<5>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Pc[(int64_t)m * P.nblk + lb] = acc[m];
+  if (lead()) st->alpha2[par] = alpha2;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_b2_5(Part P, B2Vecs V, const double* __restrict__ Pc,
+                                             double* __restrict__ Pa, KState* __restrict__ st, int par) {
+  if (st->done) return;
+  const int fl[5] = {0, 1, 2, 3, 4};
+  double v[5];
+  reduce_fields<5>(Pc, P.nblk, fl, v);
+  const double rs = v[0], ss = v[1], stt = v[2], tt = v[3], rt = v[4];
+  // minimise |r2 - omega1 s2 - omega2 t| (Gram-Schmidt of t against s2)
+  const double tau = tt - stt * stt / ss;
+  bool ok = ss > 0.0 && tau > 0.0 && isfinite(ss) && isfinite(tau) && isfinite(rs) && isfinite(rt);
+  if (!ok) {
+    if (lead()) st->done = (isfinite(ss) && isfinite(tt) && isfinite(rs) && isfinite(rt)) ? BREAKDOWN : NONFINITE;
+    return;
+  }
+  const double om2 = (rt - stt * rs / ss) / tau;
+  const double om1 = (rs - stt * om2) / ss;
+  const T o1 = (T)om1, o2 = (T)om2, ta = (T)st->alpha2[par];
+  int lb;
+  int64_t lo, hi;
+  rowrange<D, T>(P, lb, lo, hi);
+  double acc[2] = {0.0, 0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    Vec<T, D> xi = ldv<T, D>((const T*)V.x, f), u2 = ldv<T, D>((const T*)V.u, f);
+    const Vec<T, D> r2 = ldv<T, D>((const T*)V.r1, f), s2 = ldv<T, D>((const T*)V.s2, f),
+                    ti = ldv<T, D>((const T*)V.t, f), v1 = ldv<T, D>((const T*)V.v1, f),
+                    wi = ldv<T, D>((const T*)V.w, f), rh = ldv<T, D>((const T*)V.rhat, f);
+    Vec<T, D> rn;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      xi.v[i] += o1 * r2.v[i] + o2 * s2.v[i] + ta * u2.v[i];
+      rn.v[i] = r2.v[i] - o1 * s2.v[i] - o2 * ti.v[i];
+      u2.v[i] -= o1 * v1.v[i] + o2 * wi.v[i];
+      acc[0] += (double)rh.v[i] * (double)rn.v[i];
+      acc[1] += (double)rn.v[i] * (double)rn.v[i];
+    }
+    stv<T, D>((T*)V.x, f, xi);
+    stv<T, D>((T*)V.r, f, rn);
+    stv<T, D>((T*)V.u, f, u2);
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    Pa[lb] = acc[0];
+    Pa[(int64_t)3 * P.nblk + lb] = acc[1];
+  }
+  if (lead()) st->omega2[par] = om2;
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // vector slots of the workspace
-enum { V_X, V_P, V_R0, V_R1, V_W0, V_W1, V_S0, V_S1, V_RHAT, V_T, NVEC };
+enum { V_X, V_P, V_R0, V_R1, V_W0, V_W1, V_S0, V_S1, V_RHAT, V_T, V_U2, V_V2, NVEC };
 
 struct KWs {
   Part part{};           // face rows
@@ -775,8 +1061,8 @@ struct KWs {
   hipEvent_t ev[2] = {};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipStream_t cap = nullptr;
-  hipGraphExec_t exec[2][2][2] = {};  // [precision][method][operator form]
-  int exec_m[2][2][2] = {};
+  hipGraphExec_t exec[2][3][2] = {};  // [precision][method][operator form]
+  int exec_m[2][3][2] = {};
   // scratch for kernel timing
   void* tvec[NVEC] = {};
   void* ttq = nullptr;
@@ -923,7 +1209,7 @@ struct Launch {
   cr_system* s;
   KWs* w;
   int prec;    // CR_FP64 or CR_FP32_IR
-  int method;  // CR_PCG or CR_BICGSTAB
+  int method;  // CR_PCG, CR_BICGSTAB or CR_BICGSTAB2
   KState* st;  // device state of this solve
   int op;      // operator form (1: element factors)
 };
@@ -947,6 +1233,18 @@ void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
         } else if (L.method == CR_PCG) {
           hipLaunchKernelGGL((k_cg_spmv<D, T, 0>), grid, blk, 0, stream, S, par);
           hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, S, par);
+        } else if (L.method == CR_BICGSTAB2) {
+          const B2Vecs BV{V(V_X), V(V_R0), V(V_R1), V(V_P), V(V_W1), V(V_W0), V(V_U2), V(V_S0), V(V_S1), V(V_V2),
+                          V(V_T), V(V_RHAT)};
+          hipLaunchKernelGGL((k_b2_1<D, T>), grid, blk, 0, stream, P, G, L.s->cols, BV, w->part3[0], w->part3[1],
+                             L.st, par);
+          hipLaunchKernelGGL((k_b2_2<D, T>), grid, blk, 0, stream, P, G, L.s->cols, BV, w->part3[1], w->part3[2],
+                             L.st, par);
+          hipLaunchKernelGGL((k_b2_3<D, T>), grid, blk, 0, stream, P, G, L.s->cols, BV, w->part3[2], w->part3[1],
+                             L.st, par);
+          hipLaunchKernelGGL((k_b2_4<D, T>), grid, blk, 0, stream, P, G, L.s->cols, BV, w->part3[1], w->part3[2],
+                             L.st, par);
+          hipLaunchKernelGGL((k_b2_5<D, T>), grid, blk, 0, stream, P, BV, w->part3[2], w->part3[0], L.st, par);
         } else {
           T* pv[2] = {V(V_R1), V(V_W1)};  // p buffers
           T* vv[2] = {V(V_S0), V(V_S1)};  // v buffers
@@ -970,7 +1268,7 @@ void enqueue_residual(cr_system* s, KWs* w, int prec, int method, int op, KState
     constexpr int OP = decltype(oc)::value;
     using T = decltype(tc);
     hipLaunchKernelGGL((k_ir_residual<D, T, OP>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st),
-                       (T*)w->vec[V_RHAT], mode, method == CR_BICGSTAB ? 1 : 0);
+                       (T*)w->vec[V_RHAT], mode, method != CR_PCG ? 1 : 0);
   });
 }
 
@@ -985,7 +1283,7 @@ void enqueue_update(cr_system* s, KWs* w, int prec, KState* st, hipStream_t stre
 
 cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   KWs* w = L.w;
-  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method == CR_BICGSTAB ? 1 : 0, oi = L.op ? 1 : 0;
+  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method, oi = L.op ? 1 : 0;
   hipGraphExec_t& ex = w->exec[pi][mi][oi];
   int& exm = w->exec_m[pi][mi][oi];
   if (ex && exm == npairs) {
@@ -1127,8 +1425,10 @@ struct Ctl {
       if (ks.done == REPLACE) prev_true = ks.tres2;
     }
     // fold the correction into y (unless it holds non-finite values) and
-    // recompute the residual in FP64
-    if (ks.done != NONFINITE) update(prec);
+    // recompute the residual in FP64.  When the FP32 iterations of a
+    // non-symmetric method stall, their last correction is discarded: without
+    // CG's monotone error reduction it may have grown.
+    if (ks.done != NONFINITE && !(stall && method != CR_PCG)) update(prec);
     if (stall) {
       prec = CR_FP64;
       fell_back = true;

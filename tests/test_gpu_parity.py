@@ -137,15 +137,16 @@ def test_pcg_solution_parity(gpu, name, precision, bar, operator):
     s.close()
 
 
+@pytest.mark.parametrize("method", ["bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
 @pytest.mark.parametrize("name", ["steady10", "ns10"])
-def test_bicgstab_solution_parity(gpu, name, precision, bar):
+def test_bicgstab_solution_parity(gpu, name, precision, bar, method):
     case = make_case(name)
-    print(f"case {name} {precision}", flush=True)
+    print(f"case {name} {precision} {method}", flush=True)
     P = oracle_problem(case)
     U_o, P_o = cr.solve_coupled(P)
     s = gpu_system(gpu, case)
-    info = s.solve("bicgstab", precision, tol=1e-13, check_every=8, maxit=200000)
+    info = s.solve(method, precision, tol=1e-13, check_every=8, maxit=200000)
     assert info["rel_residual"] <= 1e-13
     U, Pk = s.recover()
     torch.cuda.synchronize()
