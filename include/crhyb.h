@@ -59,11 +59,11 @@ enum { CR_STOKES = 0, CR_NS_NEWTON = 1 };
 /* face numbering (cr_params.renumber) */
 enum { CR_RCM = 0, CR_NATURAL = 1 };
 /* Krylov methods (cr_solve_opts.method): CG for symmetric positive definite G;
- * for non-symmetric or indefinite G: BiCGStab, and BiCGStab(2) (two BiCG steps
- * and a degree-two minimal-residual step per iteration, four products with G;
- * it converges on the strongly indefinite G of the steady Newton step where
- * BiCGStab breaks down). */
-enum { CR_PCG = 0, CR_BICGSTAB = 1, CR_BICGSTAB2 = 2 };
+ * MINRES for symmetric G, definite or not (steady Stokes); for non-symmetric G:
+ * BiCGStab, and BiCGStab(2) (two BiCG steps and a degree-two minimal-residual
+ * step per iteration, four products with G; it converges on the strongly
+ * indefinite G of the steady Newton step where BiCGStab breaks down). */
+enum { CR_PCG = 0, CR_BICGSTAB = 1, CR_BICGSTAB2 = 2, CR_MINRES = 3 };
 /* arithmetic of the Krylov iterations (cr_solve_opts.precision) */
 enum { CR_FP64 = 0, CR_FP32_IR = 1 };
 /* how the Krylov iterations apply G (cr_solve_opts.operator_form):
@@ -133,7 +133,7 @@ cr_status cr_eliminate(cr_system* sys, const double* f_mean, const double* u_pre
 cr_status cr_update_rhs(cr_system* sys, const double* f_mean, const double* u_prev);
 
 typedef struct {
-  int32_t method;      /* CR_PCG (symmetric positive definite G), CR_BICGSTAB or CR_BICGSTAB2 */
+  int32_t method;      /* CR_PCG, CR_MINRES, CR_BICGSTAB or CR_BICGSTAB2 */
   int32_t precision;   /* CR_FP64, or CR_FP32_IR: FP32 Krylov inside FP64 iterative refinement */
   double tol;          /* stop when ||S - G W||_2 <= tol ||S||_2, residual recomputed in FP64 */
   double inner_tol;    /* factor by which the recursive residual falls between FP64 residual
@@ -158,7 +158,9 @@ typedef struct {
 
 /* Step a4: Krylov solve of G W = S; W stays resident on the device.
  * PCG applies when mu > 0 and the problem is Stokes (G symmetric positive
- * definite, Section 3.2 item 6); BiCGStab or BiCGStab(2) otherwise.  Jacobi
+ * definite, Section 3.2 item 6); MINRES for symmetric indefinite G (steady
+ * Stokes, Section 3.2 item 7), in refinement passes that each restart from the
+ * FP64 residual; BiCGStab or BiCGStab(2) otherwise.  Jacobi
  * preconditioning is applied as the symmetric scaling Ds G Ds with one scale
  * per face,
  * Ds_f = (mean over the d components of |diag G|)^{-1/2}.

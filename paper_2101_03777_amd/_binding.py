@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "CR_OK", -1: "CR_E_INVAL", -2: "CR_E_NOMEM", -3: "CR_E_MESH",
                 -5: "CR_E_NOCONV", -6: "CR_E_BREAKDOWN", -7: "CR_E_NONFINITE", -8: "CR_E_DEVICE"}
 CR_STOKES, CR_NS_NEWTON = 0, 1
 CR_RCM, CR_NATURAL = 0, 1
-CR_PCG, CR_BICGSTAB, CR_BICGSTAB2 = 0, 1, 2
+CR_PCG, CR_BICGSTAB, CR_BICGSTAB2, CR_MINRES = 0, 1, 2, 3
 CR_FP64, CR_FP32_IR = 0, 1
 CR_OP_AUTO, CR_OP_ASSEMBLED, CR_OP_ELEMENT = 0, 1, 2
 _OPFORM = {"auto": CR_OP_AUTO, "assembled": CR_OP_ASSEMBLED, "element": CR_OP_ELEMENT}
@@ -193,7 +193,7 @@ class TorchAllocator:
 
 def solve_opts(method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
                check_every=0, graph=True, warm_start=False, operator="auto"):
-    return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB, "bicgstab2": CR_BICGSTAB2}[method],
+    return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB, "bicgstab2": CR_BICGSTAB2, "minres": CR_MINRES}[method],
                      {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
                      int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)),
                      _OPFORM[operator])

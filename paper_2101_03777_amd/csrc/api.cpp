@@ -291,7 +291,7 @@ cr_status cr_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
     set_error("cr_solve before cr_eliminate");
     return CR_E_INVAL;
   }
-  if (o->method < CR_PCG || o->method > CR_BICGSTAB2) {
+  if (o->method < CR_PCG || o->method > CR_MINRES) {
     set_error("unknown method %d", o->method);
     return CR_E_INVAL;
   }

@@ -78,7 +78,11 @@ namespace {
 constexpr int NFIELD = 6;  // fields of a partial record
 
 // done codes
-enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5, STALL = 6 };
+enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5, STALL = 6, DIVERGED = 7 };
+
+// growth of the recursive |r|^2 since the last residual evaluation that is
+// treated as divergence (a factor 1e6 in norm)
+constexpr double DIVERGE2 = 1e12;
 
 struct KState {
   // per iteration parity
@@ -129,6 +133,7 @@ struct CgSys {
   void* q;
   double* Pa;                // partials: fields 0 r.r, 1 true residual^2, 2 ||S||^2
   double* Pb;                // partials: field 0 p.q
+  double* Pc;                // third partial array (MINRES)
   KState* st;
   // element-factor form (transient Stokes)
   void* p1;                  // second direction buffer (element-centric CG)
@@ -262,6 +267,8 @@ __device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh,
   }
   if (!isfinite(rr))
     d.done = NONFINITE;
+  else if (rr > DIVERGE2 * d.rr_rep)
+    d.done = DIVERGED;
   else if (it >= st->maxit)
     d.done = LIMIT;
   else if (!fresh && !(it & 1) && (rr <= d.thr_rep || rr <= d.tgt))
@@ -1045,6 +1052,228 @@ __global__ void __launch_bounds__(NT) k_b2_5(Part P, B2Vecs V, const double* __r
 }
 
 // ---------------------------------------------------------------------------
+// MINRES (Paige-Saunders) on the scaled symmetric G, positive definite or not
+// (steady Stokes: symmetric indefinite, Section 3.2 item 7).  The scaling
+// Ds G Ds is the (positive) Jacobi preconditioner.  Refinement passes: each
+// pass computes the FP64 residual r = bs - G64 y, runs MINRES in the working
+// precision on G x = r from x = 0 until its residual estimate falls below the
+// pass target, and adds x to y.  Three kernels per iteration; the Lanczos and
+// direction vectors rotate through three buffers each.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+struct ScaledIn {
+  const T* __restrict__ a;
+  T scale;
+  __device__ Vec<T, D> operator()(int64_t c) const {
+    Vec<T, D> x = ldv<T, D>(a, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) x.v[i] *= scale;
+    return x;
+  }
+};
+
+struct MState {
+  double beta[2], oldb[2], dbar[2], epsln[2], cs[2], sn[2], phibar[2], alfa[2];
+  int it[2];
+  int done;   // 0 running, 1 pass target reached, 2 converged (true residual), 3 limit, 4 breakdown, 5 non-finite
+  int iters;
+  double tres2, bnorm2, thr;
+  // parameters written by the host
+  double tol2, rep;
+  int maxit;
+};
+
+// init: r = bs - G64 y in FP64, r1 = r2 = (T) r, w = 0, x = 0;
+// partials: 0 = r.r (working precision), 1 = |S - G W|^2, 2 = |S|^2
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_hm_init(CgSys S, T* __restrict__ r1, T* __restrict__ r2, T* __restrict__ w0,
+                                                T* __restrict__ w1, MState* __restrict__ ms) {
+  const Part P = S.P;
+  const int lb = logical_block(P.nblk);
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  T* __restrict__ x = (T*)S.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<double, D> gy = spmv_row<D, double>(S.G64, S.cols, P.nf, f, Plain<double, D>{S.y});
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double b = S.bs[f * D + i], sq = S.dsq[f * D + i];
+      const double rs = b - gy.v[i];
+      const T rt = (T)rs;
+      r1[f * D + i] = rt;
+      r2[f * D + i] = rt;
+      w0[f * D + i] = T(0);
+      w1[f * D + i] = T(0);
+      x[f * D + i] = T(0);
+      acc[0] += (double)rt * (double)rt;
+      acc[1] += (sq * rs) * (sq * rs);
+      acc[2] += (sq * b) * (sq * b);
+    }
+  }
+  block_sum<3>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) S.Pa[(int64_t)m * P.nblk + lb] = acc[m];
+  if (lead()) {
+    ms->it[1] = 0;
+    ms->oldb[1] = 0.0;
+    ms->dbar[1] = 0.0;
+    ms->epsln[1] = 0.0;
+    ms->cs[1] = -1.0;
+    ms->sn[1] = 0.0;
+    ms->iters = 0;
+    ms->done = 0;
+  }
+}
+
+// MA: v = r2 / beta, y = G v - (beta / oldb) r1, partial v.y
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_hm_a(CgSys S, const T* __restrict__ r1, const T* __restrict__ r2,
+                                             T* __restrict__ v, T* __restrict__ y, MState* __restrict__ ms, int q) {
+  if (ms->done) return;
+  const Part P = S.P;
+  const int p = q ^ 1;
+  const int it = ms->it[p];
+  const bool first = it == 0;
+  double beta, oldb;
+  int done = 0;
+  if (first) {
+    const int fl[3] = {0, 1, 2};
+    double sv[3];
+    reduce_fields<3>(S.Pa, P.nblk, fl, sv);
+    beta = sqrt(sv[0]);
+    oldb = 0.0;
+    // pass target in the scaled norm: 0.1 of the tolerance, converted by the
+    // ratio of the two norms of the same residual, and at most a reduction
+    // by rep (precision of the working arithmetic)
+    const double ratio = sv[1] > 0.0 ? beta / sqrt(sv[1]) : 1.0;
+    const double thr = fmax(0.1 * sqrt(ms->tol2 * sv[2]) * ratio, ms->rep * beta);
+    if (sv[1] <= ms->tol2 * sv[2]) done = 2;
+    else if (!(beta > 0.0) || !isfinite(beta)) done = isfinite(beta) ? 4 : 5;
+    else if (it >= ms->maxit) done = 3;
+    if (lead()) {
+      ms->tres2 = sv[1];
+      ms->bnorm2 = sv[2];
+      ms->thr = thr;
+      ms->beta[p] = beta;
+      ms->phibar[p] = beta;
+    }
+  } else {
+    beta = ms->beta[p];
+    oldb = ms->oldb[p];
+    if (ms->phibar[p] <= ms->thr) done = 1;
+    else if (it >= ms->maxit) done = 3;
+  }
+  if (lead()) {
+    ms->it[q] = it + 1;
+    ms->iters = it;
+    if (done) ms->done = done;
+  }
+  if (done) return;
+  const T sb = (T)(1.0 / beta);
+  const T c1 = first ? T(0) : (T)(beta / oldb);
+  const int lb = logical_block(P.nblk);
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  const ScaledIn<T, D> in{r2, sb};
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    Vec<T, D> yy = spmv_row<D, T>((const T*)S.G, S.cols, P.nf, f, in);
+    const Vec<T, D> vv = in(f), rr = ldv<T, D>(r1, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      yy.v[i] -= c1 * rr.v[i];
+      acc[0] += (double)vv.v[i] * (double)yy.v[i];
+    }
+    stv<T, D>(v, f, vv);
+    stv<T, D>(y, f, yy);
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) S.Pb[lb] = acc[0];
+}
+
+// MB: alfa = v.y; y -= (alfa / beta) r2 (y becomes the next r2); partial y.y
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_hm_b(CgSys S, const T* __restrict__ r2, T* __restrict__ y,
+                                             MState* __restrict__ ms, int q) {
+  if (ms->done) return;
+  const Part P = S.P;
+  const int fl[1] = {0};
+  double sv[1];
+  reduce_fields<1>(S.Pb, P.nblk, fl, sv);
+  const double alfa = sv[0];
+  const T c2 = (T)(alfa / ms->beta[q ^ 1]);
+  const int lb = logical_block(P.nblk);
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  double acc[1] = {0.0};
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    Vec<T, D> yy = ldv<T, D>(y, f);
+    const Vec<T, D> rr = ldv<T, D>(r2, f);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      yy.v[i] -= c2 * rr.v[i];
+      acc[0] += (double)yy.v[i] * (double)yy.v[i];
+    }
+    stv<T, D>(y, f, yy);
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) S.Pc[lb] = acc[0];
+  if (lead()) ms->alfa[q] = alfa;
+}
+
+// MC: beta_new = |y|; plane rotations; w = (v - oldeps w1 - delta w2) / gamma; x += phi w
+template <int D, typename T>
+__global__ void __launch_bounds__(NT) k_hm_c(CgSys S, const T* __restrict__ v, const T* __restrict__ w1,
+                                             const T* __restrict__ w2, T* __restrict__ wn, MState* __restrict__ ms,
+                                             int q) {
+  if (ms->done) return;
+  const Part P = S.P;
+  const int fl[1] = {0};
+  double sv[1];
+  reduce_fields<1>(S.Pc, P.nblk, fl, sv);
+  const int p = q ^ 1;
+  if (!(sv[0] >= 0.0) || !isfinite(sv[0])) {
+    if (lead()) ms->done = isfinite(sv[0]) ? 4 : 5;
+    return;
+  }
+  const double beta = sqrt(sv[0]);
+  const double oldb = ms->beta[p];
+  const double alfa = ms->alfa[q];
+  const double cs = ms->cs[p], sn = ms->sn[p], dbar = ms->dbar[p], oldeps = ms->epsln[p];
+  const double delta = cs * dbar + sn * alfa;
+  const double gbar = sn * dbar - cs * alfa;
+  const double epsln = sn * beta;
+  const double dbar_n = -cs * beta;
+  const double gamma = fmax(hypot(gbar, beta), 1e-300);
+  const double cs_n = gbar / gamma, sn_n = beta / gamma;
+  const double phibar = ms->phibar[p];
+  const T phi = (T)(cs_n * phibar);
+  const T den = (T)(1.0 / gamma), te = (T)oldeps, td = (T)delta;
+  const int lb = logical_block(P.nblk);
+  const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  T* __restrict__ x = (T*)S.x;
+  for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+    const Vec<T, D> vv = ldv<T, D>(v, f), a = ldv<T, D>(w1, f), b = ldv<T, D>(w2, f);
+    Vec<T, D> xi = ldv<T, D>(x, f), wv;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      wv.v[i] = (vv.v[i] - te * a.v[i] - td * b.v[i]) * den;
+      xi.v[i] += phi * wv.v[i];
+    }
+    stv<T, D>(wn, f, wv);
+    stv<T, D>(x, f, xi);
+  }
+  if (lead()) {
+    ms->beta[q] = beta;
+    ms->oldb[q] = oldb;
+    ms->cs[q] = cs_n;
+    ms->sn[q] = sn_n;
+    ms->dbar[q] = dbar_n;
+    ms->epsln[q] = epsln;
+    ms->phibar[q] = sn_n * phibar;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // vector slots of the workspace
@@ -1067,6 +1296,8 @@ struct KWs {
   void* tvec[NVEC] = {};
   void* ttq = nullptr;
   double* tpart[2] = {};
+  MState* mst = nullptr;    // MINRES state (device) and its pinned copy
+  MState* mhst = nullptr;
   KState* tst = nullptr;
 };
 
@@ -1144,6 +1375,7 @@ CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
   S.q = w->vec[V_W0];
   S.Pa = w->part3[0];
   S.Pb = w->part3[1];
+  S.Pc = w->part3[2];
   S.st = st;
   S.F = prec == CR_FP32_IR ? (const void*)s->efo32 : (const void*)s->efo64;
   S.F64 = s->efo64;
@@ -1410,7 +1642,7 @@ struct Ctl {
       reason = NONFINITE;
       return true;
     }
-    if (ks.done == BREAKDOWN && !f32 && (final_eval || restarts >= 8)) {
+    if ((ks.done == BREAKDOWN || ks.done == DIVERGED) && !f32 && (final_eval || restarts >= 8)) {
       reason = BREAKDOWN;
       return true;
     }
@@ -1420,7 +1652,7 @@ struct Ctl {
     }
     bool stall = false;
     if (f32) {
-      stall = ks.done == STALL || ks.done == NONFINITE || (ks.done == BREAKDOWN && restarts >= 2) ||
+      stall = ks.done == STALL || ks.done == NONFINITE || ((ks.done == BREAKDOWN || ks.done == DIVERGED) && restarts >= 2) ||
               (ks.done == REPLACE && prev_true > 0.0 && ks.tres2 > 0.25 * prev_true);
       if (ks.done == REPLACE) prev_true = ks.tres2;
     }
@@ -1428,19 +1660,23 @@ struct Ctl {
     // recompute the residual in FP64.  When the FP32 iterations of a
     // non-symmetric method stall, their last correction is discarded: without
     // CG's monotone error reduction it may have grown.
-    if (ks.done != NONFINITE && !(stall && method != CR_PCG)) update(prec);
+    if (ks.done != NONFINITE && ks.done != DIVERGED && !(stall && method != CR_PCG)) update(prec);
     if (stall) {
       prec = CR_FP64;
       fell_back = true;
       residual(prec, 2);
-    } else if (ks.done == BREAKDOWN) {
+    } else if (ks.done == BREAKDOWN || ks.done == DIVERGED) {
+      // restart from the FP64 residual with a fresh direction; a diverged
+      // correction was discarded above
       residual(prec, 2);
       ++restarts;
     } else {
       residual(prec, ks.done == STALL ? 2 : 1);
     }
     ++reps;
-    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN) || reps > max_rep || iters >= maxit) final_eval = true;
+    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN && ks.done != DIVERGED) || reps > max_rep ||
+        iters >= maxit)
+      final_eval = true;
     return false;
   }
 
@@ -1473,11 +1709,150 @@ struct Ctl {
 
 }  // namespace
 
+namespace {
+
+template <int D, typename T>
+void enqueue_minres(cr_system* s, KWs* w, const CgSys& S, int k0, int niter) {
+  const dim3 grid(S.P.nblk), blk(NT);
+  T* R[3] = {(T*)w->vec[V_R0], (T*)w->vec[V_R1], (T*)w->vec[V_W0]};
+  T* W[3] = {(T*)w->vec[V_W1], (T*)w->vec[V_S0], (T*)w->vec[V_S1]};
+  T* v = (T*)w->vec[V_P];
+  for (int k = k0; k < k0 + niter; ++k) {
+    const int q = k & 1;
+    T* r1 = R[k % 3];
+    T* r2 = R[(k + 1) % 3];
+    T* y = R[(k + 2) % 3];
+    hipLaunchKernelGGL((k_hm_a<D, T>), grid, blk, 0, s->stream, S, r1, r2, v, y, w->mst, q);
+    hipLaunchKernelGGL((k_hm_b<D, T>), grid, blk, 0, s->stream, S, r2, y, w->mst, q);
+    hipLaunchKernelGGL((k_hm_c<D, T>), grid, blk, 0, s->stream, S, v, W[k % 3], W[(k + 1) % 3], W[(k + 2) % 3],
+                       w->mst, q);
+  }
+}
+
+// MINRES with FP64 refinement passes (see the kernels above).  A pass in FP32
+// that does not reduce the true residual by half switches the remaining passes
+// to FP64.
+cr_status run_minres(cr_system* s, KWs* w, const cr_solve_opts* o, cr_solve_info* info,
+                     std::chrono::steady_clock::time_point t_start) {
+  cr_status st = CR_OK;
+  if (!w->mst) {
+    w->mst = (MState*)dev_alloc(s, sizeof(MState));
+    if (!w->mst) return CR_E_NOMEM;
+    st = check_hip(hipHostMalloc((void**)&w->mhst, sizeof(MState), hipHostMallocDefault), "pinned MINRES state");
+    if (st != CR_OK) return st;
+  }
+  const double tol = o->tol > 0 ? o->tol : 1e-10;
+  const int maxit = o->maxit > 0 ? o->maxit : 1000000;
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 200;
+  const int blk = std::max(6, ((o->check_every > 0 ? o->check_every : 48) + 5) / 6 * 6);
+  int prec = o->precision;
+  const double rep_f32 = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+  int total = 0, fp32_total = 0, outer = 0, reason = 0;
+  double rel = -1.0, prev_t2 = -1.0;
+  bool fell_back = false;
+  if (!o->warm_start || !s->has_solution) {
+    st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, s->stream), "zero W");
+    if (st != CR_OK) return st;
+  }
+  for (;;) {
+    const bool last = outer >= max_outer || total >= maxit;
+    MState* h = w->mhst;
+    h->tol2 = tol * tol;
+    h->rep = prec == CR_FP32_IR ? rep_f32 : 0.0;
+    // an FP32 pass is capped: its recurrences lose accuracy before a long pass
+    // ends, and the next pass restarts from the FP64 residual
+    const int pass_cap = prec == CR_FP32_IR ? 25000 : maxit;
+    h->maxit = last ? 0 : std::min(maxit - total, pass_cap);
+    const size_t off = offsetof(MState, tol2);
+    st = check_hip(hipMemcpyAsync((char*)w->mst + off, (char*)h + off, sizeof(MState) - off, hipMemcpyHostToDevice,
+                                  s->stream), "MINRES parameters");
+    if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "MINRES parameters");
+    if (st != CR_OK) return st;
+    ++outer;
+    MState ks{};
+    dispatch(s->d, prec, [&](auto dc, auto tc) {
+      constexpr int D = decltype(dc)::value;
+      using T = decltype(tc);
+      const CgSys S = make_sys(s, w, prec, w->st);
+      hipLaunchKernelGGL((k_hm_init<D, T>), dim3(S.P.nblk), dim3(NT), 0, s->stream, S, (T*)w->vec[V_R0],
+                         (T*)w->vec[V_R1], (T*)w->vec[V_W1], (T*)w->vec[V_S0], w->mst);
+      int issued = 0;
+      const int max_blocks = h->maxit / blk + 2;
+      for (;;) {
+        enqueue_minres<D, T>(s, w, S, issued * blk, blk);
+        ++issued;
+        hipMemcpyAsync(w->mhst, w->mst, sizeof(MState), hipMemcpyDeviceToHost, s->stream);
+        st = check_hip(hipStreamSynchronize(s->stream), "MINRES poll");
+        if (st != CR_OK) break;
+        ks = *w->mhst;
+        if (ks.done || issued >= max_blocks) break;
+      }
+      if (st == CR_OK && ks.done != 2 && ks.done != 5)
+        hipLaunchKernelGGL((k_ir_update<D, T>), dim3(S.P.nblk), dim3(NT), 0, s->stream, S);
+    });
+    if (st != CR_OK) return st;
+    st = check_hip(hipGetLastError(), "MINRES launch");
+    if (st != CR_OK) return st;
+    total += ks.iters;
+    if (prec == CR_FP32_IR) fp32_total += ks.iters;
+    rel = ks.bnorm2 > 0 ? std::sqrt(ks.tres2 / ks.bnorm2) : std::sqrt(ks.tres2);
+    if (ks.done == 2) {
+      reason = 1;
+      break;
+    }
+    if (ks.done == 4 || ks.done == 5) {
+      reason = ks.done == 4 ? BREAKDOWN : NONFINITE;
+      break;
+    }
+    if (last || (prec != CR_FP32_IR && ks.done == 3)) {
+      reason = 3;
+      break;
+    }
+    if (prec == CR_FP32_IR && prev_t2 > 0.0 && ks.tres2 > 0.25 * prev_t2) {
+      prec = CR_FP64;
+      fell_back = true;
+    }
+    prev_t2 = ks.tres2;
+  }
+  st = check_hip(hipStreamSynchronize(s->stream), "MINRES sync");
+  if (st != CR_OK) return st;
+  s->has_solution = true;
+  if (info) {
+    info->iters = total;
+    info->outer_iters = outer;
+    info->rel_residual = rel;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    info->reason = reason;
+    info->fp32_iters = o->precision == CR_FP32_IR ? fp32_total : 0;
+    info->fp64_fallback = fell_back ? 1 : 0;
+  }
+  if (reason == 1) return CR_OK;
+  if (reason == BREAKDOWN) {
+    set_error("MINRES breakdown after %d iterations", total);
+    return CR_E_BREAKDOWN;
+  }
+  if (reason == NONFINITE) {
+    set_error("non-finite MINRES scalar after %d iterations", total);
+    return CR_E_NONFINITE;
+  }
+  set_error("MINRES: relative residual %.3e after %d iterations, %d passes", rel, total, outer);
+  return CR_E_NOCONV;
+}
+
+}  // namespace
+
 cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   auto t_start = std::chrono::steady_clock::now();
   KWs* w = nullptr;
   cr_status st = ensure_ws(s, w);
   if (st != CR_OK) return st;
+  if (o->method == CR_MINRES) {
+    if (o->operator_form == CR_OP_ELEMENT) {
+      set_error("MINRES applies the assembled G");
+      return CR_E_INVAL;
+    }
+    return run_minres(s, w, o, info, t_start);
+  }
   int op = 0;
   st = resolve_op(s, o, op);
   if (st != CR_OK) return st;
@@ -1554,6 +1929,7 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
   hp[0] = 1.0;
   KState ks{};
   ks.gam[1] = 1.0;
+  ks.rr_rep = 1.0;  // no divergence stop: r.r has not grown since the last evaluation
   ks.it[1] = 1;
   ks.it_rep = -1;
   ks.it_first = -1;
@@ -1637,6 +2013,7 @@ void free_krylov(cr_system* s) {
   if (w->t1) hipEventDestroy(w->t1);
   if (w->cap) hipStreamDestroy(w->cap);
   if (w->hst) hipHostFree(w->hst);
+  if (w->mhst) hipHostFree(w->mhst);
   delete w;
   s->kws = nullptr;
 }

@@ -200,6 +200,38 @@ def test_c4_full_size_certificate(gpu):
     s.close()
 
 
+def test_steady_stokes_full_size_certificate(gpu):
+    """Steady Stokes (mu = 0, E_K from the M1/M2 partition, symmetric indefinite
+    G) on 256x256x2: MINRES in FP64 to 1e-9 (FP32 passes restart too often to
+    pay off here), and the same certificate as the Navier-Stokes step
+    (host-recomputed residual, copy mismatch, sampled coupled rows, element
+    divergence)."""
+    w = wl.square(256, mu=0.0, nu=1.0, jitter=0.2, seed=3, quad=2)
+    s = gpu.System(w["coords"], w["elems"], 0.0, 1.0)
+    s.eliminate(dev(w["fbar"]))
+    info = s.solve("minres", "fp64", tol=1e-9, maxit=600000)
+    print("steady Stokes 256x256 MINRES:", info, flush=True)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-9
+    U, Pk, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+    G, S = s.export_G()
+    Wv = s.export_W().ravel()
+    r = np.linalg.norm(S - G @ Wv)
+    assert r <= 1.000001e-9 * np.linalg.norm(S)
+    assert abs(J.item() - r) <= 1e-6 * r + 1e-12 * np.linalg.norm(S)
+    P = cr.make_problem(w["coords"], w["elems"], 0.0, 1.0, w["fbar"])
+    faces = np.random.default_rng(4).choice(P.mesh.nf, 300, replace=False)
+    Uh, Ph = U.cpu().numpy(), Pk.cpu().numpy()
+    res, div = coupled_rows(P, Uh, Ph, faces)
+    Amax = max(np.abs(P.A[k]).sum(axis=1).max() for f in faces for k in P.mesh.face_elems[f])
+    Dmax = np.abs(P.D).max()
+    assert np.abs(res).max() <= 10 * Amax * J.item()
+    others = np.delete(div, P.k0)
+    assert np.abs(others).max() <= 10 * Dmax * J.item() * (P.d + 1)
+    assert abs(div[P.k0]) <= 10 * Dmax * J.item() * (np.sqrt(P.mesh.nf * P.d) + P.d + 1)
+    s.close()
+
+
 def test_multistep_update_rhs_parity(gpu):
     """Three backward-Euler steps with cr_update_rhs (same G, u_prev = previous U)
     against the oracle's coupled solves with the same previous velocity."""

@@ -182,6 +182,45 @@ def test_operator_forms_agree(gpu, name):
     st.close()
 
 
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+@pytest.mark.parametrize("name", ["steady10", "square16", "cube3"])
+def test_minres_solution_parity(gpu, name, precision, bar):
+    """MINRES on the symmetric G: indefinite (steady Stokes) and definite."""
+    case = make_case(name)
+    print(f"case {name} {precision} minres", flush=True)
+    P = oracle_problem(case)
+    U_o, P_o = cr.solve_coupled(P)
+    s = gpu_system(gpu, case)
+    info = s.solve("minres", precision, tol=1e-13, check_every=12, maxit=200000)
+    assert info["rel_residual"] <= 1e-13
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    assert relerr(U.cpu().numpy(), U_o) <= bar
+    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    with pytest.raises(gpu.CRError):
+        s.solve("minres", "fp64", tol=1e-10, operator="element")
+    s.close()
+
+
+@pytest.mark.parametrize("operator", ["element", "assembled"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_kernel_timing_runs_the_full_kernel(gpu, precision, operator):
+    """cr_time_spmv launches the dominant kernel on a scratch state that never
+    stops early: its launch time stays above the bytes it must move at the HBM
+    peak (8 TB/s), and the resident solution is untouched.  512x512x2, so that
+    the bytes of one launch take far longer than an early return."""
+    coords, elems = synth.square_mesh(512, jitter=0.2, seed=11)
+    fbar = np.random.default_rng(11).normal(size=(len(elems), 2))
+    s = gpu.System(coords, elems, 1000.0, 1.0)
+    s.eliminate(dev(fbar))
+    s.solve("pcg", "fp32_ir", tol=1e-6)
+    W0 = s.export_W()
+    ms, by = s.time_spmv(precision, reps=20, operator=operator)
+    assert by / (ms * 1e-3) < 8e12
+    assert np.array_equal(s.export_W(), W0)
+    s.close()
+
+
 def test_graph_and_plain_launches_agree(gpu):
     """The captured-graph replay and plain launches run the same kernels: same iterates."""
     case = make_case("jitter12")
