@@ -184,9 +184,10 @@ def main():
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--coupled-maxit", type=int, default=60000)
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="time-step requests of the serving run (0: skip; the full workload has 2000)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="session arrivals per second (Poisson)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="time-step requests of the serving run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.5,
+                    help="session arrivals per second (Poisson); 2.5 offers about 26 requests/s, below saturation")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0, help="device-memory budget for admission")
     ap.add_argument("--serve-precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     ap.add_argument("--no-other", action="store_true",

@@ -237,7 +237,9 @@ cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t operator_form,
  * side set by cr_eliminate / cr_update_rhs) and leave when finished; their
  * FP64 residual replacements are serviced between iteration blocks.  All
  * systems of a batch live on the batch's stream and have the same dimension.
- * Not thread-safe.  The batch owns only its own small tables (hipMalloc). */
+ * Systems of a batch use one operator form (the element form for CG on
+ * transient Stokes by default).  Not thread-safe.  The batch owns only its own
+ * small tables (hipMalloc) and the captured graph. */
 typedef struct cr_batch cr_batch;
 
 /* max_systems: capacity (1..4096). */
@@ -251,6 +253,9 @@ cr_status cr_batch_add(cr_batch* b, cr_system* sys, const cr_solve_opts* opts);
 
 /* Run n_iters iterations (rounded up to even) of every active system in shared
  * launches, then service stops (replacement, restart, FP64 fallback, finish).
+ * The iteration block is captured as a hipGraph once per launch shape (block
+ * counts of the active systems and n_iters) and replayed; joins and leaves
+ * that keep the shape only rewrite the device tables it reads.
  * *n_finished = systems that finished in this call.  Synchronises. */
 cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished);
 

@@ -2064,6 +2064,12 @@ struct cr_batch {
   int* hmapE[2] = {};
   int nblocks[2] = {};
   int nblocksE[2] = {};
+  // the iteration block of an advance, captured once per launch shape (block
+  // counts and iteration count) and replayed; membership changes that keep
+  // the shape only rewrite the device tables the graph reads
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int exec_key[6] = {-1, -1, -1, -1, -1, -1};
   int64_t map_cap = 0;
   bool dirty = true;
 };
@@ -2232,7 +2238,7 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
   const int npairs = (n_iters + 1) / 2;
   bool any = false;
   for (int pi = 0; pi < 2; ++pi) any = any || b->nblocks[pi] > 0;
-  if (any) {
+  auto enqueue = [&](hipStream_t stream) {
     for (int k = 0; k < npairs; ++k)
       for (int par = 0; par < 2; ++par)
         for (int pi = 0; pi < 2; ++pi) {
@@ -2242,18 +2248,42 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
             constexpr int OP = decltype(oc)::value;
             using T = decltype(tc);
             if constexpr (OP == 1) {
-              hipLaunchKernelGGL((k_ec1_b<D, T>), dim3(b->nblocksE[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+              hipLaunchKernelGGL((k_ec1_b<D, T>), dim3(b->nblocksE[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmapE[pi], par);
-              hipLaunchKernelGGL((k_ec2_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+              hipLaunchKernelGGL((k_ec2_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmap[pi], par);
             } else {
-              hipLaunchKernelGGL((k_cg_spmv_b<D, T, 0>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+              hipLaunchKernelGGL((k_cg_spmv_b<D, T, 0>), dim3(b->nblocks[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmap[pi], par);
-              hipLaunchKernelGGL((k_cg_update_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, b->stream, b->dtab[pi],
+              hipLaunchKernelGGL((k_cg_update_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmap[pi], par);
             }
           });
         }
+  };
+  if (any) {
+    const int key[6] = {b->nblocks[0], b->nblocks[1], b->nblocksE[0], b->nblocksE[1], npairs, b->op};
+    if (!b->exec || !std::equal(key, key + 6, b->exec_key)) {
+      if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+      }
+      if (!b->cap) st = check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "batch capture stream");
+      hipGraph_t g = nullptr;
+      if (st == CR_OK) st = check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "batch capture");
+      if (st == CR_OK) {
+        enqueue(b->cap);
+        const hipError_t le = hipGetLastError();
+        st = check_hip(hipStreamEndCapture(b->cap, &g), "batch capture");
+        if (st == CR_OK) st = check_hip(le, "batch captured launch");
+        if (st == CR_OK) st = check_hip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "batch graph");
+        if (g) hipGraphDestroy(g);
+      }
+      if (st != CR_OK) return st;
+      std::copy(key, key + 6, b->exec_key);
+    }
+    st = check_hip(hipGraphLaunch(b->exec, b->stream), "batch graph launch");
+    if (st != CR_OK) return st;
   }
   st = check_hip(hipMemcpyAsync(b->hst, b->dst, sizeof(KState) * b->max_sys, hipMemcpyDeviceToHost, b->stream),
                  "batch state");
@@ -2327,6 +2357,8 @@ cr_status cr_batch_count(const cr_batch* b, int32_t* n_active, int32_t* n_finish
 void cr_batch_destroy(cr_batch* b) {
   if (!b) return;
   if (b->stream || b->dst) hipStreamSynchronize(b->stream);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->cap) hipStreamDestroy(b->cap);
   if (b->dst) hipFree(b->dst);
   if (b->hst) hipHostFree(b->hst);
   for (int pi = 0; pi < 2; ++pi) {

@@ -29,9 +29,10 @@ from ._binding import Batch, System
 
 # device bytes per element of a resident 2D system with its Krylov workspace
 # (element data ~510 B including the operator factors and the per-element Krylov
-# contributions, per-face data and ten Krylov vectors ~496 B per face,
-# about 1.5 faces per element), used to decide admission before the system exists
-BYTES_PER_ELEMENT_2D = 1300
+# contributions; per-face data ~370 B and twelve Krylov vectors ~190 B per
+# face, about 1.5 faces per element; a margin for the recovery buffers), used
+# to decide admission before the system exists
+BYTES_PER_ELEMENT_2D = 1450
 
 
 class Session:
