@@ -144,6 +144,8 @@ typedef struct {
   int32_t use_graph;   /* 1: replay the iteration block as a captured hipGraph */
   int32_t warm_start;  /* 1: start from the resident W of the previous solve, 0: from W = 0 */
   int32_t operator_form; /* CR_OP_AUTO, CR_OP_ASSEMBLED or CR_OP_ELEMENT */
+  int32_t coarse;      /* 0: element-form CG adds the coarse correction where the mesh
+                          has aggregates (meshes of at least 8192 elements); 1: Jacobi only */
 } cr_solve_opts;
 
 typedef struct {

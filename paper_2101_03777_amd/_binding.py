@@ -60,7 +60,8 @@ class Allocator(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("maxit", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32), ("warm_start", C.c_int32), ("operator_form", C.c_int32)]
+                ("use_graph", C.c_int32), ("warm_start", C.c_int32), ("operator_form", C.c_int32),
+                ("coarse", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -192,11 +193,11 @@ class TorchAllocator:
 
 
 def solve_opts(method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-               check_every=0, graph=True, warm_start=False, operator="auto"):
+               check_every=0, graph=True, warm_start=False, operator="auto", coarse=True):
     return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB, "bicgstab2": CR_BICGSTAB2, "minres": CR_MINRES}[method],
                      {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
                      int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)),
-                     _OPFORM[operator])
+                     _OPFORM[operator], 0 if coarse else 1)
 
 
 def info_dict(st, info):
@@ -312,9 +313,9 @@ class System:
         _check(self.lib.cr_update_rhs(self.h, _ptr(f), _ptr(up)))
 
     def solve(self, method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-              check_every=0, graph=True, warm_start=False, raise_on_error=True, operator="auto"):
+              check_every=0, graph=True, warm_start=False, raise_on_error=True, operator="auto", coarse=True):
         o = solve_opts(method, precision, tol, inner_tol, maxit, max_outer, check_every, graph, warm_start,
-                       operator)
+                       operator, coarse)
         info = SolveInfo()
         st = self.lib.cr_solve(self.h, C.byref(o), C.byref(info))
         out = info_dict(st, info)
@@ -334,7 +335,7 @@ class System:
         torch = self._torch
         U = torch.empty((self.n_int_faces, self.dim), dtype=torch.float64, device="cuda")
         P = torch.empty((self.n_elements,), dtype=torch.float64, device="cuda")
-        o = SolveOpts(0, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0, CR_OP_AUTO)
+        o = SolveOpts(0, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0, CR_OP_AUTO, 0)
         info = SolveInfo()
         st = self.lib.cr_coupled_solve(self.h, C.byref(o), C.byref(info), _ptr(U), _ptr(P))
         if raise_on_error:

@@ -88,6 +88,87 @@ cr_status build(cr_system* s) {
 
 using namespace crh;
 
+namespace crh {
+
+// Host part of the coarse-correction setup: the aggregate of each face
+// (internal order) and, for every nonzero (a, b) of E = Z^t G' Z, the list of
+// element entries (element k, local faces j and l with faces in aggregates a
+// and b) that sum to it, grouped by a counting sort on the pair key.
+cr_status setup_coarse(cr_system* s, const std::vector<int32_t>& eface, std::vector<uint32_t>& eflags) {
+  const Topology& t = s->topo;
+  const int d1 = t.d + 1;
+  const int64_t ne = t.ne;
+  const int m = t.nagg;
+  std::vector<int64_t> count((size_t)m * m + 1, 0);
+  for (int64_t k = 0; k < ne; ++k)
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      for (int l = 0; l < d1; ++l) {
+        const int32_t fl = eface[(size_t)l * ne + k];
+        if (fl < 0) continue;
+        count[(size_t)t.face_agg[fj] * m + t.face_agg[fl] + 1]++;
+      }
+    }
+  std::vector<int32_t> key, ptr(1, 0);
+  std::vector<int64_t> start((size_t)m * m, -1);
+  int64_t total = 0;
+  for (int64_t q = 0; q < (int64_t)m * m; ++q) {
+    if (!count[q + 1]) continue;
+    start[q] = total;
+    total += count[q + 1];
+    key.push_back((int32_t)q);
+    ptr.push_back((int32_t)total);
+  }
+  if (total >= INT32_MAX) {
+    set_error("coarse correction: too many element entries");
+    return CR_E_INVAL;
+  }
+  std::vector<int32_t> ent((size_t)total);
+  for (int64_t k = 0; k < ne; ++k)
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      for (int l = 0; l < d1; ++l) {
+        const int32_t fl = eface[(size_t)l * ne + k];
+        if (fl < 0) continue;
+        const int64_t q = (int64_t)t.face_agg[fj] * m + t.face_agg[fl];
+        ent[(size_t)start[q]++] = (int32_t)(k * 16 + j * 4 + l);
+      }
+    }
+  // elements whose interior faces lie in more than one aggregate
+  int64_t nb = 0;
+  for (int64_t k = 0; k < ne; ++k) {
+    int a0 = -1;
+    bool multi = false;
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      if (a0 < 0) a0 = t.face_agg[fj];
+      else if (t.face_agg[fj] != a0) multi = true;
+    }
+    if (multi) {
+      eflags[k] |= F_AGGB;
+      ++nb;
+    }
+  }
+  s->nbnd = nb;
+  s->nagg = m;
+  s->npairs = (int32_t)key.size();
+  cr_status st = check_hip(hipMemcpy(s->eflags, eflags.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice),
+                           "element flags");
+  if (st == CR_OK) st = upload(s, s->fagg, t.face_agg);
+  if (st == CR_OK) st = upload(s, s->pair_ptr, ptr);
+  if (st == CR_OK) st = upload(s, s->pair_key, key);
+  if (st == CR_OK) st = upload(s, s->pair_ent, ent);
+  if (st == CR_OK) st = alloc_n(s, s->Ec, (size_t)m * m);
+  if (st == CR_OK) st = alloc_n(s, s->Einv, (size_t)m * m);
+  if (st == CR_OK) st = alloc_n(s, s->zy32, (size_t)t.nf * t.d);
+  return st;
+}
+
+}  // namespace crh
+
 extern "C" {
 
 const char* cr_last_error(void) { return last_error_str(); }
@@ -124,7 +205,8 @@ cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t
   cr_status st = check_params(mesh, params);
   if (st != CR_OK) return st;
   Topology t;
-  st = build_topology(mesh, params->renumber, params->mu == 0.0, t);
+  st = build_topology(mesh, params->renumber, params->mu == 0.0,
+                      params->mu > 0.0 && params->problem == CR_STOKES, t);
   if (st != CR_OK) return st;
   if (n_int_faces) *n_int_faces = t.nf;
   if (perm) std::copy(t.face_perm.begin(), t.face_perm.end(), perm);
@@ -153,7 +235,8 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
     s->alloc = *alloc;
     s->has_alloc = true;
   }
-  st = build_topology(mesh, params->renumber, params->mu == 0.0, s->topo);
+  st = build_topology(mesh, params->renumber, params->mu == 0.0,
+                      params->mu > 0.0 && params->problem == CR_STOKES, s->topo);
   if (st == CR_OK) st = build(s);
   if (st == CR_OK) st = check_hip(hipGetDevice(&s->device), "hipGetDevice");
   if (st != CR_OK) {
@@ -229,6 +312,7 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
     if (st == CR_OK) st = alloc_n(s, s->bs1, nvec);
     if (st == CR_OK) st = alloc_n(s, s->zy, nvec);
     if (st == CR_OK) st = alloc_n(s, s->k0t, (size_t)1);
+    if (st == CR_OK && t.nagg > 0) st = setup_coarse(s, eface, eflags);
   }
   if (st == CR_OK) st = alloc_n(s, s->bs, nvec);
   if (st == CR_OK) st = alloc_n(s, s->y, nvec);

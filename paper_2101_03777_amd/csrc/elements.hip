@@ -798,6 +798,143 @@ __global__ void k_k0_gauge(int64_t ne, int64_t k, const double* __restrict__ pac
   t[0] = -p * F.invB;
 }
 
+// ---------------------------------------------------------------------------
+// Coarse correction of the element-form CG.  Columns of Z: the null vector z of
+// G' restricted to the faces of one aggregate of elements (a constant pressure
+// on the aggregate, seen through the faces it owns).  E = Z^t G' Z is summed
+// element by element: entry (a, b) collects, for every element K and local
+// faces j, l with faces in aggregates a and b, z_j^t G'_K[j, l] z_l =
+// Sh_jl (z_j . z_l) - (Vh_j . z_j)(Vh_l . z_l) in the scaled variables.  One
+// wavefront per nonzero, lanes over its entry list, a fixed-order reduction.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_E(int32_t npairs, const int32_t* __restrict__ pair_ptr,
+                                                  const int32_t* __restrict__ pair_key,
+                                                  const int32_t* __restrict__ pair_ent, int64_t ne,
+                                                  const double* __restrict__ F, const int32_t* __restrict__ egat,
+                                                  const double* __restrict__ zy, double* __restrict__ E) {
+  using L = EfoLayout<D>;
+  const int w = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= npairs) return;
+  double acc = 0.0;
+  for (int32_t e = pair_ptr[w] + lane; e < pair_ptr[w + 1]; e += 64) {
+    const int32_t code = pair_ent[e];
+    const int64_t k = code >> 4;
+    const int j = (code >> 2) & 3, l = code & 3;
+    const int64_t fj = egat[(int64_t)j * ne + k], fl = egat[(int64_t)l * ne + k];
+    double zz = 0.0, vj = 0.0, vl = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double a = zy[fj * D + i], b = zy[fl * D + i];
+      zz += a * b;
+      vj += F[(int64_t)L::vh(j, i) * ne + k] * a;
+      vl += F[(int64_t)L::vh(l, i) * ne + k] * b;
+    }
+    acc += F[(int64_t)L::sym(j, l) * ne + k] * zz - vj * vl;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) E[pair_key[w]] = acc;
+}
+
+// Inverse of E + s 1 1^t (s = trace(E) / m; E is positive semi-definite with
+// null vector 1, since the columns of Z sum to z) by Gauss-Jordan without
+// pivoting, one workgroup; E is overwritten.  A pivot that is not positive
+// leaves a zero inverse (the correction then does nothing).
+__global__ void __launch_bounds__(1024) k_coarse_inv(int m, double* __restrict__ E, double* __restrict__ Einv) {
+  __shared__ double fac[1024];
+  __shared__ double s_tr;
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < m; ++i) tr += E[(int64_t)i * m + i];
+    s_tr = tr / m;
+    bad = 0;
+  }
+  __syncthreads();
+  for (int64_t q = t; q < (int64_t)m * m; q += 1024) {
+    E[q] += s_tr;
+    Einv[q] = (q / m == q % m) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const double piv = E[(int64_t)k * m + k];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (t == 0) bad = 1;
+      break;
+    }
+    for (int i = t; i < m; i += 1024) fac[i] = E[(int64_t)i * m + k];
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int c = t; c < 2 * m; c += 1024) {
+      double* row = c < m ? E + (int64_t)k * m + c : Einv + (int64_t)k * m + (c - m);
+      *row *= ip;
+    }
+    __syncthreads();
+    for (int64_t q = t; q < (int64_t)m * 2 * m; q += 1024) {
+      const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
+      if (i == k) continue;
+      const double pk = c < m ? E[(int64_t)k * m + c] : Einv[(int64_t)k * m + (c - m)];
+      double* x = c < m ? E + (int64_t)i * m + c : Einv + (int64_t)i * m + (c - m);
+      *x -= fac[i] * pk;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (bad)
+    for (int64_t q = t; q < (int64_t)m * m; q += 1024) Einv[q] = 0.0;
+}
+
+// The same inverse for m <= 128 with E held in LDS (m^2 doubles, at most
+// 128 KB) and inverted in place: for each pivot k, row k is divided by the
+// pivot (its diagonal entry becoming 1 / pivot) and eliminated from every
+// other row (their column-k entries becoming -factor / pivot).
+__global__ void __launch_bounds__(1024) k_coarse_inv_lds(int m, const double* __restrict__ E,
+                                                         double* __restrict__ Einv) {
+  extern __shared__ double A[];
+  __shared__ double fac[128];
+  __shared__ double s_tr;
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < m; ++i) tr += E[(int64_t)i * m + i];
+    s_tr = tr / m;
+    bad = 0;
+  }
+  __syncthreads();
+  for (int q = t; q < m * m; q += 1024) A[q] = E[q] + s_tr;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const double piv = A[k * m + k];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (t == 0) bad = 1;
+      break;
+    }
+    if (t < m) fac[t] = A[t * m + k];
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    if (t < m) A[k * m + t] = (t == k ? 1.0 : A[k * m + t]) * ip;
+    __syncthreads();
+    for (int q = t; q < m * m; q += 1024) {
+      const int i = q / m, c = q % m;
+      if (i == k) continue;
+      const double rk = A[k * m + c];
+      A[q] = (c == k ? 0.0 : A[q]) - fac[i] * rk;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int q = t; q < m * m; q += 1024) Einv[q] = bad ? 0.0 : A[q];
+}
+
+__global__ void __launch_bounds__(BS) k_cast_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 __global__ void __launch_bounds__(BS) k_gauge_axpy(int64_t n, const double* __restrict__ t,
                                                    const double* __restrict__ zy, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -1096,6 +1233,31 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
                          s->dsq, s->zy);
     st = k0_rhs(s);
     if (st != CR_OK) return st;
+    if (s->nagg > 0) {
+      const int m = s->nagg;
+      st = check_hip(hipMemsetAsync(s->Ec, 0, sizeof(double) * m * m, s->stream), "coarse E");
+      if (st != CR_OK) return st;
+      const unsigned gp = (unsigned)(((int64_t)s->npairs * 64 + 255) / 256);
+      if (d == 2)
+        hipLaunchKernelGGL(k_coarse_E<2>, dim3(gp), dim3(256), 0, s->stream, s->npairs, s->pair_ptr, s->pair_key,
+                           s->pair_ent, s->ne, s->efo64, s->egat, s->zy, s->Ec);
+      else
+        hipLaunchKernelGGL(k_coarse_E<3>, dim3(gp), dim3(256), 0, s->stream, s->npairs, s->pair_ptr, s->pair_key,
+                           s->pair_ent, s->ne, s->efo64, s->egat, s->zy, s->Ec);
+      if (m <= 128) {
+        st = check_hip(hipFuncSetAttribute((const void*)k_coarse_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(sizeof(double) * 128 * 128)),
+                       "coarse inverse LDS size");
+        if (st != CR_OK) return st;
+        hipLaunchKernelGGL(k_coarse_inv_lds, dim3(1), dim3(1024), sizeof(double) * m * m, s->stream, m, s->Ec, s->Einv);
+      } else {
+        hipLaunchKernelGGL(k_coarse_inv, dim3(1), dim3(1024), 0, s->stream, m, s->Ec, s->Einv);
+      }
+      const int64_t n = s->nf * d;
+      hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(n, BS)), dim3(BS), 0, s->stream, n, s->zy, s->zy32);
+      st = check_hip(hipGetLastError(), "coarse setup");
+      if (st != CR_OK) return st;
+    }
   }
   st = read_err(s, "cr_eliminate");
   if (st != CR_OK) return st;

@@ -35,16 +35,23 @@ struct Topology {
   std::vector<int32_t> elem_perm;      // caller -> internal
   std::vector<int32_t> elem_iperm;     // internal -> caller
   int64_t bw_internal = 0, bw_canonical = 0;
+  // aggregates of elements for the coarse correction (0: none); face_agg is in
+  // internal face order, and faces of one aggregate are contiguous there
+  int32_t nagg = 0;
+  std::vector<int32_t> face_agg;
 };
 
 // Returns CR_OK or an error (message set).  need_m1: compute the M1/M2 split.
-cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, Topology& t);
+// aggregate: group faces by element aggregates (the coarse correction of CG on
+// transient Stokes); other problems keep the plain RCM order.
+cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, bool aggregate, Topology& t);
 
 // element flag bits (device eflags)
 constexpr uint32_t F_INTERIOR0 = 1u;        // bit j: local face j interior
 constexpr uint32_t F_NEG0 = 1u << 8;        // bit 8+j: C_K = -1 on local face j
 constexpr uint32_t F_K0 = 1u << 16;         // pinned pressure element
 constexpr uint32_t F_M1 = 1u << 17;         // element in M1 (E_K = -lambda I)
+constexpr uint32_t F_AGGB = 1u << 18;       // interior faces in more than one aggregate
 
 constexpr int NT = 256;                     // threads per block of the row kernels
 
@@ -96,6 +103,20 @@ struct cr_system {
   double* zy = nullptr;        // [nf*d]
   double* k0t = nullptr;       // [1]
   int64_t k0i = 0;             // internal id of K0
+  // coarse correction of the element-form CG (nagg > 0): aggregate of each
+  // face, the (element, j, l) entries of each nonzero of E = Z^t G' Z grouped
+  // by (row, column) pair, E and its inverse (dense, nagg x nagg), and the
+  // null-vector columns z in FP32
+  int32_t nagg = 0;
+  int32_t npairs = 0;
+  int32_t* fagg = nullptr;     // [nf]
+  int32_t* pair_ptr = nullptr; // [npairs + 1]
+  int32_t* pair_key = nullptr; // [npairs] row * nagg + column
+  int32_t* pair_ent = nullptr; // [entries] k * 16 + j * 4 + l
+  double* Ec = nullptr;        // [nagg * nagg]
+  double* Einv = nullptr;      // [nagg * nagg]
+  float* zy32 = nullptr;       // [nf * d]
+  int64_t nbnd = 0;            // elements with F_AGGB
   double* bs = nullptr;        // [nf*d] S / dsq
   double* y = nullptr;         // [nf*d] dsq * W (resident solution, scaled)
   double* fbar = nullptr;      // [ne*d] internal element order

@@ -76,6 +76,7 @@ namespace crh {
 namespace {
 
 constexpr int NFIELD = 6;  // fields of a partial record
+constexpr int KMAX = 4;    // aggregates a face block may touch (coarse restriction)
 
 // done codes
 enum : int { RUNNING = 0, REPLACE = 1, CONVERGED = 2, LIMIT = 3, BREAKDOWN = 4, NONFINITE = 5, STALL = 6, DIVERGED = 7 };
@@ -102,6 +103,7 @@ struct KState {
   // kernel and read by later ones: rho after the even and the odd BiCG step,
   // beta and alpha of both steps, omega_2 of the minimal-residual step
   double rho_a[2], beta1[2], alpha1[2], rho_b[2], beta2[2], alpha2[2], omega2[2];
+  double bet[2];  // CG beta of the iteration with each parity
   // parameters written by the host
   double rep_tol2, tol2;
   int maxit;
@@ -140,6 +142,19 @@ struct CgSys {
   void* tq;                  // [ne][d+1][d] element contributions w_K
   const uint32_t* eflags;
   const double* bs1;         // scaled right-hand side of the element form
+  // coarse correction (nagg > 0): M^-1 = I + Z E^-1 Z^t
+  int nagg;
+  int boffC;                 // first coarse block of this system in a batched grid
+  const int32_t* fagg;       // [nf] aggregate of each face
+  const void* zT;            // [nf*d] columns of Z in the iteration precision
+  double* Pr;                // [nblk][KMAX] restriction partials of face blocks
+  const int32_t* ablk;       // [nblk] first aggregate of each face block
+  const int32_t* bfa;        // [nagg] first face block of each aggregate
+  const int32_t* bla;        // [nagg] last face block of each aggregate
+  const double* Einv;        // [nagg*nagg]
+  double* cvec;              // [nagg] c = Z^t r
+  double* mu;                // [nagg] E^-1 c
+  double* M2;                // [2][nagg] coarse part m of the direction, by parity
   const void* F;             // factors of the iteration precision
   const double* F64;         // FP64 factors (residual)
   const int32_t* egat;
@@ -158,6 +173,19 @@ __device__ __forceinline__ Vec<T, D> op_row(const CgSys& S, const void* G, const
 }
 
 __device__ __forceinline__ int logical_of(int b, int nblk) { return (b & 7) * (nblk >> 3) + (b >> 3); }
+
+// restriction partials of one face row: z_f . r_f into the slot of its aggregate
+template <int D, typename T>
+__device__ __forceinline__ void restrict_row(const CgSys& S, int64_t f, int a0, const Vec<T, D>& r,
+                                             double (&acc)[KMAX]) {
+  const Vec<T, D> z = ldv<T, D>((const T*)S.zT, f);
+  double zr = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) zr += (double)z.v[i] * (double)r.v[i];
+  const int a = S.fagg[f] - a0;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) acc[k] += a == k ? zr : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // Residual (replacement) kernel: r_s = bs - G64 y in FP64; r = (T) r_s; x = 0.
@@ -180,6 +208,9 @@ __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __re
   T* __restrict__ r = (T*)S.r;
   T* __restrict__ x = (T*)S.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool crs = OP == 1 && S.nagg > 0;
+  const int a0 = crs ? S.ablk[lb] : 0;
+  double racc[KMAX] = {};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
     Vec<double, D> w = op_row<D, double, OP>(S, S.G64, S.F64, f, Plain<double, D>{S.y});
     Vec<T, D> rt, zero, rh;
@@ -196,6 +227,7 @@ __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __re
     }
     stv<T, D>(r, f, rt);
     stv<T, D>(x, f, zero);
+    if (crs) restrict_row<D, T>(S, f, a0, rt, racc);
     if (bicg) {
       if (init)
         rh = rt;
@@ -215,6 +247,12 @@ __device__ __forceinline__ void ir_residual_body(const CgSys& S, int lb, T* __re
     S.Pa[(int64_t)1 * P.nblk + lb] = acc[1];
     S.Pa[(int64_t)2 * P.nblk + lb] = acc[2];
     S.Pa[(int64_t)3 * P.nblk + lb] = acc[3];
+  }
+  if (crs) {
+    block_sum<KMAX>(racc);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) S.Pr[(int64_t)lb * KMAX + k] = racc[k];
   }
   if (threadIdx.x == 0 && lb == 0) {
     if (mode == 0) {
@@ -302,7 +340,8 @@ __device__ __forceinline__ void record_decision(KState* st, const Decision& d, b
 // partials Pa, applies the stopping logic (the workgroup with logical index 0
 // records it) and returns false if the iteration does not run; else sets beta
 // and whether this iteration starts a new direction.
-__device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f32, double& beta, bool& first) {
+__device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f32, double& beta, bool& first,
+                                        double coarse = 0.0) {
   KState* st = S.st;
   if (st->done) return false;
   const int it = st->it[par ^ 1];
@@ -323,17 +362,25 @@ __device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f3
     rr = v[0];
   }
   const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, f32);
-  if (threadIdx.x == 0 && lb == 0) {
-    record_decision(st, dec, fresh, it, rr, tres2, snorm2);
-    if (!dec.done) {
-      st->gam[par] = rr;
-      st->it[par] = it + 1;
-      st->nrun += 1;
-    }
+  if (threadIdx.x == 0 && lb == 0) record_decision(st, dec, fresh, it, rr, tres2, snorm2);
+  // rho = r . M^-1 r = r.r + c . E^-1 c with the coarse correction
+  beta = first ? 0.0 : (rr + coarse) / st->gam[par ^ 1];
+  if (threadIdx.x == 0 && lb == 0 && !dec.done) {
+    st->gam[par] = rr + coarse;
+    st->bet[par] = beta;
+    st->it[par] = it + 1;
+    st->nrun += 1;
   }
   if (dec.done) return false;
-  beta = first ? 0.0 : rr / st->gam[par ^ 1];
   return true;
+}
+
+// c . mu over the aggregates, summed in the same order by every workgroup
+__device__ __forceinline__ double coarse_dot(const CgSys& S) {
+  double v[1] = {0.0};
+  for (int a = threadIdx.x; a < S.nagg; a += NT) v[0] += S.cvec[a] * S.mu[a];
+  block_sum<1>(v);
+  return v[0];
 }
 
 template <int D, typename T, int OP>
@@ -471,7 +518,9 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   constexpr int N = L::N;
   double beta_d;
   bool first;
-  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first)) return;
+  if (S.st->done) return;
+  const double cd = S.nagg > 0 ? coarse_dot(S) : 0.0;
+  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, cd)) return;
   const T beta = (T)beta_d;
   const T* __restrict__ F = (const T*)S.F;
   const T* __restrict__ r = (const T*)S.r;
@@ -481,18 +530,35 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   const int64_t ne = S.ne;
   const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(ne, lo + S.PE.chunk);
   double acc[1] = {0.0};
+  const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
   for (int64_t K = lo + threadIdx.x; K < hi; K += NT) {
     int32_t g[N];
-    Vec<T, D> pn[N];
+    Vec<T, D> ph[N], pn[N];
+    const uint32_t fl = S.eflags[K];
 #pragma unroll
     for (int l = 0; l < N; ++l) g[l] = S.egat[(int64_t)l * ne + K];
 #pragma unroll
     for (int l = 0; l < N; ++l) {
-      pn[l] = ldv<T, D>(r, g[l]);
+      ph[l] = ldv<T, D>(r, g[l]);
       if (!first) {
         const Vec<T, D> po = ldv<T, D>(pold, g[l]);
 #pragma unroll
-        for (int i = 0; i < D; ++i) pn[l].v[i] = pn[l].v[i] + beta * po.v[i];
+        for (int i = 0; i < D; ++i) ph[l].v[i] = ph[l].v[i] + beta * po.v[i];
+      }
+      pn[l] = ph[l];
+    }
+    // The direction is p = ph + Z m, with m = E^-1 Z^t r + beta m_old per
+    // aggregate.  Where all faces of K lie in one aggregate, (Z m)_K is m_a
+    // times the local null vector of G'_K: it changes neither G'_K p_K nor
+    // p_K . G'_K p_K, so only elements on aggregate boundaries add it here.
+    if (S.nagg > 0 && (fl & F_AGGB)) {
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        const int a = S.fagg[g[l]];
+        const T m = (T)(first ? S.mu[a] : S.mu[a] + beta_d * mold[a]);
+        const Vec<T, D> z = ldv<T, D>((const T*)S.zT, g[l]);
+#pragma unroll
+        for (int i = 0; i < D; ++i) pn[l].v[i] += z.v[i] * m;
       }
     }
     T vh[N][D];
@@ -520,10 +586,10 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
       }
 #pragma unroll
     for (int j = 0; j < N; ++j) stv<T, D>(tq, K * N + j, w[j]);
-    const uint32_t fl = S.eflags[K];
+    // the owner stores the direction without its coarse part
 #pragma unroll
     for (int j = 0; j < N; ++j)
-      if (((fl >> j) & 1u) && !((fl >> (8 + j)) & 1u)) stv<T, D>(pnew, g[j], pn[j]);
+      if (((fl >> j) & 1u) && !((fl >> (8 + j)) & 1u)) stv<T, D>(pnew, g[j], ph[j]);
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) S.Pb[lb] = acc[0];
@@ -550,13 +616,39 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
   const T* __restrict__ p = (const T*)(par ? S.p1 : S.p);
   const T* __restrict__ tq = (const T*)S.tq;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
+  const int a0 = S.nagg > 0 ? S.ablk[lb] : 0;
+  const double cbeta = st->bet[par];
+  const bool cfirst = st->it[par] - 1 == st->it_first;
+  const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
+  if (S.nagg > 0 && lb == 0)  // the coarse part m of this iteration's direction
+    for (int a = threadIdx.x; a < S.nagg; a += NT)
+      S.M2[par * S.nagg + a] = cfirst ? S.mu[a] : S.mu[a] + cbeta * mold[a];
+  // m of the (at most KMAX) aggregates of this block's faces
+  T mk[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int a = min(a0 + k, S.nagg - 1);
+    mk[k] = S.nagg > 0 ? (T)(cfirst ? S.mu[a] : S.mu[a] + cbeta * mold[a]) : T(0);
+  }
   double acc[1] = {0.0};
+  double racc[KMAX] = {};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
     const int64_t K = S.fel[f], Lr = S.fel[P.nf + f];
     const int lc = S.floc[f];
     const Vec<T, D> wk = ldv<T, D>(tq, K * N + (lc & 0xff));
     const Vec<T, D> wl = ldv<T, D>(tq, Lr * N + ((lc >> 8) & 0xff));
     Vec<T, D> xi = ldv<T, D>(x, f), ri = ldv<T, D>(r, f), pi = ldv<T, D>(p, f);
+    Vec<T, D> zf;
+    int ak = 0;
+    if (S.nagg > 0) {
+      zf = ldv<T, D>((const T*)S.zT, f);
+      ak = S.fagg[f] - a0;
+      T m = mk[0];
+#pragma unroll
+      for (int k = 1; k < KMAX; ++k) m = ak == k ? mk[k] : m;
+#pragma unroll
+      for (int i = 0; i < D; ++i) pi.v[i] += zf.v[i] * m;
+    }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const T qi = wk.v[i] + wl.v[i];
@@ -566,10 +658,53 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
     }
     stv<T, D>(x, f, xi);
     stv<T, D>(r, f, ri);
+    if (S.nagg > 0) {
+      double zr = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) zr += (double)zf.v[i] * (double)ri.v[i];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) racc[k] += ak == k ? zr : 0.0;
+    }
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) S.Pa[lb] = acc[0];
+  if (S.nagg > 0) {
+    block_sum<KMAX>(racc);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) S.Pr[(int64_t)lb * KMAX + k] = racc[k];
+  }
   if (threadIdx.x == 0 && lb == 0) st->alp[par] = alpha;
+}
+
+// Coarse solve: c_a = sum of the restriction partials of the face blocks that
+// hold aggregate a (fixed order), mu = E^-1 c; one wavefront per row.
+__device__ __forceinline__ void coarse_body(const CgSys& S, int cb) {
+  if (S.st->done) return;
+  __shared__ double c[256];
+  for (int a = threadIdx.x; a < S.nagg; a += NT) {
+    double v = 0.0;
+    for (int b = S.bfa[a]; b <= S.bla[a]; ++b) v += S.Pr[(int64_t)b * KMAX + (a - S.ablk[b])];
+    c[a] = v;
+  }
+  __syncthreads();
+  const int row = cb * (NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= S.nagg) return;
+  double v = 0.0;
+  for (int j = lane; j < S.nagg; j += 64) v += S.Einv[(int64_t)row * S.nagg + j] * c[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) {
+    S.mu[row] = v;
+    S.cvec[row] = c[row];
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_coarse(CgSys S) { coarse_body(S, blockIdx.x); }
+
+__global__ void __launch_bounds__(NT) k_coarse_b(const CgSys* __restrict__ tab, const int* __restrict__ bmap) {
+  const CgSys S = tab[bmap[blockIdx.x]];
+  coarse_body(S, (int)blockIdx.x - S.boffC);
 }
 
 template <int D, typename T>
@@ -1284,14 +1419,24 @@ struct KWs {
   Part epart{};          // elements
   void* vec[NVEC] = {};  // each nf*d doubles
   void* tq = nullptr;    // element contributions, ne*(d+1)*d doubles
+  // coarse correction: block/aggregate tables of this partition, restriction
+  // partials, c and mu; use_coarse is set per solve
+  bool coarse_ok = false, use_coarse = false;
+  int32_t* ablk = nullptr;
+  int32_t* bfa = nullptr;
+  int32_t* bla = nullptr;
+  double* Pr = nullptr;
+  double* cvec = nullptr;
+  double* mu = nullptr;
+  double* M2 = nullptr;
   double* part3[3] = {};   // partial arrays, NFIELD x nblk each
   KState* st = nullptr;
   KState* hst = nullptr;   // pinned [3]
   hipEvent_t ev[2] = {};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipStream_t cap = nullptr;
-  hipGraphExec_t exec[2][3][2] = {};  // [precision][method][operator form]
-  int exec_m[2][3][2] = {};
+  hipGraphExec_t exec[2][3][3] = {};  // [precision][method][operator form, with coarse correction]
+  int exec_m[2][3][3] = {};
   // scratch for kernel timing
   void* tvec[NVEC] = {};
   void* ttq = nullptr;
@@ -1339,6 +1484,46 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
     w->tq = dev_alloc(s, sizeof(double) * (size_t)s->ne * (s->d + 1) * s->d);
     if (!w->tq) return CR_E_NOMEM;
   }
+  if (s->nagg > 0) {
+    // tables of the coarse restriction for this face partition: faces of an
+    // aggregate are contiguous, so each face block holds a contiguous range of
+    // aggregates (at most KMAX, else the correction is not used)
+    const Part& P = w->part;
+    const std::vector<int32_t>& fa = s->topo.face_agg;
+    const int m = s->nagg;
+    std::vector<int32_t> ablk(P.nblk, 0), bfa(m, 1), bla(m, 0);
+    bool ok = true;
+    for (int b = 0; b < P.nblk; ++b) {
+      const int64_t lo = (int64_t)b * P.chunk, hi = std::min<int64_t>(s->nf, lo + P.chunk);
+      if (lo >= hi) continue;
+      ablk[b] = fa[lo];
+      if (fa[hi - 1] - fa[lo] + 1 > KMAX) ok = false;
+    }
+    for (int64_t f = 0; f < s->nf; ++f) {
+      const int a = fa[f], b = (int)(f / P.chunk);
+      if (f == 0 || fa[f - 1] != a) bfa[a] = b;
+      bla[a] = b;
+    }
+    w->coarse_ok = ok;
+    auto up = [&](int32_t*& dst, const std::vector<int32_t>& src) {
+      dst = (int32_t*)dev_alloc(s, sizeof(int32_t) * src.size());
+      if (!dst) return CR_E_NOMEM;
+      return check_hip(hipMemcpy(dst, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice), "coarse tables");
+    };
+    cr_status cs = up(w->ablk, ablk);
+    if (cs == CR_OK) cs = up(w->bfa, bfa);
+    if (cs == CR_OK) cs = up(w->bla, bla);
+    if (cs != CR_OK) return cs;
+    w->Pr = (double*)dev_alloc(s, sizeof(double) * (size_t)P.nblk * KMAX);
+    w->cvec = (double*)dev_alloc(s, sizeof(double) * m);
+    w->mu = (double*)dev_alloc(s, sizeof(double) * m);
+    w->M2 = (double*)dev_alloc(s, sizeof(double) * 2 * m);
+    if (!w->Pr || !w->cvec || !w->mu || !w->M2) return CR_E_NOMEM;
+    cs = check_hip(hipMemset(w->cvec, 0, sizeof(double) * m), "coarse vectors");
+    if (cs == CR_OK) cs = check_hip(hipMemset(w->mu, 0, sizeof(double) * m), "coarse vectors");
+    if (cs == CR_OK) cs = check_hip(hipMemset(w->M2, 0, sizeof(double) * 2 * m), "coarse vectors");
+    if (cs != CR_OK) return cs;
+  }
   const size_t pbytes = sizeof(double) * (size_t)std::max(w->part.nblk, w->epart.nblk) * NFIELD;
   for (auto& p : w->part3) {
     p = (double*)dev_alloc(s, pbytes);
@@ -1363,6 +1548,19 @@ CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
   S.tq = w->tq;
   S.eflags = s->eflags;
   S.bs1 = s->bs1;
+  if (w->use_coarse) {
+    S.nagg = s->nagg;
+    S.fagg = s->fagg;
+    S.zT = prec == CR_FP32_IR ? (const void*)s->zy32 : (const void*)s->zy;
+    S.Pr = w->Pr;
+    S.ablk = w->ablk;
+    S.bfa = w->bfa;
+    S.bla = w->bla;
+    S.Einv = s->Einv;
+    S.cvec = w->cvec;
+    S.mu = w->mu;
+    S.M2 = w->M2;
+  }
   S.G = prec == CR_FP32_IR ? (const void*)s->G32 : (const void*)s->G64;
   S.cols = s->cols;
   S.G64 = s->G64;
@@ -1462,6 +1660,7 @@ void enqueue_iters(const Launch& L, hipStream_t stream, int npairs) {
         if constexpr (OP == 1) {
           hipLaunchKernelGGL((k_ec1<D, T>), dim3(w->epart.nblk), blk, 0, stream, S, par);
           hipLaunchKernelGGL((k_ec2<D, T>), grid, blk, 0, stream, S, par);
+          if (S.nagg > 0) hipLaunchKernelGGL(k_coarse, dim3((S.nagg + 3) / 4), blk, 0, stream, S);
         } else if (L.method == CR_PCG) {
           hipLaunchKernelGGL((k_cg_spmv<D, T, 0>), grid, blk, 0, stream, S, par);
           hipLaunchKernelGGL((k_cg_update<D, T>), grid, blk, 0, stream, S, par);
@@ -1499,8 +1698,10 @@ void enqueue_residual(cr_system* s, KWs* w, int prec, int method, int op, KState
     constexpr int D = decltype(dc)::value;
     constexpr int OP = decltype(oc)::value;
     using T = decltype(tc);
-    hipLaunchKernelGGL((k_ir_residual<D, T, OP>), dim3(P.nblk), dim3(NT), 0, stream, make_sys(s, w, prec, st),
-                       (T*)w->vec[V_RHAT], mode, method != CR_PCG ? 1 : 0);
+    const CgSys S = make_sys(s, w, prec, st);
+    hipLaunchKernelGGL((k_ir_residual<D, T, OP>), dim3(P.nblk), dim3(NT), 0, stream, S, (T*)w->vec[V_RHAT], mode,
+                       method != CR_PCG ? 1 : 0);
+    if (OP == 1 && S.nagg > 0) hipLaunchKernelGGL(k_coarse, dim3((S.nagg + 3) / 4), dim3(NT), 0, stream, S);
   });
 }
 
@@ -1515,7 +1716,7 @@ void enqueue_update(cr_system* s, KWs* w, int prec, KState* st, hipStream_t stre
 
 cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   KWs* w = L.w;
-  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method, oi = L.op ? 1 : 0;
+  const int pi = L.prec == CR_FP32_IR ? 1 : 0, mi = L.method, oi = L.op ? (L.w->use_coarse ? 2 : 1) : 0;
   hipGraphExec_t& ex = w->exec[pi][mi][oi];
   int& exm = w->exec_m[pi][mi][oi];
   if (ex && exm == npairs) {
@@ -1856,6 +2057,7 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   int op = 0;
   st = resolve_op(s, o, op);
   if (st != CR_OK) return st;
+  w->use_coarse = op == 1 && o->coarse == 0 && w->coarse_ok;
   Ctl c;
   c.init(o);
   const int blk = o->check_every > 0 ? o->check_every : 32;
@@ -1904,6 +2106,7 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
   int op = 0;
   st = resolve_op(s, &o, op);
   if (st != CR_OK) return st;
+  w->use_coarse = op == 1 && w->coarse_ok;
   const int d = s->d;
   const size_t vb = sizeof(double) * (size_t)s->nf * d;
   const Part P = w->part;
@@ -1991,6 +2194,9 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
       // once (by the owner elements); w_K written once
       *bytes = ne * (d1 * (d1 + 1) / 2 + d1 * d) * vsz + ne * (d1 + 1) * 4.0 + nf * d * vsz * 3 +
                ne * d1 * d * vsz;
+      // with the coarse correction: the aggregate of each face and the column
+      // of Z there, read by the elements on aggregate boundaries
+      if (w->use_coarse) *bytes += (double)s->nbnd * d1 * (4.0 + d * vsz);
     } else {
       // values and column indices of G read once, the gathered input r read
       // once, p and q read and written
@@ -2059,17 +2265,20 @@ struct cr_batch {
   crh::CgSys* dtab[2] = {};
   int* dmap[2] = {};   // face block -> table entry
   int* dmapE[2] = {};  // element block -> table entry
+  int* dmapC[2] = {};  // coarse block -> table entry
   crh::CgSys* htab[2] = {};
   int* hmap[2] = {};
   int* hmapE[2] = {};
+  int* hmapC[2] = {};
   int nblocks[2] = {};
   int nblocksE[2] = {};
+  int nblocksC[2] = {};
   // the iteration block of an advance, captured once per launch shape (block
   // counts and iteration count) and replayed; membership changes that keep
   // the shape only rewrite the device tables the graph reads
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
-  int exec_key[6] = {-1, -1, -1, -1, -1, -1};
+  int exec_key[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int64_t map_cap = 0;
   bool dirty = true;
 };
@@ -2080,25 +2289,30 @@ namespace {
 cr_status batch_rebuild(cr_batch* b) {
   for (int pi = 0; pi < 2; ++pi) {
     const int prec = pi ? CR_FP32_IR : CR_FP64;
-    int n = 0, blocks = 0, eblocks = 0;
+    int n = 0, blocks = 0, eblocks = 0, cblocks = 0;
     for (int k = 0; k < b->max_sys; ++k) {
       BEntry& en = b->e[k];
       if (!en.active || en.c.prec != prec) continue;
       CgSys S = make_sys(en.s, en.w, prec, b->dst + k);
       S.boff = blocks;
       S.boffE = eblocks;
+      S.boffC = cblocks;
+      const int nc = S.nagg > 0 ? (S.nagg + 3) / 4 : 0;
       if (blocks + S.P.nblk > b->map_cap || eblocks + S.PE.nblk > b->map_cap) {
         set_error("batch block table full");
         return CR_E_NOMEM;
       }
       for (int j = 0; j < S.P.nblk; ++j) b->hmap[pi][blocks + j] = n;
       for (int j = 0; j < S.PE.nblk; ++j) b->hmapE[pi][eblocks + j] = n;
+      for (int j = 0; j < nc; ++j) b->hmapC[pi][cblocks + j] = n;
       blocks += S.P.nblk;
       eblocks += S.PE.nblk;
+      cblocks += nc;
       b->htab[pi][n++] = S;
     }
     b->nblocks[pi] = blocks;
     b->nblocksE[pi] = eblocks;
+    b->nblocksC[pi] = cblocks;
     if (n) {
       cr_status st = check_hip(
           hipMemcpyAsync(b->dtab[pi], b->htab[pi], sizeof(CgSys) * n, hipMemcpyHostToDevice, b->stream), "batch table");
@@ -2108,6 +2322,10 @@ cr_status batch_rebuild(cr_batch* b) {
       if (st == CR_OK)
         st = check_hip(
             hipMemcpyAsync(b->dmapE[pi], b->hmapE[pi], sizeof(int) * eblocks, hipMemcpyHostToDevice, b->stream),
+            "batch map");
+      if (st == CR_OK && cblocks)
+        st = check_hip(
+            hipMemcpyAsync(b->dmapC[pi], b->hmapC[pi], sizeof(int) * cblocks, hipMemcpyHostToDevice, b->stream),
             "batch map");
       if (st != CR_OK) return st;
     }
@@ -2141,9 +2359,11 @@ cr_status cr_batch_create(void* hip_stream, int32_t max_systems, cr_batch** out)
     st = check_hip(hipMalloc((void**)&b->dtab[pi], sizeof(CgSys) * max_systems), "batch table");
     if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmap[pi], sizeof(int) * b->map_cap), "batch map");
     if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmapE[pi], sizeof(int) * b->map_cap), "batch map");
+    if (st == CR_OK) st = check_hip(hipMalloc((void**)&b->dmapC[pi], sizeof(int) * b->map_cap), "batch map");
     if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->htab[pi], sizeof(CgSys) * max_systems, hipHostMallocDefault), "batch table");
     if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmap[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
     if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmapE[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
+    if (st == CR_OK) st = check_hip(hipHostMalloc((void**)&b->hmapC[pi], sizeof(int) * b->map_cap, hipHostMallocDefault), "batch map");
   }
   if (st != CR_OK) {
     cr_batch_destroy(b);
@@ -2209,6 +2429,7 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
   en.o = *o;
   en.c.init(o);
   en.op = op;
+  w->use_coarse = op == 1 && o->coarse == 0 && w->coarse_ok;
   en.t0 = std::chrono::steady_clock::now();
   if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, b->stream), "zero W");
@@ -2252,6 +2473,8 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
                                  b->dmapE[pi], par);
               hipLaunchKernelGGL((k_ec2_b<D, T>), dim3(b->nblocks[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmap[pi], par);
+              if (b->nblocksC[pi])
+                hipLaunchKernelGGL(k_coarse_b, dim3(b->nblocksC[pi]), dim3(NT), 0, stream, b->dtab[pi], b->dmapC[pi]);
             } else {
               hipLaunchKernelGGL((k_cg_spmv_b<D, T, 0>), dim3(b->nblocks[pi]), dim3(NT), 0, stream, b->dtab[pi],
                                  b->dmap[pi], par);
@@ -2262,8 +2485,9 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
         }
   };
   if (any) {
-    const int key[6] = {b->nblocks[0], b->nblocks[1], b->nblocksE[0], b->nblocksE[1], npairs, b->op};
-    if (!b->exec || !std::equal(key, key + 6, b->exec_key)) {
+    const int key[8] = {b->nblocks[0], b->nblocks[1], b->nblocksE[0], b->nblocksE[1],
+                        b->nblocksC[0], b->nblocksC[1], npairs, b->op};
+    if (!b->exec || !std::equal(key, key + 8, b->exec_key)) {
       if (b->exec) {
         hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -2280,7 +2504,7 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
         if (g) hipGraphDestroy(g);
       }
       if (st != CR_OK) return st;
-      std::copy(key, key + 6, b->exec_key);
+      std::copy(key, key + 8, b->exec_key);
     }
     st = check_hip(hipGraphLaunch(b->exec, b->stream), "batch graph launch");
     if (st != CR_OK) return st;
@@ -2365,9 +2589,11 @@ void cr_batch_destroy(cr_batch* b) {
     if (b->dtab[pi]) hipFree(b->dtab[pi]);
     if (b->dmap[pi]) hipFree(b->dmap[pi]);
     if (b->dmapE[pi]) hipFree(b->dmapE[pi]);
+    if (b->dmapC[pi]) hipFree(b->dmapC[pi]);
     if (b->htab[pi]) hipHostFree(b->htab[pi]);
     if (b->hmap[pi]) hipHostFree(b->hmap[pi]);
     if (b->hmapE[pi]) hipHostFree(b->hmapE[pi]);
+    if (b->hmapC[pi]) hipHostFree(b->hmapC[pi]);
   }
   delete b;
 }

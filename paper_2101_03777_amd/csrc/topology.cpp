@@ -19,6 +19,39 @@ namespace crh {
 
 namespace {
 
+// recursive coordinate bisection of idx[lo, hi) into `parts` (a power of two)
+// groups at the median of the longest centroid extent; group ids in
+// depth-first order
+void rcb(std::vector<int32_t>& idx, size_t lo, size_t hi, int parts, const std::vector<double>& cen, int d,
+         int& next, std::vector<int32_t>& agg) {
+  if (parts == 1 || hi - lo < 2) {
+    for (size_t i = lo; i < hi; ++i) agg[idx[i]] = next;
+    ++next;
+    return;
+  }
+  int ax = 0;
+  double best = -1.0;
+  for (int a = 0; a < d; ++a) {
+    double mn = 1e300, mx = -1e300;
+    for (size_t i = lo; i < hi; ++i) {
+      const double c = cen[(size_t)idx[i] * d + a];
+      mn = std::min(mn, c);
+      mx = std::max(mx, c);
+    }
+    if (mx - mn > best) {
+      best = mx - mn;
+      ax = a;
+    }
+  }
+  const size_t mid = lo + (hi - lo) / 2;
+  std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [&](int32_t a, int32_t b) {
+    const double ca = cen[(size_t)a * d + ax], cb = cen[(size_t)b * d + ax];
+    return ca < cb || (ca == cb && a < b);
+  });
+  rcb(idx, lo, mid, parts / 2, cen, d, next, agg);
+  rcb(idx, mid, hi, parts / 2, cen, d, next, agg);
+}
+
 struct LocalFace {
   uint32_t v[3];
   int32_t elem;
@@ -70,7 +103,7 @@ int bfs_eccentricity(int root, const std::vector<int64_t>& ptr, const std::vecto
 
 }  // namespace
 
-cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, Topology& t) {
+cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, bool aggregate, Topology& t) {
   const int d = mesh->dim;
   if (d != 2 && d != 3) {
     set_error("dim must be 2 or 3 (got %d)", d);
@@ -255,6 +288,32 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, T
       }
     }
     std::reverse(order.begin(), order.end());
+    // Aggregates for the coarse correction: recursive coordinate bisection of
+    // the element centroids into nagg parts (a power of two, about 2048
+    // elements each, at most 128; none below 4 parts), numbered in bisection
+    // order so that consecutive aggregates are neighbours.  A face belongs to
+    // the aggregate of its owner element (the lower caller id, C = +1).  Faces
+    // are grouped by aggregate, in RCM order inside a group.
+    int nagg = 1;
+    while (nagg < 128 && (int64_t)nagg * 2 * 2048 <= ne) nagg *= 2;
+    if (aggregate && nagg >= 4) {
+      std::vector<double> cen((size_t)ne * d, 0.0);
+      for (int64_t k = 0; k < ne; ++k)
+        for (int j = 0; j < d1; ++j) {
+          const int64_t v = mesh->elem_vertices[k * d1 + j];
+          for (int a = 0; a < d; ++a) cen[k * d + a] += mesh->coords[v * d + a] / d1;
+        }
+      std::vector<int32_t> eagg(ne, 0), idx(ne);
+      std::iota(idx.begin(), idx.end(), 0);
+      int next = 0;
+      rcb(idx, 0, (size_t)ne, nagg, cen, d, next, eagg);
+      std::vector<int32_t> fagg(nf);
+      for (int64_t f = 0; f < nf; ++f) fagg[f] = eagg[t.face_elem[2 * f]];
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fagg[a] < fagg[b]; });
+      t.nagg = nagg;
+      t.face_agg.resize(nf);
+      for (int64_t i = 0; i < nf; ++i) t.face_agg[i] = fagg[order[i]];
+    }
     for (int64_t i = 0; i < nf; ++i) {
       t.face_iperm[i] = order[i];
       t.face_perm[order[i]] = (int32_t)i;

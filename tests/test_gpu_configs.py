@@ -258,7 +258,9 @@ def test_multistep_update_rhs_parity(gpu):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_batch_bitwise_equals_single(gpu, precision):
     systems = []
-    for n, mu in [(8, 300.0), (12, 50.0), (20, 1000.0), (33, 10.0)]:
+    # 64 x 64 x 2 = 8192 elements: the smallest mesh with aggregates, so the
+    # batched coarse solve runs too
+    for n, mu in [(8, 300.0), (12, 50.0), (20, 1000.0), (33, 10.0), (64, 1000.0)]:
         co, el = synth.square_mesh(n, jitter=0.2, seed=n)
         fb = np.random.default_rng(n).normal(size=(len(el), 2))
         s = gpu.System(co, el, mu, 1.0)

@@ -221,6 +221,33 @@ def test_kernel_timing_runs_the_full_kernel(gpu, precision, operator):
     s.close()
 
 
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+def test_coarse_correction_parity(gpu, precision, bar):
+    """CG with the aggregate coarse correction (64 x 64 x 2 = 8192 elements, 4
+    aggregates, and 128 x 128 x 2 with 16) against the oracle's direct solve, and
+    against the same solve with Jacobi only: same solution, fewer iterations."""
+    for n, seed in [(64, 21), (128, 22)]:
+        coords, elems = synth.square_mesh(n, jitter=0.2, seed=seed)
+        fbar = np.random.default_rng(seed).normal(size=(len(elems), 2))
+        mu = 1000.0
+        P = cr.make_problem(coords, elems, mu, 1.0, fbar)
+        U_o, P_o = cr.solve_coupled(P)
+        s = gpu.System(coords, elems, mu, 1.0)
+        s.eliminate(dev(fbar))
+        a = s.solve("pcg", precision, tol=1e-13)
+        U, Pk = s.recover()
+        torch.cuda.synchronize()
+        print(f"{n}x{n}x2 {precision}: coarse {a['iters']} iterations", flush=True)
+        assert relerr(U.cpu().numpy(), U_o) <= bar
+        assert relerr(Pk.cpu().numpy(), P_o) <= bar
+        Wa = s.export_W()
+        b = s.solve("pcg", precision, tol=1e-13, coarse=False)
+        print(f"{n}x{n}x2 {precision}: Jacobi only {b['iters']} iterations", flush=True)
+        assert relerr(Wa, s.export_W()) <= 1e-9
+        assert a["iters"] < b["iters"]
+        s.close()
+
+
 def test_graph_and_plain_launches_agree(gpu):
     """The captured-graph replay and plain launches run the same kernels: same iterates."""
     case = make_case("jitter12")
