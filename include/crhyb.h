@@ -220,9 +220,12 @@ cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_i
                            double* U, double* P);
 
 /* Average device time of the dominant Krylov kernel (SpMV fused with the CG
- * direction updates) over reps back-to-back launches on the system's stream,
- * measured with HIP events, on scratch copies of the state (the resident
- * solution is untouched).  precision and operator_form as in cr_solve_opts.
+ * direction updates) over reps launches on the system's stream, measured with
+ * HIP events, on scratch copies of the state (the resident solution is
+ * untouched; the coarse-correction vectors of the last solve are not kept).
+ * Back-to-back launches, except with the coarse correction, where the element
+ * kernel runs inside the iteration sequence with events attached to each of its
+ * launches.  precision and operator_form as in cr_solve_opts.
  * Also returns the algorithmic bytes one launch moves: the operator data once
  * (assembled: values and column indices of G; element form: element factors,
  * element gather indices, face-to-element table), the gathered input vector
