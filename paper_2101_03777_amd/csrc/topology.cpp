@@ -335,16 +335,27 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     t.bw_internal = bandwidth(t.face_perm);
   }
 
-  // element order: by smallest internal face id, ties by caller id
+  // element order: by smallest internal face id, ties by caller id; with
+  // aggregates, the elements whose faces lie in more than one aggregate come
+  // last within the range of their aggregate, so that few wavefronts of the
+  // element kernel handle the coarse term
   {
     std::vector<int64_t> key(ne);
     for (int64_t k = 0; k < ne; ++k) {
       int64_t m = INT64_MAX;
+      int a0 = -1;
+      bool multi = false;
       for (int j = 0; j < d1; ++j) {
         int f = t.elem_face[k * d1 + j];
-        if (f >= 0) m = std::min<int64_t>(m, t.face_perm[f]);
+        if (f < 0) continue;
+        m = std::min<int64_t>(m, t.face_perm[f]);
+        if (t.nagg > 0) {
+          const int a = t.face_agg[t.face_perm[f]];
+          if (a0 < 0) a0 = a;
+          else if (a != a0) multi = true;
+        }
       }
-      key[k] = m;
+      key[k] = t.nagg > 0 ? (int64_t)t.face_agg[m] * 2 * nf + (multi ? nf : 0) + m : m;
     }
     t.elem_iperm.resize(ne);
     std::iota(t.elem_iperm.begin(), t.elem_iperm.end(), 0);
