@@ -13,6 +13,7 @@
 // element holding both faces and the diagonal block from the face's two
 // elements, so assembly needs no atomics.
 #include <cmath>
+#include <utility>
 
 #include "internal.h"
 #include "geometry.h"
@@ -840,51 +841,53 @@ __global__ void __launch_bounds__(256) k_coarse_E(int32_t npairs, const int32_t*
 
 // Inverse of E + s 1 1^t (s = trace(E) / m; E is positive semi-definite with
 // null vector 1, since the columns of Z sum to z) by Gauss-Jordan without
-// pivoting, one workgroup; E is overwritten.  A pivot that is not positive
+// pivoting on the m x 2m array [E + s 1 1^t | I], one launch per pivot,
+// reading one buffer and writing the other.  A pivot that is not positive
 // leaves a zero inverse (the correction then does nothing).
-__global__ void __launch_bounds__(1024) k_coarse_inv(int m, double* __restrict__ E, double* __restrict__ Einv) {
-  __shared__ double fac[1024];
-  __shared__ double s_tr;
-  __shared__ int bad;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < m; ++i) tr += E[(int64_t)i * m + i];
-    s_tr = tr / m;
-    bad = 0;
+__global__ void __launch_bounds__(1024) k_gj_init(int m, const double* __restrict__ E, double* __restrict__ X,
+                                                  double* __restrict__ scal) {
+  __shared__ double red[16];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) tr += E[(int64_t)i * m + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k];
+    red[0] = t / m;
   }
   __syncthreads();
-  for (int64_t q = t; q < (int64_t)m * m; q += 1024) {
-    E[q] += s_tr;
-    Einv[q] = (q / m == q % m) ? 1.0 : 0.0;
+  const double sh = red[0];
+  for (int64_t q = threadIdx.x; q < (int64_t)m * 2 * m; q += 1024) {
+    const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
+    X[q] = c < m ? E[(int64_t)i * m + c] + sh : (c - m == i ? 1.0 : 0.0);
   }
-  __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    const double piv = E[(int64_t)k * m + k];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (t == 0) bad = 1;
-      break;
-    }
-    for (int i = t; i < m; i += 1024) fac[i] = E[(int64_t)i * m + k];
-    __syncthreads();
-    const double ip = 1.0 / piv;
-    for (int c = t; c < 2 * m; c += 1024) {
-      double* row = c < m ? E + (int64_t)k * m + c : Einv + (int64_t)k * m + (c - m);
-      *row *= ip;
-    }
-    __syncthreads();
-    for (int64_t q = t; q < (int64_t)m * 2 * m; q += 1024) {
-      const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
-      if (i == k) continue;
-      const double pk = c < m ? E[(int64_t)k * m + c] : Einv[(int64_t)k * m + (c - m)];
-      double* x = c < m ? E + (int64_t)i * m + c : Einv + (int64_t)i * m + (c - m);
-      *x -= fac[i] * pk;
-    }
-    __syncthreads();
+  if (threadIdx.x == 0) scal[0] = 0.0;  // bad-pivot flag
+}
+
+__global__ void __launch_bounds__(256) k_gj_step(int m, int k, const double* __restrict__ X, double* __restrict__ Y,
+                                                 double* __restrict__ scal) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (int64_t)m * 2 * m) return;
+  const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
+  const double piv = X[(int64_t)k * 2 * m + k];
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    if (q == 0) scal[0] = 1.0;
+    Y[q] = X[q];
+    return;
   }
-  __syncthreads();
-  if (bad)
-    for (int64_t q = t; q < (int64_t)m * m; q += 1024) Einv[q] = 0.0;
+  const double rk = X[(int64_t)k * 2 * m + c] / piv;
+  Y[q] = i == k ? rk : X[q] - X[(int64_t)i * 2 * m + k] * rk;
+}
+
+__global__ void __launch_bounds__(256) k_gj_final(int m, const double* __restrict__ X, const double* __restrict__ scal,
+                                                  double* __restrict__ Einv) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (int64_t)m * m) return;
+  const int i = (int)(q / m), c = (int)(q % m);
+  Einv[q] = scal[0] != 0.0 ? 0.0 : X[(int64_t)i * 2 * m + m + c];
 }
 
 // The same inverse for m <= 128 with E held in LDS (m^2 doubles, at most
@@ -1251,7 +1254,20 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
         if (st != CR_OK) return st;
         hipLaunchKernelGGL(k_coarse_inv_lds, dim3(1), dim3(1024), sizeof(double) * m * m, s->stream, m, s->Ec, s->Einv);
       } else {
-        hipLaunchKernelGGL(k_coarse_inv, dim3(1), dim3(1024), 0, s->stream, m, s->Ec, s->Einv);
+        // two m x 2m buffers and a flag in scratch memory of this system
+        if (!s->gjbuf) s->gjbuf = (double*)dev_alloc(s, sizeof(double) * ((size_t)4 * m * m + 1));
+        if (!s->gjbuf) return CR_E_NOMEM;
+        double* X = s->gjbuf;
+        double* Y = X + (size_t)2 * m * m;
+        double* flag = Y + (size_t)2 * m * m;
+        hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(1024), 0, s->stream, m, s->Ec, X, flag);
+        const unsigned gq = (unsigned)(((int64_t)m * 2 * m + 255) / 256);
+        for (int k = 0; k < m; ++k) {
+          hipLaunchKernelGGL(k_gj_step, dim3(gq), dim3(256), 0, s->stream, m, k, X, Y, flag);
+          std::swap(X, Y);
+        }
+        hipLaunchKernelGGL(k_gj_final, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, s->stream, m, X,
+                           flag, s->Einv);
       }
       const int64_t n = s->nf * d;
       hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(n, BS)), dim3(BS), 0, s->stream, n, s->zy, s->zy32);

@@ -115,6 +115,7 @@ struct cr_system {
   int32_t* pair_ent = nullptr; // [entries] k * 16 + j * 4 + l
   double* Ec = nullptr;        // [nagg * nagg]
   double* Einv = nullptr;      // [nagg * nagg]
+  double* gjbuf = nullptr;     // inversion scratch for nagg > 128
   float* zy32 = nullptr;       // [nf * d]
   int64_t nbnd = 0;            // elements with F_AGGB
   double* bs = nullptr;        // [nf*d] S / dsq

@@ -290,12 +290,12 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     std::reverse(order.begin(), order.end());
     // Aggregates for the coarse correction: recursive coordinate bisection of
     // the element centroids into nagg parts (a power of two, about 2048
-    // elements each, at most 128; none below 4 parts), numbered in bisection
+    // elements each, at most 256; none below 4 parts), numbered in bisection
     // order so that consecutive aggregates are neighbours.  A face belongs to
     // the aggregate of its owner element (the lower caller id, C = +1).  Faces
     // are grouped by aggregate, in RCM order inside a group.
     int nagg = 1;
-    while (nagg < 128 && (int64_t)nagg * 2 * 2048 <= ne) nagg *= 2;
+    while (nagg < 256 && (int64_t)nagg * 2 * 2048 <= ne) nagg *= 2;
     if (aggregate && nagg >= 4) {
       std::vector<double> cen((size_t)ne * d, 0.0);
       for (int64_t k = 0; k < ne; ++k)
