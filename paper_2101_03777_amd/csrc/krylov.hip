@@ -514,10 +514,15 @@ __global__ void __launch_bounds__(NT) k_cg_update_b(const CgSys* __restrict__ ta
 // p alternates between two buffers by parity.  w is stored [element][local
 // face][component] so that E2 reads each side as one short vector.
 // ---------------------------------------------------------------------------
+// Elements per thread whose loads are in flight together: four in 2D FP32
+// (about 28 values each), one elsewhere (measured on 512x512x2 and 64^3x6).
+template <int D, typename T>
+constexpr int ec1_batch() { return (D == 2 && sizeof(T) == 4) ? 4 : 1; }
+
 template <int D, typename T>
 __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   using L = EfoLayout<D>;
-  constexpr int N = L::N;
+  constexpr int N = L::N, EB = ec1_batch<D, T>();
   double beta_d;
   bool first;
   if (S.st->done) return;
@@ -533,65 +538,81 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(ne, lo + S.PE.chunk);
   double acc[1] = {0.0};
   const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
-  for (int64_t K = lo + threadIdx.x; K < hi; K += NT) {
-    int32_t g[N];
-    Vec<T, D> ph[N], pn[N];
-    const uint32_t fl = S.eflags[K];
+  // EB elements (stride NT) per pass: indices, flags, factors, and r and the
+  // previous direction at their faces are all loaded before any is used;
+  // indices past the range are clamped to its last element (ne >= 1), so the
+  // loads carry no branches
+  for (int64_t Kb = lo + threadIdx.x; Kb < hi; Kb += (int64_t)EB * NT) {
+    int32_t g[EB][N];
+    uint32_t fl[EB];
+    T fv[EB][L::NF];
+    Vec<T, D> rv[EB][N], po[EB][N];
 #pragma unroll
-    for (int l = 0; l < N; ++l) g[l] = S.egat[(int64_t)l * ne + K];
+    for (int e = 0; e < EB; ++e) {
+      const int64_t K = min(Kb + (int64_t)e * NT, hi - 1);
+      fl[e] = S.eflags[K];
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
-      ph[l] = ldv<T, D>(r, g[l]);
-      if (!first) {
-        const Vec<T, D> po = ldv<T, D>(pold, g[l]);
+      for (int l = 0; l < N; ++l) g[e][l] = S.egat[(int64_t)l * ne + K];
 #pragma unroll
-        for (int i = 0; i < D; ++i) ph[l].v[i] = ph[l].v[i] + beta * po.v[i];
-      }
-      pn[l] = ph[l];
+      for (int c = 0; c < L::NF; ++c) fv[e][c] = F[(int64_t)c * ne + K];
     }
-    // The direction is p = ph + Z m, with m = E^-1 Z^t r + beta m_old per
-    // aggregate.  Where all faces of K lie in one aggregate, (Z m)_K is m_a
-    // times the local null vector of G'_K: it changes neither G'_K p_K nor
-    // p_K . G'_K p_K, so only elements on aggregate boundaries add it here.
-    if (S.nagg > 0 && (fl & F_AGGB)) {
+#pragma unroll
+    for (int e = 0; e < EB; ++e)
 #pragma unroll
       for (int l = 0; l < N; ++l) {
-        const int a = S.fagg[g[l]];
-        const T m = (T)(first ? S.mu[a] : S.mu[a] + beta_d * mold[a]);
-        const Vec<T, D> z = ldv<T, D>((const T*)S.zT, g[l]);
-#pragma unroll
-        for (int i = 0; i < D; ++i) pn[l].v[i] += z.v[i] * m;
+        rv[e][l] = ldv<T, D>(r, g[e][l]);
+        if (!first) po[e][l] = ldv<T, D>(pold, g[e][l]);
       }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int64_t K = Kb + (int64_t)e * NT;
+      if (K >= hi) break;
+      Vec<T, D> ph[N], pn[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        ph[l] = rv[e][l];
+        if (!first)
+#pragma unroll
+          for (int i = 0; i < D; ++i) ph[l].v[i] = ph[l].v[i] + beta * po[e][l].v[i];
+        pn[l] = ph[l];
+      }
+      // The direction is p = ph + Z m, with m = E^-1 Z^t r + beta m_old per
+      // aggregate.  Where all faces of K lie in one aggregate, (Z m)_K is m_a
+      // times the local null vector of G'_K: it changes neither G'_K p_K nor
+      // p_K . G'_K p_K, so only elements on aggregate boundaries add it here.
+      if (S.nagg > 0 && (fl[e] & F_AGGB)) {
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          const int a = S.fagg[g[e][l]];
+          const T m = (T)(first ? S.mu[a] : S.mu[a] + beta_d * mold[a]);
+          const Vec<T, D> z = ldv<T, D>((const T*)S.zT, g[e][l]);
+#pragma unroll
+          for (int i = 0; i < D; ++i) pn[l].v[i] += z.v[i] * m;
+        }
+      }
+      T t = T(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l)
+#pragma unroll
+        for (int i = 0; i < D; ++i) t += fv[e][L::vh(l, i)] * pn[l].v[i];
+      Vec<T, D> w[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          T a = -fv[e][L::vh(j, i)] * t;
+#pragma unroll
+          for (int l = 0; l < N; ++l) a += fv[e][L::sym(j, l)] * pn[l].v[i];
+          w[j].v[i] = a;
+          acc[0] += (double)pn[j].v[i] * (double)a;
+        }
+#pragma unroll
+      for (int j = 0; j < N; ++j) stv<T, D>(tq, K * N + j, w[j]);
+      // the owner stores the direction without its coarse part
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (((fl[e] >> j) & 1u) && !((fl[e] >> (8 + j)) & 1u)) stv<T, D>(pnew, g[e][j], ph[j]);
     }
-    T vh[N][D];
-    T t = T(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l)
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        vh[l][i] = F[(int64_t)L::vh(l, i) * ne + K];
-        t += vh[l][i] * pn[l].v[i];
-      }
-    T sh[L::NSYM];
-#pragma unroll
-    for (int c = 0; c < L::NSYM; ++c) sh[c] = F[(int64_t)c * ne + K];
-    Vec<T, D> w[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        T a = -vh[j][i] * t;
-#pragma unroll
-        for (int l = 0; l < N; ++l) a += sh[L::sym(j, l)] * pn[l].v[i];
-        w[j].v[i] = a;
-        acc[0] += (double)pn[j].v[i] * (double)a;
-      }
-#pragma unroll
-    for (int j = 0; j < N; ++j) stv<T, D>(tq, K * N + j, w[j]);
-    // the owner stores the direction without its coarse part
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (((fl >> j) & 1u) && !((fl >> (8 + j)) & 1u)) stv<T, D>(pnew, g[j], ph[j]);
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) S.Pb[lb] = acc[0];
