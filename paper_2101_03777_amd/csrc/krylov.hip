@@ -515,19 +515,17 @@ __global__ void __launch_bounds__(NT) k_cg_update_b(const CgSys* __restrict__ ta
 // face][component] so that E2 reads each side as one short vector.
 // ---------------------------------------------------------------------------
 // Elements per thread whose loads are in flight together: four in 2D FP32
-// (about 28 values each), one elsewhere (measured on 512x512x2 and 64^3x6).
+// (about 28 values each) where each thread has at least four elements, one
+// elsewhere (measured on 512x512x2 and 64^3x6).
 template <int D, typename T>
 constexpr int ec1_batch() { return (D == 2 && sizeof(T) == 4) ? 4 : 1; }
 
-template <int D, typename T>
-__device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
+// the element loop of E1 over [lo, hi) with EB elements per pass
+template <int D, typename T, int EB>
+__device__ __forceinline__ void ec1_pass(const CgSys& S, int par, int64_t lo, int64_t hi, double beta_d, bool first,
+                                         double (&acc)[1]) {
   using L = EfoLayout<D>;
-  constexpr int N = L::N, EB = ec1_batch<D, T>();
-  double beta_d;
-  bool first;
-  if (S.st->done) return;
-  const double cd = S.nagg > 0 ? coarse_dot(S) : 0.0;
-  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, cd)) return;
+  constexpr int N = L::N;
   const T beta = (T)beta_d;
   const T* __restrict__ F = (const T*)S.F;
   const T* __restrict__ r = (const T*)S.r;
@@ -535,8 +533,6 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   T* __restrict__ pnew = (T*)(par ? S.p1 : S.p);
   T* __restrict__ tq = (T*)S.tq;
   const int64_t ne = S.ne;
-  const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(ne, lo + S.PE.chunk);
-  double acc[1] = {0.0};
   const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
   // EB elements (stride NT) per pass: indices, flags, factors, and r and the
   // previous direction at their faces are all loaded before any is used;
@@ -614,6 +610,22 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
         if (((fl[e] >> j) & 1u) && !((fl[e] >> (8 + j)) & 1u)) stv<T, D>(pnew, g[e][j], ph[j]);
     }
   }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
+  constexpr int EB = ec1_batch<D, T>();
+  double beta_d;
+  bool first;
+  if (S.st->done) return;
+  const double cd = S.nagg > 0 ? coarse_dot(S) : 0.0;
+  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, cd)) return;
+  const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(S.ne, lo + S.PE.chunk);
+  double acc[1] = {0.0};
+  if (EB > 1 && S.PE.chunk >= (int64_t)EB * NT)
+    ec1_pass<D, T, EB>(S, par, lo, hi, beta_d, first, acc);
+  else
+    ec1_pass<D, T, 1>(S, par, lo, hi, beta_d, first, acc);
   block_sum<1>(acc);
   if (threadIdx.x == 0) S.Pb[lb] = acc[0];
 }
