@@ -115,6 +115,22 @@ typedef struct {
 cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params,
                       const cr_allocator* alloc, void* hip_stream, cr_system** out);
 
+/* cr_assemble in two parts, for callers that build systems on a host thread
+ * while other systems keep the device busy (Section 2 item 1, as cr_assemble).
+ * cr_prepare is the host part only: checks, topology, renumbering, the element
+ * and face tables in internal order (and, for transient Stokes, the aggregates
+ * of the coarse correction); it makes no HIP call and may run on any thread,
+ * concurrently with device work of other systems.  *out is NULL on error;
+ * errors as cr_assemble except CR_E_DEVICE.
+ * cr_assemble_prepared is the device part: allocation and upload on hip_stream;
+ * it always consumes prep (also on error), and *out is what cr_assemble would
+ * return for the same mesh and parameters.
+ * cr_prepared_destroy frees a prepared mesh that is not assembled (NULL: no-op). */
+typedef struct cr_prepared cr_prepared;
+cr_status cr_prepare(const cr_mesh_desc* mesh, const cr_params* params, cr_prepared** out);
+cr_status cr_assemble_prepared(cr_prepared* prep, const cr_allocator* alloc, void* hip_stream, cr_system** out);
+void cr_prepared_destroy(cr_prepared* prep);
+
 /* Steps a1-a3: element-wise elimination (Section 3.2 items 4-5) and assembly of
  * G (same block stencil as A) and S.
  * f_mean: device [n_elements][dim], element means of the force (eq. defrhs).

@@ -30,7 +30,8 @@ _OPFORM = {"auto": CR_OP_AUTO, "assembled": CR_OP_ASSEMBLED, "element": CR_OP_EL
 EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recover", "cr_query_sizes",
            "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
            "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
-           "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy"]
+           "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy", "cr_prepare",
+           "cr_assemble_prepared", "cr_prepared_destroy"]
 
 
 class CRError(RuntimeError):
@@ -99,6 +100,9 @@ def load(path: str = LIB_PATH):
         "cr_coupled_solve": (I32, [P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P, P]),
         "cr_time_spmv": (I32, [P, I32, I32, I32, C.POINTER(D), C.POINTER(D)]),
         "cr_destroy": (None, [P]),
+        "cr_prepare": (I32, [C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(P)]),
+        "cr_assemble_prepared": (I32, [P, C.POINTER(Allocator), P, C.POINTER(P)]),
+        "cr_prepared_destroy": (None, [P]),
         "cr_batch_create": (I32, [P, I32, C.POINTER(P)]),
         "cr_batch_add": (I32, [P, P, C.POINTER(SolveOpts)]),
         "cr_batch_advance": (I32, [P, I32, C.POINTER(I32)]),
@@ -261,28 +265,60 @@ class Batch:
             pass
 
 
-class System:
-    """One hybridised Crouzeix-Raviart system resident on the current GPU."""
+class Prepared:
+    """Host part of a system (cr_prepare): topology and tables, no device call,
+    so it can be built on a worker thread while the device is busy.  Pass it to
+    System(prepared=...), which consumes it."""
 
-    def __init__(self, coords, elems, mu, nu, k0=0, problem="stokes", renumber="rcm", stream=None,
-                 allocator="torch"):
-        import torch
-        self._torch = torch
+    def __init__(self, coords, elems, mu, nu, k0=0, problem="stokes", renumber="rcm"):
         self.lib = load()
         self.dim = int(np.asarray(coords).shape[1])
         self.n_elements = int(np.asarray(elems).shape[0])
+        m, keep = _mesh(coords, elems)
+        p = _params(mu, nu, k0, problem, renumber)
+        h = C.c_void_p()
+        _check(self.lib.cr_prepare(C.byref(m), C.byref(p), C.byref(h)))
+        self.h = h
+
+    def take(self):
+        h, self.h = self.h, None
+        if h is None:
+            raise ValueError("prepared mesh already assembled")
+        return h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and not sys.is_finalizing():
+            self.lib.cr_prepared_destroy(self.h)
+            self.h = None
+
+
+class System:
+    """One hybridised Crouzeix-Raviart system resident on the current GPU."""
+
+    def __init__(self, coords=None, elems=None, mu=None, nu=None, k0=0, problem="stokes", renumber="rcm",
+                 stream=None, allocator="torch", prepared=None):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        if prepared is not None:
+            self.dim, self.n_elements = prepared.dim, prepared.n_elements
+        else:
+            self.dim = int(np.asarray(coords).shape[1])
+            self.n_elements = int(np.asarray(elems).shape[0])
         self.device = torch.cuda.current_device()
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         self._alloc = TorchAllocator(self.device) if allocator == "torch" else None
-        m, keep = _mesh(coords, elems)
-        p = _params(mu, nu, k0, problem, renumber)
         h = C.c_void_p()
-        _check(self.lib.cr_assemble(C.byref(m), C.byref(p),
-                                    C.byref(self._alloc.struct) if self._alloc else None,
-                                    C.c_void_p(handle), C.byref(h)))
+        al = C.byref(self._alloc.struct) if self._alloc else None
+        if prepared is not None:
+            _check(self.lib.cr_assemble_prepared(prepared.take(), al, C.c_void_p(handle), C.byref(h)))
+        else:
+            m, keep = _mesh(coords, elems)
+            p = _params(mu, nu, k0, problem, renumber)
+            _check(self.lib.cr_assemble(C.byref(m), C.byref(p), al, C.c_void_p(handle), C.byref(h)))
         self.h = h
         nf, ng, nc = C.c_int64(), C.c_int64(), C.c_int64()
         _check(self.lib.cr_query_sizes(h, C.byref(nf), C.byref(ng), C.byref(nc)))

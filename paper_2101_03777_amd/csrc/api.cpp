@@ -90,92 +90,16 @@ using namespace crh;
 
 namespace crh {
 
-// Host part of the coarse-correction setup: the aggregate of each face
-// (internal order) and, for every nonzero (a, b) of E = Z^t G' Z, the list of
-// element entries (element k, local faces j and l with faces in aggregates a
-// and b) that sum to it, grouped by a counting sort on the pair key.
-cr_status setup_coarse(cr_system* s, const std::vector<int32_t>& eface, std::vector<uint32_t>& eflags) {
-  const Topology& t = s->topo;
-  const int d1 = t.d + 1;
-  const int64_t ne = t.ne;
-  const int m = t.nagg;
-  std::vector<int64_t> count((size_t)m * m + 1, 0);
-  for (int64_t k = 0; k < ne; ++k)
-    for (int j = 0; j < d1; ++j) {
-      const int32_t fj = eface[(size_t)j * ne + k];
-      if (fj < 0) continue;
-      for (int l = 0; l < d1; ++l) {
-        const int32_t fl = eface[(size_t)l * ne + k];
-        if (fl < 0) continue;
-        count[(size_t)t.face_agg[fj] * m + t.face_agg[fl] + 1]++;
-      }
-    }
-  std::vector<int32_t> key, ptr(1, 0);
-  std::vector<int64_t> start((size_t)m * m, -1);
-  int64_t total = 0;
-  for (int64_t q = 0; q < (int64_t)m * m; ++q) {
-    if (!count[q + 1]) continue;
-    start[q] = total;
-    total += count[q + 1];
-    key.push_back((int32_t)q);
-    ptr.push_back((int32_t)total);
-  }
-  if (total >= INT32_MAX) {
-    set_error("coarse correction: too many element entries");
-    return CR_E_INVAL;
-  }
-  std::vector<int32_t> ent((size_t)total);
-  for (int64_t k = 0; k < ne; ++k)
-    for (int j = 0; j < d1; ++j) {
-      const int32_t fj = eface[(size_t)j * ne + k];
-      if (fj < 0) continue;
-      for (int l = 0; l < d1; ++l) {
-        const int32_t fl = eface[(size_t)l * ne + k];
-        if (fl < 0) continue;
-        const int64_t q = (int64_t)t.face_agg[fj] * m + t.face_agg[fl];
-        ent[(size_t)start[q]++] = (int32_t)(k * 16 + j * 4 + l);
-      }
-    }
-  // elements whose interior faces lie in more than one aggregate
-  int64_t nb = 0;
-  for (int64_t k = 0; k < ne; ++k) {
-    int a0 = -1;
-    bool multi = false;
-    for (int j = 0; j < d1; ++j) {
-      const int32_t fj = eface[(size_t)j * ne + k];
-      if (fj < 0) continue;
-      if (a0 < 0) a0 = t.face_agg[fj];
-      else if (t.face_agg[fj] != a0) multi = true;
-    }
-    if (multi) {
-      eflags[k] |= F_AGGB;
-      ++nb;
-    }
-  }
-  s->nbnd = nb;
-  s->nagg = m;
-  s->npairs = (int32_t)key.size();
-  cr_status st = check_hip(hipMemcpy(s->eflags, eflags.data(), sizeof(uint32_t) * ne, hipMemcpyHostToDevice),
-                           "element flags");
-  if (st == CR_OK) st = upload(s, s->fagg, t.face_agg);
-  if (st == CR_OK) st = upload(s, s->pair_ptr, ptr);
-  if (st == CR_OK) st = upload(s, s->pair_key, key);
-  if (st == CR_OK) st = upload(s, s->pair_ent, ent);
-  if (st == CR_OK) st = alloc_n(s, s->Ec, (size_t)m * m);
-  if (st == CR_OK) st = alloc_n(s, s->Einv, (size_t)m * m);
-  if (st == CR_OK) st = alloc_n(s, s->zy32, (size_t)t.nf * t.d);
-  return st;
-}
+// Host tables of a system in internal order, staged for upload.
+struct Staging {
+  std::vector<double> ecoord;
+  std::vector<int32_t> eface, ecaller, enb, fel, floc, fcanon;
+  std::vector<uint32_t> eflags;
+  std::vector<int32_t> pair_ptr, pair_key, pair_ent;  // coarse correction
+  bool coarse = false;
+};
 
-}  // namespace crh
-
-extern "C" {
-
-const char* cr_last_error(void) { return last_error_str(); }
-
-const char* cr_version(void) { return "crhyb 0.1 (gfx950)"; }
-
-static cr_status check_params(const cr_mesh_desc* mesh, const cr_params* p) {
+cr_status check_params(const cr_mesh_desc* mesh, const cr_params* p) {
   if (!mesh || !p) {
     set_error("NULL mesh or params");
     return CR_E_INVAL;
@@ -198,6 +122,223 @@ static cr_status check_params(const cr_mesh_desc* mesh, const cr_params* p) {
   }
   return CR_OK;
 }
+
+
+// Host part of the coarse-correction setup: the aggregate of each face
+// (internal order) and, for every nonzero (a, b) of E = Z^t G' Z, the list of
+// element entries (element k, local faces j and l with faces in aggregates a
+// and b) that sum to it, grouped by a counting sort on the pair key; flags the
+// elements whose interior faces lie in more than one aggregate.
+cr_status coarse_host(cr_system* s, Staging& h) {
+  const Topology& t = s->topo;
+  const int d1 = t.d + 1;
+  const int64_t ne = t.ne;
+  const int m = t.nagg;
+  const std::vector<int32_t>& eface = h.eface;
+  std::vector<int64_t> count((size_t)m * m + 1, 0);
+  for (int64_t k = 0; k < ne; ++k)
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      for (int l = 0; l < d1; ++l) {
+        const int32_t fl = eface[(size_t)l * ne + k];
+        if (fl < 0) continue;
+        count[(size_t)t.face_agg[fj] * m + t.face_agg[fl] + 1]++;
+      }
+    }
+  h.pair_key.clear();
+  h.pair_ptr.assign(1, 0);
+  std::vector<int64_t> start((size_t)m * m, -1);
+  int64_t total = 0;
+  for (int64_t q = 0; q < (int64_t)m * m; ++q) {
+    if (!count[q + 1]) continue;
+    start[q] = total;
+    total += count[q + 1];
+    h.pair_key.push_back((int32_t)q);
+    h.pair_ptr.push_back((int32_t)total);
+  }
+  if (total >= INT32_MAX) {
+    set_error("coarse correction: too many element entries");
+    return CR_E_INVAL;
+  }
+  h.pair_ent.assign((size_t)total, 0);
+  for (int64_t k = 0; k < ne; ++k)
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      for (int l = 0; l < d1; ++l) {
+        const int32_t fl = eface[(size_t)l * ne + k];
+        if (fl < 0) continue;
+        const int64_t q = (int64_t)t.face_agg[fj] * m + t.face_agg[fl];
+        h.pair_ent[(size_t)start[q]++] = (int32_t)(k * 16 + j * 4 + l);
+      }
+    }
+  int64_t nb = 0;
+  for (int64_t k = 0; k < ne; ++k) {
+    int a0 = -1;
+    bool multi = false;
+    for (int j = 0; j < d1; ++j) {
+      const int32_t fj = eface[(size_t)j * ne + k];
+      if (fj < 0) continue;
+      if (a0 < 0) a0 = t.face_agg[fj];
+      else if (t.face_agg[fj] != a0) multi = true;
+    }
+    if (multi) {
+      h.eflags[k] |= F_AGGB;
+      ++nb;
+    }
+  }
+  s->nbnd = nb;
+  s->nagg = m;
+  s->npairs = (int32_t)h.pair_key.size();
+  h.coarse = true;
+  return CR_OK;
+}
+
+// Host part of cr_assemble (no device call): parameters, topology, and the
+// element and face tables in internal order.
+cr_status prepare_host(const cr_mesh_desc* mesh, const cr_params* params, cr_system*& out, Staging& h) {
+  out = nullptr;
+  cr_status st = check_params(mesh, params);
+  if (st != CR_OK) return st;
+  cr_system* s = new (std::nothrow) cr_system();
+  if (!s) return CR_E_NOMEM;
+  s->params = *params;
+  st = build_topology(mesh, params->renumber, params->mu == 0.0,
+                      params->mu > 0.0 && params->problem == CR_STOKES, s->topo);
+  if (st == CR_OK) st = build(s);
+  if (st != CR_OK) {
+    delete s;
+    return st;
+  }
+  const Topology& t = s->topo;
+  const int d = t.d, d1 = d + 1;
+  const int64_t ne = t.ne, nf = t.nf;
+  h.ecoord.assign((size_t)d1 * d * ne, 0.0);
+  h.eface.assign((size_t)d1 * ne, 0);
+  h.ecaller.assign(ne, 0);
+  h.enb.assign((size_t)d1 * ne, 0);
+  h.eflags.assign(ne, 0u);
+  for (int64_t k = 0; k < ne; ++k) {
+    const int32_t c = t.elem_iperm[k];
+    h.ecaller[k] = c;
+    uint32_t fl = 0;
+    for (int j = 0; j < d1; ++j) {
+      const int32_t v = mesh->elem_vertices[(int64_t)c * d1 + j];
+      for (int r = 0; r < d; ++r) h.ecoord[(size_t)(j * d + r) * ne + k] = mesh->coords[(int64_t)v * d + r];
+      const int32_t fc = t.elem_face[(int64_t)c * d1 + j];
+      if (fc >= 0) {
+        h.eface[(size_t)j * ne + k] = t.face_perm[fc];
+        fl |= F_INTERIOR0 << j;
+        const bool owner = t.face_elem[2 * fc] == c;
+        if (!owner) fl |= F_NEG0 << j;
+        const int32_t other = owner ? t.face_elem[2 * fc + 1] : t.face_elem[2 * fc];
+        h.enb[(size_t)j * ne + k] = t.elem_perm[other];
+      } else {
+        h.eface[(size_t)j * ne + k] = -1;
+        h.enb[(size_t)j * ne + k] = -1;
+      }
+    }
+    if (c == params->k0) {
+      fl |= F_K0;
+      s->k0i = k;
+    }
+    if (t.m1[c]) fl |= F_M1;
+    h.eflags[k] = fl;
+  }
+  h.fel.assign((size_t)2 * nf, 0);
+  h.floc.assign(nf, 0);
+  h.fcanon.assign(nf, 0);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t fc = t.face_iperm[f];
+    h.fcanon[f] = fc;
+    h.fel[f] = t.elem_perm[t.face_elem[2 * fc]];
+    h.fel[nf + f] = t.elem_perm[t.face_elem[2 * fc + 1]];
+    h.floc[f] = (int32_t)t.face_loc[2 * fc] | ((int32_t)t.face_loc[2 * fc + 1] << 8);
+  }
+  const bool ns = params->problem == CR_NS_NEWTON;
+  if (!ns && params->mu > 0.0 && t.nagg > 0) st = coarse_host(s, h);
+  if (st != CR_OK) {
+    delete s;
+    return st;
+  }
+  out = s;
+  return CR_OK;
+}
+
+// Device part of cr_assemble: uploads the staged tables and allocates the
+// system's device arrays on its stream; releases the system on failure.
+cr_status finish_device(cr_system* s, Staging& h, const cr_allocator* alloc, void* hip_stream) {
+  s->stream = (hipStream_t)hip_stream;
+  if (alloc && alloc->alloc && alloc->release) {
+    s->alloc = *alloc;
+    s->has_alloc = true;
+  }
+  cr_status st = check_hip(hipGetDevice(&s->device), "hipGetDevice");
+  const Topology& t = s->topo;
+  const int d = t.d, d1 = d + 1;
+  const int64_t ne = t.ne, nf = t.nf;
+  const bool ns = s->params.problem == CR_NS_NEWTON;
+  const size_t nslot = 2 * d + 1, nvec = (size_t)nf * d;
+  if (st == CR_OK) st = upload(s, s->ecoord, h.ecoord);
+  if (st == CR_OK) st = upload(s, s->eface, h.eface);
+  if (st == CR_OK) st = upload(s, s->eflags, h.eflags);
+  if (st == CR_OK) st = upload(s, s->ecaller, h.ecaller);
+  if (st == CR_OK) st = upload(s, s->enb, h.enb);
+  if (st == CR_OK) st = upload(s, s->fel, h.fel);
+  if (st == CR_OK) st = upload(s, s->floc, h.floc);
+  if (st == CR_OK) st = upload(s, s->fcanon, h.fcanon);
+  if (st == CR_OK) st = alloc_n(s, s->cols, (size_t)2 * d * nf);
+  if (st == CR_OK) st = alloc_n(s, s->pack, (size_t)s->npack * ne);
+  if (st == CR_OK) st = alloc_n(s, s->RK, (size_t)d1 * d * ne);
+  if (st == CR_OK) st = alloc_n(s, s->sK, (size_t)d1 * d * ne);
+  if (st == CR_OK) st = alloc_n(s, s->lam, (size_t)ne);
+  if (st == CR_OK) st = alloc_n(s, s->G64, nslot * d * d * nf);
+  if (st == CR_OK) st = alloc_n(s, s->G32, nslot * d * d * nf);
+  if (st == CR_OK) st = alloc_n(s, s->dsq, nvec);
+  if (st == CR_OK && !ns && s->params.mu > 0.0) {
+    // element-factor form of the scaled operator (transient Stokes CG)
+    const size_t nplanes = (size_t)d1 * (d1 + 1) / 2 + (size_t)d1 * d;
+    st = alloc_n(s, s->efo64, nplanes * ne);
+    if (st == CR_OK) st = alloc_n(s, s->efo32, nplanes * ne);
+    if (st == CR_OK) st = alloc_n(s, s->egat, (size_t)d1 * ne);
+    if (st == CR_OK) st = alloc_n(s, s->bs1, nvec);
+    if (st == CR_OK) st = alloc_n(s, s->zy, nvec);
+    if (st == CR_OK) st = alloc_n(s, s->k0t, (size_t)1);
+    if (st == CR_OK && h.coarse) {
+      const size_t m = (size_t)s->nagg;
+      st = upload(s, s->fagg, t.face_agg);
+      if (st == CR_OK) st = upload(s, s->pair_ptr, h.pair_ptr);
+      if (st == CR_OK) st = upload(s, s->pair_key, h.pair_key);
+      if (st == CR_OK) st = upload(s, s->pair_ent, h.pair_ent);
+      if (st == CR_OK) st = alloc_n(s, s->Ec, m * m);
+      if (st == CR_OK) st = alloc_n(s, s->Einv, m * m);
+      if (st == CR_OK) st = alloc_n(s, s->zy32, nvec);
+    }
+  }
+  if (st == CR_OK) st = alloc_n(s, s->bs, nvec);
+  if (st == CR_OK) st = alloc_n(s, s->y, nvec);
+  if (st == CR_OK) st = alloc_n(s, s->fbar, (size_t)ne * d);
+  if (st == CR_OK) st = alloc_n(s, s->uprev, nvec);
+  if (st == CR_OK && ns) st = alloc_n(s, s->ulin, nvec);
+  if (st == CR_OK) st = alloc_n(s, s->err, 4);
+  // the staged host tables are read by the uploads until the stream drains
+  if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "upload sync");
+  if (st != CR_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    release_all(s);
+    delete s;
+  }
+  return st;
+}
+
+}  // namespace crh
+
+extern "C" {
+
+const char* cr_last_error(void) { return last_error_str(); }
+
+const char* cr_version(void) { return "crhyb 0.1 (gfx950)"; }
 
 cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t* n_int_faces, int32_t* perm,
                       int64_t* bw_int, int64_t* bw_can, int32_t* m1) {
@@ -225,109 +366,57 @@ cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params, const c
     return CR_E_INVAL;
   }
   *out = nullptr;
-  cr_status st = check_params(mesh, params);
-  if (st != CR_OK) return st;
-  cr_system* s = new (std::nothrow) cr_system();
-  if (!s) return CR_E_NOMEM;
-  s->params = *params;
-  s->stream = (hipStream_t)hip_stream;
-  if (alloc && alloc->alloc && alloc->release) {
-    s->alloc = *alloc;
-    s->has_alloc = true;
+  cr_system* s = nullptr;
+  Staging h;
+  cr_status st = prepare_host(mesh, params, s, h);
+  if (st == CR_OK) st = finish_device(s, h, alloc, hip_stream);
+  if (st == CR_OK) *out = s;
+  return st;
+}
+
+struct cr_prepared {
+  cr_system* s = nullptr;
+  crh::Staging h;
+};
+
+cr_status cr_prepare(const cr_mesh_desc* mesh, const cr_params* params, cr_prepared** out) {
+  clear_error();
+  if (!out) {
+    set_error("NULL output pointer");
+    return CR_E_INVAL;
   }
-  st = build_topology(mesh, params->renumber, params->mu == 0.0,
-                      params->mu > 0.0 && params->problem == CR_STOKES, s->topo);
-  if (st == CR_OK) st = build(s);
-  if (st == CR_OK) st = check_hip(hipGetDevice(&s->device), "hipGetDevice");
+  *out = nullptr;
+  cr_prepared* p = new (std::nothrow) cr_prepared();
+  if (!p) return CR_E_NOMEM;
+  const cr_status st = prepare_host(mesh, params, p->s, p->h);
   if (st != CR_OK) {
-    delete s;
+    delete p;
     return st;
   }
-  const Topology& t = s->topo;
-  const int d = t.d, d1 = d + 1;
-  const int64_t ne = t.ne, nf = t.nf;
-  const bool ns = params->problem == CR_NS_NEWTON;
-  // host staging in internal order
-  std::vector<double> ecoord((size_t)d1 * d * ne);
-  std::vector<int32_t> eface((size_t)d1 * ne), ecaller(ne), enb((size_t)d1 * ne);
-  std::vector<uint32_t> eflags(ne);
-  for (int64_t k = 0; k < ne; ++k) {
-    const int32_t c = t.elem_iperm[k];
-    ecaller[k] = c;
-    uint32_t fl = 0;
-    for (int j = 0; j < d1; ++j) {
-      const int32_t v = mesh->elem_vertices[(int64_t)c * d1 + j];
-      for (int r = 0; r < d; ++r) ecoord[(size_t)(j * d + r) * ne + k] = mesh->coords[(int64_t)v * d + r];
-      const int32_t fc = t.elem_face[(int64_t)c * d1 + j];
-      if (fc >= 0) {
-        eface[(size_t)j * ne + k] = t.face_perm[fc];
-        fl |= F_INTERIOR0 << j;
-        const bool owner = t.face_elem[2 * fc] == c;
-        if (!owner) fl |= F_NEG0 << j;
-        const int32_t other = owner ? t.face_elem[2 * fc + 1] : t.face_elem[2 * fc];
-        enb[(size_t)j * ne + k] = t.elem_perm[other];
-      } else {
-        eface[(size_t)j * ne + k] = -1;
-        enb[(size_t)j * ne + k] = -1;
-      }
-    }
-    if (c == params->k0) {
-      fl |= F_K0;
-      s->k0i = k;
-    }
-    if (t.m1[c]) fl |= F_M1;
-    eflags[k] = fl;
-  }
-  std::vector<int32_t> fel((size_t)2 * nf), floc(nf), fcanon(nf);
-  for (int64_t f = 0; f < nf; ++f) {
-    const int32_t fc = t.face_iperm[f];
-    fcanon[f] = fc;
-    fel[f] = t.elem_perm[t.face_elem[2 * fc]];
-    fel[nf + f] = t.elem_perm[t.face_elem[2 * fc + 1]];
-    floc[f] = (int32_t)t.face_loc[2 * fc] | ((int32_t)t.face_loc[2 * fc + 1] << 8);
-  }
-  const size_t nslot = 2 * d + 1, nvec = (size_t)nf * d;
-  st = upload(s, s->ecoord, ecoord);
-  if (st == CR_OK) st = upload(s, s->eface, eface);
-  if (st == CR_OK) st = upload(s, s->eflags, eflags);
-  if (st == CR_OK) st = upload(s, s->ecaller, ecaller);
-  if (st == CR_OK) st = upload(s, s->enb, enb);
-  if (st == CR_OK) st = upload(s, s->fel, fel);
-  if (st == CR_OK) st = upload(s, s->floc, floc);
-  if (st == CR_OK) st = upload(s, s->fcanon, fcanon);
-  if (st == CR_OK) st = alloc_n(s, s->cols, (size_t)2 * d * nf);
-  if (st == CR_OK) st = alloc_n(s, s->pack, (size_t)s->npack * ne);
-  if (st == CR_OK) st = alloc_n(s, s->RK, (size_t)d1 * d * ne);
-  if (st == CR_OK) st = alloc_n(s, s->sK, (size_t)d1 * d * ne);
-  if (st == CR_OK) st = alloc_n(s, s->lam, (size_t)ne);
-  if (st == CR_OK) st = alloc_n(s, s->G64, nslot * d * d * nf);
-  if (st == CR_OK) st = alloc_n(s, s->G32, nslot * d * d * nf);
-  if (st == CR_OK) st = alloc_n(s, s->dsq, nvec);
-  if (st == CR_OK && !ns && s->params.mu > 0.0) {
-    // element-factor form of the scaled operator (transient Stokes CG)
-    const size_t nplanes = (size_t)d1 * (d1 + 1) / 2 + (size_t)d1 * d;
-    st = alloc_n(s, s->efo64, nplanes * ne);
-    if (st == CR_OK) st = alloc_n(s, s->efo32, nplanes * ne);
-    if (st == CR_OK) st = alloc_n(s, s->egat, (size_t)d1 * ne);
-    if (st == CR_OK) st = alloc_n(s, s->bs1, nvec);
-    if (st == CR_OK) st = alloc_n(s, s->zy, nvec);
-    if (st == CR_OK) st = alloc_n(s, s->k0t, (size_t)1);
-    if (st == CR_OK && t.nagg > 0) st = setup_coarse(s, eface, eflags);
-  }
-  if (st == CR_OK) st = alloc_n(s, s->bs, nvec);
-  if (st == CR_OK) st = alloc_n(s, s->y, nvec);
-  if (st == CR_OK) st = alloc_n(s, s->fbar, (size_t)ne * d);
-  if (st == CR_OK) st = alloc_n(s, s->uprev, nvec);
-  if (st == CR_OK && ns) st = alloc_n(s, s->ulin, nvec);
-  if (st == CR_OK) st = alloc_n(s, s->err, 4);
-  if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "upload sync");
-  if (st != CR_OK) {
-    release_all(s);
-    delete s;
-    return st;
-  }
-  *out = s;
+  *out = p;
   return CR_OK;
+}
+
+cr_status cr_assemble_prepared(cr_prepared* prep, const cr_allocator* alloc, void* hip_stream, cr_system** out) {
+  clear_error();
+  if (!prep || !out || !prep->s) {
+    set_error("NULL prepared mesh or output pointer");
+    delete prep;
+    return CR_E_INVAL;
+  }
+  *out = nullptr;
+  cr_system* s = prep->s;
+  prep->s = nullptr;
+  const cr_status st = finish_device(s, prep->h, alloc, hip_stream);
+  delete prep;
+  if (st == CR_OK) *out = s;
+  return st;
+}
+
+void cr_prepared_destroy(cr_prepared* prep) {
+  if (!prep) return;
+  delete prep->s;
+  delete prep;
 }
 
 cr_status cr_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin) {

@@ -103,3 +103,26 @@ def test_topology_errors():
     with pytest.raises(crh.CRError) as e:
         crh.topology(coords[:3], np.array([[0, 1, 3]], dtype=np.int32) % 3)
     assert e.value.status == -3
+
+
+def test_prepare_is_host_only():
+    """cr_prepare (the host part of cr_assemble) runs without a device, with and
+    without the aggregates of the coarse correction, and reports bad input."""
+    lib = crh.load()
+    coords, elems = synth.square_mesh(64, jitter=0.2, seed=3)  # 8192 elements: 4 aggregates
+    for mu, problem in ((100.0, "stokes"), (0.0, "stokes"), (0.0, "ns")):
+        p = crh.Prepared(coords, elems, mu=mu, nu=1.0, problem=problem)
+        assert p.n_elements == len(elems) and p.dim == 2
+        h = p.take()
+        with pytest.raises(ValueError):
+            p.take()
+        lib.cr_prepared_destroy(h)
+    c3, e3 = synth.cube_mesh(3)
+    crh.Prepared(c3, e3, mu=10.0, nu=1.0)  # released by its destructor
+    lib.cr_prepared_destroy(None)
+    with pytest.raises(crh.CRError) as e:
+        crh.Prepared(coords, elems, mu=1.0, nu=0.0)
+    assert e.value.status == -1
+    with pytest.raises(crh.CRError) as e:
+        crh.Prepared(coords[:3], np.array([[0, 1, 2]], dtype=np.int32), mu=1.0, nu=1.0)
+    assert e.value.status == -3

@@ -321,3 +321,25 @@ def test_serving_mix_equals_solo(gpu):
             assert np.array_equal(U.cpu().numpy(), Us), (i, step)
             assert np.array_equal(Pk.cpu().numpy(), Ps), (i, step)
         s.close()
+
+
+def test_prepared_assembly_equals_direct(gpu):
+    """cr_prepare + cr_assemble_prepared (host part on a worker thread) builds the
+    same system as cr_assemble: bitwise equal W and iteration count, with the
+    coarse correction (128 x 128 x 2: 16 aggregates) and without (steady case)."""
+    import concurrent.futures
+    for n, mu, method in [(128, 1000.0, "pcg"), (24, 0.0, "minres")]:
+        co, el = synth.square_mesh(n, jitter=0.2, seed=7)
+        fb = dev(np.random.default_rng(n).normal(size=(len(el), 2)))
+        with concurrent.futures.ThreadPoolExecutor(1) as ex:
+            prep = ex.submit(gpu.Prepared, co, el, mu=mu, nu=1.0).result()
+        out = []
+        for s in (gpu.System(co, el, mu, 1.0), gpu.System(prepared=prep)):
+            assert s.n_elements == len(el)
+            s.eliminate(fb)
+            info = s.solve(method, "fp64", tol=1e-10)
+            out.append((s.export_W(), info["iters"], info["status"]))
+            s.close()
+        assert out[0][2] == 0 and out[1][2] == 0
+        assert out[0][1] == out[1][1]
+        assert np.array_equal(out[0][0], out[1][0])
