@@ -23,7 +23,7 @@ void* dev_alloc(cr_system* s, size_t bytes) {
   if (s->has_alloc) {
     p = s->alloc.alloc(bytes, s->alloc.ctx, (void*)s->stream);
   } else if (hipMalloc(&p, bytes) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     p = nullptr;
   }
   if (p)
@@ -42,7 +42,7 @@ void release_all(cr_system* s) {
     if (s->has_alloc)
       s->alloc.release(p, s->alloc.ctx, (void*)s->stream);
     else
-      hipFree(p);
+      (void)hipFree(p);
   }
   s->owned.clear();
 }
@@ -650,7 +650,7 @@ cr_status cr_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* 
 
 void cr_destroy(cr_system* s) {
   if (!s) return;
-  hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->stream);
   release_all(s);
   delete s;
 }

@@ -527,8 +527,8 @@ cr_status ensure_cws(cr_system* s, CWs*& w) {
 void free_cws(CWs* w) {
   if (!w) return;
   for (auto& e : w->ev)
-    if (e) hipEventDestroy(e);
-  if (w->hst) hipHostFree(w->hst);
+    if (e) (void)hipEventDestroy(e);
+  if (w->hst) (void)hipHostFree(w->hst);
   delete w;
 }
 
@@ -593,8 +593,11 @@ cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* inf
     for (;;) {
       enqueue_mr<D>(s, w, issued * blk, blk);
       ++issued;
-      hipMemcpyAsync(&w->hst[0], w->st, sizeof(CState), hipMemcpyDeviceToHost, s->stream);
-      st = check_hip(hipStreamSynchronize(s->stream), "coupled poll");
+      st = check_hip(hipGetLastError(), "coupled launch");
+      if (st == CR_OK)
+        st = check_hip(hipMemcpyAsync(&w->hst[0], w->st, sizeof(CState), hipMemcpyDeviceToHost, s->stream),
+                       "coupled state copy");
+      if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "coupled poll");
       if (st != CR_OK) break;
       ks = w->hst[0];
       if (ks.done || issued >= max_blocks) break;

@@ -1759,7 +1759,7 @@ cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
     return CR_OK;
   }
   if (ex) {
-    hipGraphExecDestroy(ex);
+    (void)hipGraphExecDestroy(ex);
     ex = nullptr;
   }
   hipGraph_t g = nullptr;
@@ -1771,11 +1771,11 @@ cr_status get_graph(const Launch& L, int npairs, hipGraphExec_t& out) {
   if (st != CR_OK) return st;
   st = check_hip(le, "captured launch");
   if (st != CR_OK) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return st;
   }
   st = check_hip(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (st != CR_OK) return st;
   exm = npairs;
   out = ex;
@@ -1792,27 +1792,33 @@ cr_status run_inner(const Launch& L, int npairs, bool graph, int max_blocks, KSt
     cr_status st = get_graph(L, npairs, exec);
     if (st != CR_OK) return st;
   }
+  // one iteration block, then the copy of its state and the event the host polls
   auto launch = [&](int slot) {
+    hipError_t e = hipSuccess;
     if (graph)
-      hipGraphLaunch(exec, s->stream);
+      e = hipGraphLaunch(exec, s->stream);
     else
       enqueue_iters(L, s->stream, npairs);
-    hipMemcpyAsync(&w->hst[slot], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
-    hipEventRecord(w->ev[slot], s->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&w->hst[slot], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(w->ev[slot], s->stream);
+    return check_hip(e, "inner launch");
   };
   int issued = 0, slot = 0;
-  for (int k = 0; k < 2 && issued < max_blocks; ++k) launch(issued++ & 1);
-  cr_status st = check_hip(hipGetLastError(), "inner launch");
+  cr_status st = CR_OK;
+  for (int k = 0; k < 2 && issued < max_blocks && st == CR_OK; ++k) st = launch(issued++ & 1);
   if (st != CR_OK) return st;
   for (;;) {
     st = check_hip(hipEventSynchronize(w->ev[slot]), "inner poll");
     if (st != CR_OK) return st;
     if (w->hst[slot].done || issued >= max_blocks) break;
-    launch(slot);
+    st = launch(slot);
+    if (st != CR_OK) return st;
     ++issued;
     slot ^= 1;
   }
-  hipMemcpyAsync(&w->hst[2], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream);
+  st = check_hip(hipMemcpyAsync(&w->hst[2], L.st, sizeof(KState), hipMemcpyDeviceToHost, s->stream), "state copy");
+  if (st != CR_OK) return st;
   st = check_hip(hipStreamSynchronize(s->stream), "inner sync");
   if (st != CR_OK) return st;
   out = w->hst[2];
@@ -2017,8 +2023,11 @@ cr_status run_minres(cr_system* s, KWs* w, const cr_solve_opts* o, cr_solve_info
       for (;;) {
         enqueue_minres<D, T>(s, w, S, issued * blk, blk);
         ++issued;
-        hipMemcpyAsync(w->mhst, w->mst, sizeof(MState), hipMemcpyDeviceToHost, s->stream);
-        st = check_hip(hipStreamSynchronize(s->stream), "MINRES poll");
+        st = check_hip(hipGetLastError(), "MINRES launch");
+        if (st == CR_OK)
+          st = check_hip(hipMemcpyAsync(w->mhst, w->mst, sizeof(MState), hipMemcpyDeviceToHost, s->stream),
+                         "MINRES state copy");
+        if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "MINRES poll");
         if (st != CR_OK) break;
         ks = *w->mhst;
         if (ks.done || issued >= max_blocks) break;
@@ -2235,25 +2244,27 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
         hipLaunchKernelGGL(k_coarse, dim3((S.nagg + 3) / 4), blk, 0, s->stream, S);
       }
     });
+    if (st == CR_OK) st = check_hip(hipGetLastError(), "timing launch");
     if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "timing");
     double tot = 0.0;
     for (int k = 0; k < reps && st == CR_OK; ++k) {
       float e = 0.f;
-      hipEventElapsedTime(&e, ev[2 * k], ev[2 * k + 1]);
+      st = check_hip(hipEventElapsedTime(&e, ev[2 * k], ev[2 * k + 1]), "timing events");
       tot += e;
     }
     for (auto& e : ev)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     if (st != CR_OK) return st;
     ms = (float)tot;
   } else {
     launch();  // warm-up
-    hipEventRecord(w->t0, s->stream);
-    for (int k = 0; k < reps; ++k) launch();
-    hipEventRecord(w->t1, s->stream);
-    st = check_hip(hipEventSynchronize(w->t1), "timing");
+    st = check_hip(hipEventRecord(w->t0, s->stream), "timing");
+    for (int k = 0; k < reps && st == CR_OK; ++k) launch();
+    if (st == CR_OK) st = check_hip(hipGetLastError(), "timing launch");
+    if (st == CR_OK) st = check_hip(hipEventRecord(w->t1, s->stream), "timing");
+    if (st == CR_OK) st = check_hip(hipEventSynchronize(w->t1), "timing");
+    if (st == CR_OK) st = check_hip(hipEventElapsedTime(&ms, w->t0, w->t1), "timing events");
     if (st != CR_OK) return st;
-    hipEventElapsedTime(&ms, w->t0, w->t1);
   }
   if (avg_ms) *avg_ms = (double)ms / reps;
   if (bytes) {
@@ -2284,14 +2295,14 @@ void free_krylov(cr_system* s) {
   for (auto& a : w->exec)
     for (auto& b : a)
       for (auto& e : b)
-        if (e) hipGraphExecDestroy(e);
+        if (e) (void)hipGraphExecDestroy(e);
   for (auto& e : w->ev)
-    if (e) hipEventDestroy(e);
-  if (w->t0) hipEventDestroy(w->t0);
-  if (w->t1) hipEventDestroy(w->t1);
-  if (w->cap) hipStreamDestroy(w->cap);
-  if (w->hst) hipHostFree(w->hst);
-  if (w->mhst) hipHostFree(w->mhst);
+    if (e) (void)hipEventDestroy(e);
+  if (w->t0) (void)hipEventDestroy(w->t0);
+  if (w->t1) (void)hipEventDestroy(w->t1);
+  if (w->cap) (void)hipStreamDestroy(w->cap);
+  if (w->hst) (void)hipHostFree(w->hst);
+  if (w->mhst) (void)hipHostFree(w->mhst);
   delete w;
   s->kws = nullptr;
 }
@@ -2561,7 +2572,7 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
                         b->nblocksC[0], b->nblocksC[1], npairs, b->op};
     if (!b->exec || !std::equal(key, key + 8, b->exec_key)) {
       if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
       }
       if (!b->cap) st = check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "batch capture stream");
@@ -2573,7 +2584,7 @@ cr_status cr_batch_advance(cr_batch* b, int32_t n_iters, int32_t* n_finished) {
         st = check_hip(hipStreamEndCapture(b->cap, &g), "batch capture");
         if (st == CR_OK) st = check_hip(le, "batch captured launch");
         if (st == CR_OK) st = check_hip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "batch graph");
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
       }
       if (st != CR_OK) return st;
       std::copy(key, key + 8, b->exec_key);
@@ -2652,20 +2663,20 @@ cr_status cr_batch_count(const cr_batch* b, int32_t* n_active, int32_t* n_finish
 
 void cr_batch_destroy(cr_batch* b) {
   if (!b) return;
-  if (b->stream || b->dst) hipStreamSynchronize(b->stream);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->cap) hipStreamDestroy(b->cap);
-  if (b->dst) hipFree(b->dst);
-  if (b->hst) hipHostFree(b->hst);
+  if (b->stream || b->dst) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->dst) (void)hipFree(b->dst);
+  if (b->hst) (void)hipHostFree(b->hst);
   for (int pi = 0; pi < 2; ++pi) {
-    if (b->dtab[pi]) hipFree(b->dtab[pi]);
-    if (b->dmap[pi]) hipFree(b->dmap[pi]);
-    if (b->dmapE[pi]) hipFree(b->dmapE[pi]);
-    if (b->dmapC[pi]) hipFree(b->dmapC[pi]);
-    if (b->htab[pi]) hipHostFree(b->htab[pi]);
-    if (b->hmap[pi]) hipHostFree(b->hmap[pi]);
-    if (b->hmapE[pi]) hipHostFree(b->hmapE[pi]);
-    if (b->hmapC[pi]) hipHostFree(b->hmapC[pi]);
+    if (b->dtab[pi]) (void)hipFree(b->dtab[pi]);
+    if (b->dmap[pi]) (void)hipFree(b->dmap[pi]);
+    if (b->dmapE[pi]) (void)hipFree(b->dmapE[pi]);
+    if (b->dmapC[pi]) (void)hipFree(b->dmapC[pi]);
+    if (b->htab[pi]) (void)hipHostFree(b->htab[pi]);
+    if (b->hmap[pi]) (void)hipHostFree(b->hmap[pi]);
+    if (b->hmapE[pi]) (void)hipHostFree(b->hmapE[pi]);
+    if (b->hmapC[pi]) (void)hipHostFree(b->hmapC[pi]);
   }
   delete b;
 }
