@@ -45,7 +45,7 @@ def log(*a):
 # source of the dominant kernel: its own code, the shared iteration start and
 # stopping logic, the structs it reads, and the row/element helpers
 KERNEL_PARTS = ("struct KState", "struct CgSys", "struct Decision", "Decision decide(", "void record_decision(",
-                "bool cg_head(", "double coarse_dot(", "void ec1_pass(", "void ec1_body(", "k_ec1(CgSys S")
+                "bool cg_head(", "void ec1_pass(", "void ec1_body(", "k_ec1(CgSys S")
 
 
 def _block(text, key):

@@ -339,34 +339,37 @@ __device__ __forceinline__ void record_decision(KState* st, const Decision& d, b
 // ---------------------------------------------------------------------------
 // Start of a CG iteration (parity par), shared by both operator forms: reduces
 // r.r (and after a replacement the true residual and ||S||) from the face
-// partials Pa, applies the stopping logic (the workgroup with logical index 0
-// records it) and returns false if the iteration does not run; else sets beta
-// and whether this iteration starts a new direction.
+// partials Pa, with the coarse correction also c . mu over the aggregates
+// (rho = r.M^-1 r = r.r + c.E^-1 c), applies the stopping logic (the
+// workgroup with logical index 0 records it) and returns false if the
+// iteration does not run; else sets beta and whether this iteration starts a
+// new direction.  The state words and all the sums' inputs are requested
+// before any is used, and one workgroup reduction forms every sum (each in the
+// same order as its own reduction would).
 __device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f32, double& beta, bool& first,
-                                        double coarse = 0.0) {
+                                        bool with_coarse = false) {
   KState* st = S.st;
-  if (st->done) return false;
+  const int done = st->done;
   const int it = st->it[par ^ 1];
-  first = it == st->it_first;
-  const bool fresh = it == st->it_rep;
-  double rr, tres2 = 0.0, snorm2 = 0.0;
-  if (fresh) {
-    const int fl[3] = {0, 1, 2};
-    double v[3];
-    reduce_fields<3>(S.Pa, S.P.nblk, fl, v);
-    rr = v[0];
-    tres2 = v[1];
-    snorm2 = v[2];
-  } else {
-    const int fl[1] = {0};
-    double v[1];
-    reduce_fields<1>(S.Pa, S.P.nblk, fl, v);
-    rr = v[0];
+  const int it_first = st->it_first, it_rep = st->it_rep;
+  const double gam_old = st->gam[par ^ 1];
+  const int nblk = S.P.nblk;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += NT) {
+    v[0] += S.Pa[i];
+    v[1] += S.Pa[(int64_t)nblk + i];
+    v[2] += S.Pa[(int64_t)2 * nblk + i];
   }
+  if (with_coarse)
+    for (int a = threadIdx.x; a < S.nagg; a += NT) v[3] += S.cvec[a] * S.mu[a];
+  if (done) return false;
+  block_sum<4>(v);
+  first = it == it_first;
+  const bool fresh = it == it_rep;
+  const double rr = v[0], tres2 = fresh ? v[1] : 0.0, snorm2 = fresh ? v[2] : 0.0, coarse = v[3];
   const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, f32);
   if (threadIdx.x == 0 && lb == 0) record_decision(st, dec, fresh, it, rr, tres2, snorm2);
-  // rho = r . M^-1 r = r.r + c . E^-1 c with the coarse correction
-  beta = first ? 0.0 : (rr + coarse) / st->gam[par ^ 1];
+  beta = first ? 0.0 : (rr + coarse) / gam_old;
   if (threadIdx.x == 0 && lb == 0 && !dec.done) {
     st->gam[par] = rr + coarse;
     st->bet[par] = beta;
@@ -375,14 +378,6 @@ __device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f3
   }
   if (dec.done) return false;
   return true;
-}
-
-// c . mu over the aggregates, summed in the same order by every workgroup
-__device__ __forceinline__ double coarse_dot(const CgSys& S) {
-  double v[1] = {0.0};
-  for (int a = threadIdx.x; a < S.nagg; a += NT) v[0] += S.cvec[a] * S.mu[a];
-  block_sum<1>(v);
-  return v[0];
 }
 
 template <int D, typename T, int OP>
@@ -617,9 +612,7 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   constexpr int EB = ec1_batch<D, T>();
   double beta_d;
   bool first;
-  if (S.st->done) return;
-  const double cd = S.nagg > 0 ? coarse_dot(S) : 0.0;
-  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, cd)) return;
+  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, S.nagg > 0)) return;
   const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(S.ne, lo + S.PE.chunk);
   double acc[1] = {0.0};
   if (EB > 1 && S.PE.chunk >= (int64_t)EB * NT)
@@ -634,16 +627,30 @@ template <int D, typename T>
 __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
   constexpr int N = D + 1;
   KState* st = S.st;
-  if (st->done) return;
-  const int fl0[1] = {0};
-  double v[1];
-  reduce_fields<1>(S.Pb, S.PE.nblk, fl0, v);
+  // the state words, the partials of p.G~p and the coarse values of this
+  // block's aggregates are all requested before any is used
+  const int done = st->done;
+  const double gam = st->gam[par], cbeta = st->bet[par];
+  const bool cfirst = st->it[par] - 1 == st->it_first;
+  const int a0 = S.nagg > 0 ? S.ablk[lb] : 0;
+  const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < S.PE.nblk; i += NT) v[0] += S.Pb[i];
+  double mu_k[KMAX], mo_k[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int a = min(a0 + k, S.nagg - 1);
+    mu_k[k] = S.nagg > 0 ? S.mu[a] : 0.0;
+    mo_k[k] = S.nagg > 0 ? mold[a] : 0.0;
+  }
+  if (done) return;
+  block_sum<1>(v);
   const double pq = v[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (threadIdx.x == 0 && lb == 0) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
     return;
   }
-  const double alpha = st->gam[par] / pq;
+  const double alpha = gam / pq;
   const T ta = (T)alpha;
   const Part P = S.P;
   T* __restrict__ x = (T*)S.x;
@@ -651,20 +658,13 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
   const T* __restrict__ p = (const T*)(par ? S.p1 : S.p);
   const T* __restrict__ tq = (const T*)S.tq;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
-  const int a0 = S.nagg > 0 ? S.ablk[lb] : 0;
-  const double cbeta = st->bet[par];
-  const bool cfirst = st->it[par] - 1 == st->it_first;
-  const double* __restrict__ mold = S.nagg > 0 ? S.M2 + (par ^ 1) * S.nagg : nullptr;
   if (S.nagg > 0 && lb == 0)  // the coarse part m of this iteration's direction
     for (int a = threadIdx.x; a < S.nagg; a += NT)
       S.M2[par * S.nagg + a] = cfirst ? S.mu[a] : S.mu[a] + cbeta * mold[a];
   // m of the (at most KMAX) aggregates of this block's faces
   T mk[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const int a = min(a0 + k, S.nagg - 1);
-    mk[k] = S.nagg > 0 ? (T)(cfirst ? S.mu[a] : S.mu[a] + cbeta * mold[a]) : T(0);
-  }
+  for (int k = 0; k < KMAX; ++k) mk[k] = S.nagg > 0 ? (T)(cfirst ? mu_k[k] : mu_k[k] + cbeta * mo_k[k]) : T(0);
   double acc[1] = {0.0};
   double racc[KMAX] = {};
   for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
