@@ -209,6 +209,19 @@ cr_status cr_query_sizes(const cr_system* sys, int64_t* n_int_faces, int64_t* nn
  * Synchronises. */
 cr_status cr_export_G(const cr_system* sys, int64_t* rowptr, int32_t* col, double* val, double* S);
 
+/* Host copy of the coupled system of Section 3.1 (eq. syslin), Stokes only:
+ * [A D^t; D 0] as FP64 CSR and its right-hand side [R; 0].  Rows and columns:
+ * the velocity unknowns (canonical face, component), then one pressure per
+ * element in caller order without k0 (P_k0 = 0 is not an unknown), so
+ * n = dim * n_int_faces + n_elements - 1.  A = sum_K H_K (S_K (x) I_d) H_K^t,
+ * D_K = -a_K (rows of K0 dropped), R = sum_K H_K R_K, columns sorted within a
+ * row, nnz = nnz_coupled of cr_query_sizes (structural entries, zeros kept).
+ * Buffers (host): rowptr [n+1], col [nnz], val [nnz], R [n]; any may be NULL.
+ * Assembled on the device with the coupled baseline's kernels (its workspace
+ * is allocated on first use); synchronises.  Errors: CR_E_INVAL (NULL system,
+ * not eliminated, Navier-Stokes), CR_E_NOMEM, CR_E_DEVICE. */
+cr_status cr_export_coupled(cr_system* sys, int64_t* rowptr, int32_t* col, double* val, double* R);
+
 /* Host copy of the resident W [n_int_faces][dim] (canonical). Synchronises. */
 cr_status cr_export_W(const cr_system* sys, double* W);
 

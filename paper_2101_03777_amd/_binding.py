@@ -31,7 +31,7 @@ EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recov
            "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
            "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
            "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy", "cr_prepare",
-           "cr_assemble_prepared", "cr_prepared_destroy"]
+           "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled"]
 
 
 class CRError(RuntimeError):
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
         "cr_query_sizes": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
         "cr_export_G": (I32, [P, P, P, P, P]),
         "cr_export_W": (I32, [P, P]),
+        "cr_export_coupled": (I32, [P, P, P, P, P]),
         "cr_import_W": (I32, [P, P]),
         "cr_interior_faces": (I32, [P, P]),
         "cr_topology": (I32, [C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(I64), P, C.POINTER(I64),
@@ -388,6 +389,17 @@ class System:
         S = np.empty(n, dtype=np.float64)
         _check(self.lib.cr_export_G(self.h, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(S)))
         return sps.csr_matrix((val, col, rowptr), shape=(n, n)), S
+
+    def export_coupled(self):
+        """The coupled matrix [A D^t; D 0] (scipy CSR) and [R; 0], Stokes only."""
+        import scipy.sparse as sps
+        n = self.n_int_faces * self.dim + self.n_elements - 1
+        rowptr = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(self.nnz_coupled, dtype=np.int32)
+        val = np.empty(self.nnz_coupled, dtype=np.float64)
+        R = np.empty(n, dtype=np.float64)
+        _check(self.lib.cr_export_coupled(self.h, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(R)))
+        return sps.csr_matrix((val, col, rowptr), shape=(n, n)), R
 
     def export_W(self):
         W = np.empty((self.n_int_faces, self.dim), dtype=np.float64)

@@ -90,6 +90,21 @@ using namespace crh;
 
 namespace crh {
 
+// Structural non-zeros of the coupled matrix [A D^t; D 0] (A: d x d blocks of
+// the face stencil, or their diagonals for Stokes; D and D^t: d per interior
+// face of every element but K0).
+int64_t coupled_nnz(const cr_system* s) {
+  const int d = s->d, d1 = d + 1;
+  int64_t dcount = 0;
+  for (int64_t k = 0; k < s->ne; ++k) {
+    if (k == s->params.k0) continue;
+    for (int j = 0; j < d1; ++j) dcount += s->topo.elem_face[k * d1 + j] >= 0 ? d : 0;
+  }
+  const int64_t blocks = stencil_blocks(s->topo);
+  const int64_t a = s->params.problem == CR_NS_NEWTON ? blocks * d * d : blocks * d;
+  return a + 2 * dcount;
+}
+
 // Host tables of a system in internal order, staged for upload.
 struct Staging {
   std::vector<double> ecoord;
@@ -502,16 +517,7 @@ cr_status cr_query_sizes(const cr_system* s, int64_t* n_int_faces, int64_t* nnz_
   const int d = s->d;
   if (n_int_faces) *n_int_faces = s->nf;
   if (nnz_G) *nnz_G = blocks * d * d;
-  if (nnz_coupled) {
-    int64_t dcount = 0;
-    const int d1 = d + 1;
-    for (int64_t k = 0; k < s->ne; ++k) {
-      if (k == s->params.k0) continue;
-      for (int j = 0; j < d1; ++j) dcount += s->topo.elem_face[k * d1 + j] >= 0 ? d : 0;
-    }
-    const int64_t a = s->params.problem == CR_NS_NEWTON ? blocks * d * d : blocks * d;
-    *nnz_coupled = a + 2 * dcount;
-  }
+  if (nnz_coupled) *nnz_coupled = coupled_nnz(s);
   return CR_OK;
 }
 
@@ -629,6 +635,19 @@ cr_status cr_time_spmv(cr_system* s, int32_t precision, int32_t operator_form, i
     return CR_E_INVAL;
   }
   return run_time_spmv(s, precision, operator_form, reps, avg_ms, bytes);
+}
+
+cr_status cr_export_coupled(cr_system* s, int64_t* rowptr, int32_t* col, double* val, double* R) {
+  clear_error();
+  if (!s || !s->eliminated) {
+    set_error("cr_export_coupled needs an eliminated system");
+    return CR_E_INVAL;
+  }
+  if (s->params.problem != CR_STOKES) {
+    set_error("the coupled export is for the Stokes problem");
+    return CR_E_INVAL;
+  }
+  return run_coupled_export(s, rowptr, col, val, R);
 }
 
 cr_status cr_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <vector>
 
 #include "geometry.h"
 #include "internal.h"
@@ -551,19 +552,27 @@ void enqueue_mr(cr_system* s, CWs* w, int k0, int niter) {
   }
 }
 
+// the coupled matrix, its right-hand side and the preconditioner, on the device
 template <int D>
-cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
-  auto t0 = std::chrono::steady_clock::now();
-  CWs* w = nullptr;
+cr_status coupled_assemble(cr_system* s, CWs*& w) {
   cr_status st = ensure_cws(s, w);
   if (st != CR_OK) return st;
-  const CDims C = w->dims;
-  const MatArgs M{w->Aval, s->cols, w->an, s->fel, w->ea, s->eface};
   hipLaunchKernelGGL(k_coupled_faces<D>, dim3((unsigned)((s->nf + 127) / 128)), dim3(128), 0, s->stream, s->nf, s->ne,
                      s->ecoord, s->eflags, s->fel, s->floc, s->RK, s->params.mu, s->params.nu, w->Aval, w->an, w->b,
                      w->dinv);
   hipLaunchKernelGGL(k_coupled_elems<D>, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->nf, s->ne,
                      s->ecoord, s->eflags, s->eface, w->Aval, w->ea, w->b, w->dinv);
+  return check_hip(hipGetLastError(), "coupled assembly");
+}
+
+template <int D>
+cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
+  auto t0 = std::chrono::steady_clock::now();
+  CWs* w = nullptr;
+  cr_status st = coupled_assemble<D>(s, w);
+  if (st != CR_OK) return st;
+  const CDims C = w->dims;
+  const MatArgs M{w->Aval, s->cols, w->an, s->fel, w->ea, s->eface};
   st = check_hip(hipMemsetAsync(w->x, 0, sizeof(double) * w->n, s->stream), "coupled x");
   const double tol = o->tol > 0 ? o->tol : 1e-10;
   const int maxit = o->maxit > 0 ? o->maxit : 200000;
@@ -645,6 +654,86 @@ cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* inf
 
 cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
   return s->d == 2 ? coupled_solve<2>(s, o, info, U, P) : coupled_solve<3>(s, o, info, U, P);
+}
+
+// The coupled matrix [A D^t; D 0] in canonical order as CSR: velocity rows
+// (canonical face, component), then one pressure row per element in caller
+// order without K0; columns sorted in each row.  Assembled by the coupled
+// baseline's kernels, copied to the host and reordered there.
+cr_status run_coupled_export(cr_system* s, int64_t* rowptr, int32_t* col, double* val, double* R) {
+  CWs* w = nullptr;
+  cr_status st = s->d == 2 ? coupled_assemble<2>(s, w) : coupled_assemble<3>(s, w);
+  if (st != CR_OK) return st;
+  const int d = s->d, d1 = d + 1;
+  const int64_t nf = s->nf, ne = s->ne, nu = nf * d;
+  std::vector<double> Aval((size_t)(2 * d + 1) * nf), an((size_t)d * nf), ea((size_t)d1 * d * ne), b((size_t)nf * d);
+  std::vector<int32_t> cols((size_t)2 * d * nf);
+  auto get = [&](void* dst, const void* src, size_t bytes) {
+    if (st == CR_OK) st = check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream), "export coupled");
+  };
+  get(Aval.data(), w->Aval, Aval.size() * 8);
+  get(an.data(), w->an, an.size() * 8);
+  get(ea.data(), w->ea, ea.size() * 8);
+  get(b.data(), w->b, b.size() * 8);
+  get(cols.data(), s->cols, cols.size() * 4);
+  if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "export coupled");
+  if (st != CR_OK) return st;
+  const Topology& t = s->topo;
+  const int32_t k0 = s->params.k0;
+  auto pcol = [&](int32_t c) { return (int32_t)(nu + (c < k0 ? c : c - 1)); };
+  // the rows in order; emit(r, rhs) receives each row's entries in `row`
+  std::vector<std::pair<int32_t, double>> row;
+  auto rows = [&](auto&& emit) {
+    for (int64_t fc = 0; fc < nf; ++fc) {
+      const int64_t f = t.face_perm[fc];
+      const int32_t own = t.face_elem[2 * fc], oth = t.face_elem[2 * fc + 1];  // caller ids, owner (C = +1) first
+      for (int i = 0; i < d; ++i) {
+        row.clear();
+        row.emplace_back((int32_t)(fc * d + i), Aval[f]);
+        for (int sl = 1; sl <= 2 * d; ++sl) {
+          const int64_t c = cols[(size_t)(sl - 1) * nf + f];
+          if (c == f) continue;  // padding slot of an exterior face
+          row.emplace_back((int32_t)(t.face_iperm[c] * d + i), Aval[(size_t)sl * nf + f]);
+        }
+        // D^t P at face f: -a_{K,f} (P_K - P_L), K the owner
+        if (own != k0) row.emplace_back(pcol(own), -an[f * d + i]);
+        if (oth != k0) row.emplace_back(pcol(oth), an[f * d + i]);
+        emit(fc * d + i, b[f * d + i]);
+      }
+    }
+    for (int32_t c = 0; c < (int32_t)ne; ++c) {
+      if (c == k0) continue;
+      const int64_t k = t.elem_perm[c];
+      row.clear();
+      // D U at element K: -sum_j a_{K,j} . U_j over its interior faces
+      for (int j = 0; j < d1; ++j) {
+        const int32_t fcan = t.elem_face[(int64_t)c * d1 + j];
+        if (fcan < 0) continue;
+        for (int i = 0; i < d; ++i) row.emplace_back((int32_t)(fcan * d + i), -ea[(size_t)(j * d + i) * ne + k]);
+      }
+      emit(pcol(c), 0.0);
+    }
+  };
+  // count first: the caller's buffers hold coupled_nnz entries
+  int64_t pos = 0;
+  rows([&](int64_t, double) { pos += (int64_t)row.size(); });
+  if (pos != coupled_nnz(s)) {
+    set_error("coupled export: %lld entries where %lld are declared", (long long)pos, (long long)coupled_nnz(s));
+    return CR_E_DEVICE;
+  }
+  pos = 0;
+  rows([&](int64_t r, double rhs) {
+    std::sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    if (rowptr) rowptr[r] = pos;
+    for (auto& e : row) {
+      if (col) col[pos] = e.first;
+      if (val) val[pos] = e.second;
+      ++pos;
+    }
+    if (R) R[r] = rhs;
+  });
+  if (rowptr) rowptr[nu + ne - 1] = pos;
+  return CR_OK;
 }
 
 void free_coupled(cr_system* s) {

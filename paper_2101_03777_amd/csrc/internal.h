@@ -154,6 +154,8 @@ void free_krylov(cr_system* s);
 
 // coupled baseline (coupled.hip)
 cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P);
+int64_t coupled_nnz(const cr_system* s);
+cr_status run_coupled_export(cr_system* s, int64_t* rowptr, int32_t* col, double* val, double* R);
 void free_coupled(cr_system* s);
 
 }  // namespace crh

@@ -104,6 +104,31 @@ def test_recover_from_oracle_W(gpu, name):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["square16", "jitter12", "cube3", "steady10"])
+def test_export_coupled_matches_oracle(gpu, name):
+    """cr_export_coupled gives the oracle's coupled matrix [A D^t; D 0] and [R; 0]
+    (Section 3.1) entry by entry, with the structural count of cr_query_sizes;
+    the Navier-Stokes system is refused."""
+    import scipy.sparse as sps
+    case = make_case(name)
+    P = oracle_problem(case)
+    A, D, R, prow = cr.assemble_coupled(P)
+    Mo = sps.bmat([[A, D.T], [D, None]], format="csr")
+    bo = np.concatenate([R, np.zeros(D.shape[0])])
+    s = gpu_system(gpu, case)
+    M, b = s.export_coupled()
+    assert M.shape == Mo.shape and M.nnz == s.nnz_coupled
+    assert np.all(np.diff(M.indptr) >= 0)
+    scale = np.abs(Mo.data).max()
+    assert abs(M - Mo).max() <= 1e-12 * scale
+    assert np.abs(b - bo).max() <= 1e-12 * np.abs(bo).max()
+    s.close()
+    ns = gpu_system(gpu, make_case("ns10"))
+    with pytest.raises(gpu.CRError):
+        ns.export_coupled()
+    ns.close()
+
+
 def test_jump_equals_residual_random_W(gpu):
     """For any W the copy mismatch ||C^ U^|| equals ||S - G W|| (substitution of the
     recovery relations into the C^ row of the three-field system)."""
