@@ -324,6 +324,44 @@ def test_error_paths(gpu):
     s.close()
 
 
+@pytest.mark.parametrize("method", ["pcg", "minres"])
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
+def test_degenerate_meshes_and_data(gpu, method, precision, bar):
+    """Edge cases of the method: the smallest meshes (two triangles or two
+    tetrahedra sharing one face: one interior face, one Schur term besides
+    K0), a pinned element other than the first, and a zero right-hand side
+    (S = 0: no iteration, U = 0 and P = 0)."""
+    c2 = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=float)
+    e2 = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    c3 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]], dtype=float)
+    e3 = np.array([[0, 1, 2, 3], [1, 2, 3, 4]], dtype=np.int32)
+    co12, el12 = synth.square_mesh(12, jitter=0.2, seed=7)
+    cases = [(c2, e2, 10.0, 0), (c3, e3, 10.0, 1), (co12, el12, 300.0, 37)]
+    for coords, elems, mu, k0 in cases:
+        d = coords.shape[1]
+        fbar = np.random.default_rng(len(elems)).normal(size=(len(elems), d))
+        P = cr.make_problem(coords, elems, mu, 1.0, fbar, k0=k0)
+        U_o, P_o = cr.solve_coupled(P)
+        s = gpu.System(coords, elems, mu, 1.0, k0=k0)
+        s.eliminate(dev(fbar))
+        info = s.solve(method, precision, tol=1e-13, maxit=100000)
+        U, Pk = s.recover()
+        torch.cuda.synchronize()
+        print(f"{len(elems)} elements k0={k0} {method} {precision}: {info['iters']} iterations", flush=True)
+        assert info["status"] == 0
+        assert float(Pk[k0]) == 0.0
+        assert np.abs(U.cpu().numpy() - U_o).max() <= bar * max(np.abs(U_o).max(), np.abs(P_o).max())
+        assert relerr(Pk.cpu().numpy(), P_o) <= bar
+        # zero data: the solution is zero, with no iteration
+        s.eliminate(dev(np.zeros_like(fbar)))
+        z = s.solve(method, precision, tol=1e-13)
+        U0, P0 = s.recover()
+        torch.cuda.synchronize()
+        assert z["status"] == 0 and z["iters"] == 0
+        assert not U0.any() and not P0.any()
+        s.close()
+
+
 @pytest.mark.parametrize("name", ["square16", "jitter12", "cube3"])
 def test_coupled_minres_baseline_parity(gpu, name):
     """The GPU coupled-system baseline reaches the oracle's coupled solution."""
