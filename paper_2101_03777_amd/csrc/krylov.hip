@@ -509,6 +509,24 @@ __global__ void __launch_bounds__(NT) k_cg_update_b(const CgSys* __restrict__ ta
 // p alternates between two buffers by parity.  w is stored [element][local
 // face][component] so that E2 reads each side as one short vector.
 // ---------------------------------------------------------------------------
+// a * b + c with one rounding, the same in every kernel that forms the
+// direction (the element kernel and, in 3D, the face kernel compute it for the
+// same face and must agree bit for bit)
+template <typename T>
+__device__ __forceinline__ T mul_add(T a, T b, T c) {
+  if constexpr (std::is_same<T, float>::value)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
+// In 3D the face kernel stores the new direction (coalesced, one thread per
+// face) and the element kernel does not scatter it to the owner faces: the
+// scattered 12-byte stores cost as much as the element contributions' twice
+// larger coalesced ones (measured on 64^3 x 6).  In 2D the scattered stores are
+// cheap and the element kernel keeps them.
+__host__ __device__ constexpr bool ec2_stores_direction(int d) { return d == 3; }
+
 // Elements per thread whose loads are in flight together: four in 2D FP32
 // (about 28 values each) where each thread has at least four elements, one
 // elsewhere (measured on 512x512x2 and 64^3x6).
@@ -564,7 +582,7 @@ __device__ __forceinline__ void ec1_pass(const CgSys& S, int par, int64_t lo, in
         ph[l] = rv[e][l];
         if (!first)
 #pragma unroll
-          for (int i = 0; i < D; ++i) ph[l].v[i] = ph[l].v[i] + beta * po[e][l].v[i];
+          for (int i = 0; i < D; ++i) ph[l].v[i] = mul_add(beta, po[e][l].v[i], ph[l].v[i]);
         pn[l] = ph[l];
       }
       // The direction is p = ph + Z m, with m = E^-1 Z^t r + beta m_old per
@@ -600,9 +618,10 @@ __device__ __forceinline__ void ec1_pass(const CgSys& S, int par, int64_t lo, in
 #pragma unroll
       for (int j = 0; j < N; ++j) stv<T, D>(tq, K * N + j, w[j]);
       // the owner stores the direction without its coarse part
+      if constexpr (!ec2_stores_direction(D))
 #pragma unroll
-      for (int j = 0; j < N; ++j)
-        if (((fl[e] >> j) & 1u) && !((fl[e] >> (8 + j)) & 1u)) stv<T, D>(pnew, g[e][j], ph[j]);
+        for (int j = 0; j < N; ++j)
+          if (((fl[e] >> j) & 1u) && !((fl[e] >> (8 + j)) & 1u)) stv<T, D>(pnew, g[e][j], ph[j]);
     }
   }
 }
@@ -655,7 +674,13 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
   const Part P = S.P;
   T* __restrict__ x = (T*)S.x;
   T* __restrict__ r = (T*)S.r;
+  // the direction without its coarse part: stored by the element kernel, or
+  // (3D) formed here from r and the previous direction as the element kernel
+  // formed it, and stored
   const T* __restrict__ p = (const T*)(par ? S.p1 : S.p);
+  const T* __restrict__ pold = (const T*)(par ? S.p : S.p1);
+  T* __restrict__ pnew = (T*)(par ? S.p1 : S.p);
+  const T tbeta = (T)cbeta;
   const T* __restrict__ tq = (const T*)S.tq;
   const int64_t lo = (int64_t)lb * P.chunk, hi = min(P.nf, lo + P.chunk);
   if (S.nagg > 0 && lb == 0)  // the coarse part m of this iteration's direction
@@ -672,7 +697,18 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
     const int lc = S.floc[f];
     const Vec<T, D> wk = ldv<T, D>(tq, K * N + (lc & 0xff));
     const Vec<T, D> wl = ldv<T, D>(tq, Lr * N + ((lc >> 8) & 0xff));
-    Vec<T, D> xi = ldv<T, D>(x, f), ri = ldv<T, D>(r, f), pi = ldv<T, D>(p, f);
+    Vec<T, D> xi = ldv<T, D>(x, f), ri = ldv<T, D>(r, f), pi;
+    if constexpr (ec2_stores_direction(D)) {
+      pi = ri;
+      if (!cfirst) {
+        const Vec<T, D> po = ldv<T, D>(pold, f);
+#pragma unroll
+        for (int i = 0; i < D; ++i) pi.v[i] = mul_add(tbeta, po.v[i], ri.v[i]);
+      }
+      stv<T, D>(pnew, f, pi);
+    } else {
+      pi = ldv<T, D>(p, f);
+    }
     Vec<T, D> zf;
     int ak = 0;
     if (S.nagg > 0) {
@@ -2274,9 +2310,10 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
     if (op) {
       // element-centric kernel: element factors, gather indices and flags read
       // once; r and the previous p read once (gathered); the new p written
-      // once (by the owner elements); w_K written once
-      *bytes = ne * (d1 * (d1 + 1) / 2 + d1 * d) * vsz + ne * (d1 + 1) * 4.0 + nf * d * vsz * 3 +
-               ne * d1 * d * vsz;
+      // once by the owner elements (2D; in 3D the face kernel writes it);
+      // w_K written once
+      *bytes = ne * (d1 * (d1 + 1) / 2 + d1 * d) * vsz + ne * (d1 + 1) * 4.0 +
+               nf * d * vsz * (ec2_stores_direction(d) ? 2 : 3) + ne * d1 * d * vsz;
       // with the coarse correction: the aggregate of each face and the column
       // of Z there, read by the elements on aggregate boundaries
       if (w->use_coarse) *bytes += (double)s->nbnd * d1 * (4.0 + d * vsz);
