@@ -161,7 +161,8 @@ typedef struct {
   int32_t warm_start;  /* 1: start from the resident W of the previous solve, 0: from W = 0 */
   int32_t operator_form; /* CR_OP_AUTO, CR_OP_ASSEMBLED or CR_OP_ELEMENT */
   int32_t coarse;      /* 0: element-form CG adds the coarse correction where the mesh
-                          has aggregates (meshes of at least 8192 elements); 1: Jacobi only */
+                          has aggregates (2D meshes of at least 8192 elements, 3D of at
+                          least 4096); 1: Jacobi only */
 } cr_solve_opts;
 
 typedef struct {

@@ -54,6 +54,7 @@ constexpr uint32_t F_M1 = 1u << 17;         // element in M1 (E_K = -lambda I)
 constexpr uint32_t F_AGGB = 1u << 18;       // interior faces in more than one aggregate
 
 constexpr int NT = 256;                     // threads per block of the row kernels
+constexpr int MAX_AGG = 512;                // most aggregates of the coarse correction
 
 }  // namespace crh
 

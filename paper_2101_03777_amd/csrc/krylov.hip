@@ -752,7 +752,7 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
 // hold aggregate a (fixed order), mu = E^-1 c; one wavefront per row.
 __device__ __forceinline__ void coarse_body(const CgSys& S, int cb) {
   if (S.st->done) return;
-  __shared__ double c[256];
+  __shared__ double c[MAX_AGG];
   for (int a = threadIdx.x; a < S.nagg; a += NT) {
     double v = 0.0;
     for (int b = S.bfa[a]; b <= S.bla[a]; ++b) v += S.Pr[(int64_t)b * KMAX + (a - S.ablk[b])];

@@ -289,13 +289,17 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     }
     std::reverse(order.begin(), order.end());
     // Aggregates for the coarse correction: recursive coordinate bisection of
-    // the element centroids into nagg parts (a power of two, about 2048
-    // elements each, at most 256; none below 4 parts), numbered in bisection
-    // order so that consecutive aggregates are neighbours.  A face belongs to
-    // the aggregate of its owner element (the lower caller id, C = +1).  Faces
-    // are grouped by aggregate, in RCM order inside a group.
+    // the element centroids into nagg parts (a power of two; in 2D at least
+    // 2048 elements each and at most 256 parts, in 3D at least 1024 and at most
+    // MAX_AGG = 512: measured on 512x512x2 and 64^3x6; none below 4 parts),
+    // numbered in bisection order so that consecutive aggregates are
+    // neighbours.  A face belongs to the aggregate of its owner element (the
+    // lower caller id, C = +1).  Faces are grouped by aggregate, in RCM order
+    // inside a group.
+    const int agg_cap = d == 3 ? MAX_AGG : 256;
+    const int64_t agg_min = d == 3 ? 1024 : 2048;
     int nagg = 1;
-    while (nagg < 256 && (int64_t)nagg * 2 * 2048 <= ne) nagg *= 2;
+    while (nagg < agg_cap && (int64_t)nagg * 2 * agg_min <= ne) nagg *= 2;
     if (aggregate && nagg >= 4) {
       std::vector<double> cen((size_t)ne * d, 0.0);
       for (int64_t k = 0; k < ne; ++k)

@@ -275,7 +275,7 @@ def test_coarse_correction_parity(gpu, precision, bar):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_coarse_correction_3d(gpu, precision):
-    """3D coarse correction (12^3 x 6 = 10,368 tetrahedra, 4 aggregates): the
+    """3D coarse correction (12^3 x 6 = 10,368 tetrahedra, 8 aggregates): the
     same W as the Jacobi-only solve of the same system (whose parity with the
     oracle is tested on 5^3 x 6; the oracle's direct solve at this size takes
     about a minute), fewer iterations, and the FP64 residual at the tolerance."""
