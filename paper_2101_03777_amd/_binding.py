@@ -82,6 +82,11 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or "
                            "python -m paper_2101_03777_amd.build")
+    # torch first: its HIP runtime then provides the library's HIP symbols, so
+    # the process holds one runtime (device pointers and streams come from
+    # torch).  Loaded the other way round, the library would bring in a second
+    # HIP runtime, and device calls through one of them can fail.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {

@@ -126,3 +126,22 @@ def test_prepare_is_host_only():
     with pytest.raises(crh.CRError) as e:
         crh.Prepared(coords[:3], np.array([[0, 1, 2]], dtype=np.int32), mu=1.0, nu=1.0)
     assert e.value.status == -3
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library before torch is imported still leaves one HIP runtime
+    in the process (the one torch brings), whichever import comes first."""
+    import subprocess
+    import sys
+    code = ("import paper_2101_03777_amd as crh\n"
+            "crh.load()\n"
+            "import torch\n"
+            "libs = set()\n"
+            "for line in open('/proc/self/maps'):\n"
+            "    f = line.split()\n"
+            "    if len(f) >= 6 and 'libamdhip64' in f[-1]:\n"
+            "        libs.add(f[-1])\n"
+            "print(len(libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
