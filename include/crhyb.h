@@ -183,6 +183,9 @@ typedef struct {
  * preconditioning is applied as the symmetric scaling Ds G Ds with one scale
  * per face,
  * Ds_f = (mean over the d components of |diag G|)^{-1/2}.
+ * CG with the element form adds an aggregate coarse correction (one column per
+ * aggregate: the null vector of the gauge-shifted G restricted to the
+ * aggregate's faces; opts.coarse); it changes the iterations, not the solution.
  * CR_FP32_IR runs the Krylov recurrences in FP32 with FP64 residual
  * replacements; if the FP32 iterations stop reducing the FP64 residual, the
  * remaining iterations run in FP64 (reported in cr_solve_info.fp64_fallback).
@@ -249,17 +252,20 @@ cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t
 cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* info,
                            double* U, double* P);
 
-/* Average device time of the dominant Krylov kernel (SpMV fused with the CG
- * direction updates) over reps launches on the system's stream, measured with
+/* Average device time of the dominant Krylov kernel (the product with G fused
+ * with the CG direction update) over reps launches on the system's stream, measured with
  * HIP events, on scratch copies of the state (the resident solution is
  * untouched; the coarse-correction vectors of the last solve are not kept).
  * Back-to-back launches, except with the coarse correction, where the element
  * kernel runs inside the iteration sequence with events attached to each of its
  * launches.  precision and operator_form as in cr_solve_opts.
- * Also returns the algorithmic bytes one launch moves: the operator data once
- * (assembled: values and column indices of G; element form: element factors,
- * element gather indices, face-to-element table), the gathered input vector
- * once, and the fused vector reads/writes.  Synchronises.
+ * Also returns the algorithmic bytes one launch moves, each datum counted once:
+ * assembled form: values and column indices of G, the gathered input vector,
+ * the fused vector reads and writes; element form: element factors, gather
+ * indices and flags, r and the previous direction at the faces, the element
+ * contributions, the new direction (2D; in 3D the face kernel stores it), and
+ * with the coarse correction the face aggregate and Z column read by the
+ * elements on aggregate boundaries.  Synchronises.
  * Errors: CR_E_INVAL (not eliminated, reps < 1, element form unavailable). */
 cr_status cr_time_spmv(cr_system* sys, int32_t precision, int32_t operator_form, int32_t reps,
                        double* avg_ms, double* bytes_per_launch);
