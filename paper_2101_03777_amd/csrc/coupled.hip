@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(NT) k_mr_a(CDims C, MatArgs M, const double* _
                                              double* __restrict__ v, double* __restrict__ y,
                                              const double* __restrict__ pa, double* __restrict__ pb,
                                              CState* __restrict__ st, int q) {
-  if (st->done) return;
+  const int seen = st->done;
   const int p = q ^ 1;
   const int it = st->it[p];
   const bool first = it == 0;
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(NT) k_mr_a(CDims C, MatArgs M, const double* _
   int done = 0;
   if (first) {
     double s[3];
-    reduce_partials<3>(pa, C.nbf + C.nbe, 0, s);
+    if (reduce_partials_stop<3>(pa, C.nbf + C.nbe, 0, s, seen)) return;
     beta = sqrt(s[0]);
     oldb = 0.0;
     const double thr = 0.1 * sqrt(st->tol2 * s[2]) * (s[1] > 0.0 ? beta / sqrt(s[1]) : 1.0);
@@ -315,6 +315,9 @@ __global__ void __launch_bounds__(NT) k_mr_a(CDims C, MatArgs M, const double* _
       st->phibar[p] = beta;
     }
   } else {
+    // no reduction before the decision: a wave that saw the word set returns,
+    // and the others reach the same decision from the same state and return
+    if (seen) return;
     beta = st->beta[p];
     oldb = st->oldb[p];
     if (st->phibar[p] <= st->thr) done = 1;
@@ -393,9 +396,9 @@ __global__ void __launch_bounds__(NT) k_mr_c(CDims C, int64_t n, const double* _
                                              const double* __restrict__ w1, const double* __restrict__ w2,
                                              double* __restrict__ wn, double* __restrict__ x,
                                              const double* __restrict__ pc, CState* __restrict__ st, int q) {
-  if (st->done) return;
+  const int seen = st->done;
   double s[1];
-  reduce_partials<1>(pc, C.nbf + C.nbe, 0, s);
+  if (reduce_partials_stop<1>(pc, C.nbf + C.nbe, 0, s, seen)) return;
   const int p = q ^ 1;
   if (!(s[0] >= 0.0) || !isfinite(s[0])) {
     if (lead()) st->done = isfinite(s[0]) ? 4 : 5;

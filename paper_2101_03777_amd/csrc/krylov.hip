@@ -362,8 +362,7 @@ __device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f3
   }
   if (with_coarse)
     for (int a = threadIdx.x; a < S.nagg; a += NT) v[3] += S.cvec[a] * S.mu[a];
-  if (done) return false;
-  block_sum<4>(v);
+  if (block_sum_stop<4>(v, done)) return false;
   first = it == it_first;
   const bool fresh = it == it_rep;
   const double rr = v[0], tres2 = fresh ? v[1] : 0.0, snorm2 = fresh ? v[2] : 0.0, coarse = v[3];
@@ -420,11 +419,11 @@ __device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
 template <int D, typename T>
 __device__ __forceinline__ void cg_update_body(const CgSys& S, int lb, int par) {
   KState* st = S.st;
-  if (st->done) return;
+  const int seen = st->done;
   const Part P = S.P;
   const int fl[1] = {0};
   double v[1];
-  reduce_fields<1>(S.Pb, P.nblk, fl, v);
+  if (reduce_fields_stop<1>(S.Pb, P.nblk, fl, v, seen)) return;
   const double pq = v[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (threadIdx.x == 0 && lb == 0) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
@@ -662,8 +661,7 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
     mu_k[k] = S.nagg > 0 ? S.mu[a] : 0.0;
     mo_k[k] = S.nagg > 0 ? mold[a] : 0.0;
   }
-  if (done) return;
-  block_sum<1>(v);
+  if (block_sum_stop<1>(v, done)) return;
   const double pq = v[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (threadIdx.x == 0 && lb == 0) st->done = isfinite(pq) ? BREAKDOWN : NONFINITE;
@@ -845,7 +843,7 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
                                                T* __restrict__ p_new, T* __restrict__ v_new,
                                                const double* __restrict__ Pa, double* __restrict__ Pb,
                                                KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   const int it = st->it[par ^ 1];
   const bool first = it == st->it_first;
   const bool fresh = it == st->it_rep;
@@ -853,7 +851,7 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
   if (fresh) {
     const int fl[4] = {0, 3, 1, 2};
     double v[4];
-    reduce_fields<4>(Pa, P.nblk, fl, v);
+    if (reduce_fields_stop<4>(Pa, P.nblk, fl, v, seen)) return;
     rho = v[0];
     rr = v[1];
     tres2 = v[2];
@@ -861,7 +859,7 @@ __global__ void __launch_bounds__(NT) k_bicg_1(Part P, const T* __restrict__ G, 
   } else {
     const int fl[2] = {0, 3};
     double v[2];
-    reduce_fields<2>(Pa, P.nblk, fl, v);
+    if (reduce_fields_stop<2>(Pa, P.nblk, fl, v, seen)) return;
     rho = v[0];
     rr = v[1];
   }
@@ -901,10 +899,10 @@ __global__ void __launch_bounds__(NT) k_bicg_2(Part P, const T* __restrict__ G, 
                                                const T* __restrict__ r, const T* __restrict__ v_new,
                                                T* __restrict__ s, T* __restrict__ t, const double* __restrict__ Pb,
                                                double* __restrict__ Pc, KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   const int fl[1] = {0};
   double v[1];
-  reduce_fields<1>(Pb, P.nblk, fl, v);
+  if (reduce_fields_stop<1>(Pb, P.nblk, fl, v, seen)) return;
   const double rv = v[0];
   if (!(rv != 0.0) || !isfinite(rv)) {
     if (lead()) st->done = isfinite(rv) ? BREAKDOWN : NONFINITE;
@@ -940,10 +938,10 @@ __global__ void __launch_bounds__(NT) k_bicg_3(Part P, T* __restrict__ x, T* __r
                                                const T* __restrict__ s, const T* __restrict__ t,
                                                const double* __restrict__ Pc, double* __restrict__ Pa,
                                                KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   const int fl[2] = {0, 1};
   double v[2];
-  reduce_fields<2>(Pc, P.nblk, fl, v);
+  if (reduce_fields_stop<2>(Pc, P.nblk, fl, v, seen)) return;
   const double ts = v[0], tt = v[1];
   if (!(tt > 0.0) || !isfinite(tt) || !isfinite(ts)) {
     if (lead()) st->done = (isfinite(tt) && isfinite(ts)) ? BREAKDOWN : NONFINITE;
@@ -1035,7 +1033,7 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_b2_1(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                              B2Vecs V, const double* __restrict__ Pa, double* __restrict__ Pb,
                                              KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   const int it = st->it[par ^ 1];
   const bool first = it == st->it_first;
   const bool fresh = it == st->it_rep;
@@ -1043,7 +1041,7 @@ __global__ void __launch_bounds__(NT) k_b2_1(Part P, const T* __restrict__ G, co
   if (fresh) {
     const int fl[4] = {0, 3, 1, 2};
     double v[4];
-    reduce_fields<4>(Pa, P.nblk, fl, v);
+    if (reduce_fields_stop<4>(Pa, P.nblk, fl, v, seen)) return;
     rho1 = v[0];
     rr = v[1];
     tres2 = v[2];
@@ -1051,7 +1049,7 @@ __global__ void __launch_bounds__(NT) k_b2_1(Part P, const T* __restrict__ G, co
   } else {
     const int fl[2] = {0, 3};
     double v[2];
-    reduce_fields<2>(Pa, P.nblk, fl, v);
+    if (reduce_fields_stop<2>(Pa, P.nblk, fl, v, seen)) return;
     rho1 = v[0];
     rr = v[1];
   }
@@ -1094,10 +1092,11 @@ __global__ void __launch_bounds__(NT) k_b2_1(Part P, const T* __restrict__ G, co
 }
 
 // E2 and E4 share the breakdown test of a denominator from one partial field
-__device__ __forceinline__ bool b2_denominator(const double* __restrict__ part, int nblk, KState* st, double& val) {
+__device__ __forceinline__ bool b2_denominator(const double* __restrict__ part, int nblk, KState* st, int seen,
+                                               double& val) {
   const int fl[1] = {0};
   double v[1];
-  reduce_fields<1>(part, nblk, fl, v);
+  if (reduce_fields_stop<1>(part, nblk, fl, v, seen)) return false;
   val = v[0];
   if (!(val != 0.0) || !isfinite(val)) {
     if (lead()) st->done = isfinite(val) ? BREAKDOWN : NONFINITE;
@@ -1110,9 +1109,9 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_b2_2(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                              B2Vecs V, const double* __restrict__ Pb, double* __restrict__ Pc,
                                              KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   double g1;
-  if (!b2_denominator(Pb, P.nblk, st, g1)) return;
+  if (!b2_denominator(Pb, P.nblk, st, seen, g1)) return;
   const double alpha1 = st->rho_a[par] / g1;
   const AxpyIn<T, D> in{(const T*)V.r, (const T*)V.v, (T)alpha1, false};
   int lb;
@@ -1142,9 +1141,9 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_b2_3(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                              B2Vecs V, const double* __restrict__ Pc, double* __restrict__ Pb,
                                              KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   double rho2;
-  if (!b2_denominator(Pc, P.nblk, st, rho2)) return;
+  if (!b2_denominator(Pc, P.nblk, st, seen, rho2)) return;
   const double beta2 = st->alpha1[par] * rho2 / st->rho_a[par];
   const AxpyIn<T, D> in{(const T*)V.s, (const T*)V.v, (T)beta2, false};
   int lb;
@@ -1171,9 +1170,9 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_b2_4(Part P, const T* __restrict__ G, const int32_t* __restrict__ cols,
                                              B2Vecs V, const double* __restrict__ Pb, double* __restrict__ Pc,
                                              KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   double g2;
-  if (!b2_denominator(Pb, P.nblk, st, g2)) return;
+  if (!b2_denominator(Pb, P.nblk, st, seen, g2)) return;
   const double alpha2 = st->rho_b[par] / g2;
   const T ta = (T)alpha2, tb = (T)st->beta2[par];
   const AxpyIn<T, D> in{(const T*)V.s, (const T*)V.w, ta, false};
@@ -1212,10 +1211,10 @@ __global__ void __launch_bounds__(NT) k_b2_4(Part P, const T* __restrict__ G, co
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_b2_5(Part P, B2Vecs V, const double* __restrict__ Pc,
                                              double* __restrict__ Pa, KState* __restrict__ st, int par) {
-  if (st->done) return;
+  const int seen = st->done;
   const int fl[5] = {0, 1, 2, 3, 4};
   double v[5];
-  reduce_fields<5>(Pc, P.nblk, fl, v);
+  if (reduce_fields_stop<5>(Pc, P.nblk, fl, v, seen)) return;
   const double rs = v[0], ss = v[1], stt = v[2], tt = v[3], rt = v[4];
   // minimise |r2 - omega1 s2 - omega2 t| (Gram-Schmidt of t against s2)
   const double tau = tt - stt * stt / ss;
@@ -1336,7 +1335,7 @@ __global__ void __launch_bounds__(NT) k_hm_init(CgSys S, T* __restrict__ r1, T* 
 template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_hm_a(CgSys S, const T* __restrict__ r1, const T* __restrict__ r2,
                                              T* __restrict__ v, T* __restrict__ y, MState* __restrict__ ms, int q) {
-  if (ms->done) return;
+  const int seen = ms->done;
   const Part P = S.P;
   const int p = q ^ 1;
   const int it = ms->it[p];
@@ -1346,7 +1345,7 @@ __global__ void __launch_bounds__(NT) k_hm_a(CgSys S, const T* __restrict__ r1, 
   if (first) {
     const int fl[3] = {0, 1, 2};
     double sv[3];
-    reduce_fields<3>(S.Pa, P.nblk, fl, sv);
+    if (reduce_fields_stop<3>(S.Pa, P.nblk, fl, sv, seen)) return;
     beta = sqrt(sv[0]);
     oldb = 0.0;
     // pass target in the scaled norm: 0.1 of the tolerance, converted by the
@@ -1365,6 +1364,9 @@ __global__ void __launch_bounds__(NT) k_hm_a(CgSys S, const T* __restrict__ r1, 
       ms->phibar[p] = beta;
     }
   } else {
+    // no reduction before the decision: a wave that saw the word set returns,
+    // and the others reach the same decision from the same state and return
+    if (seen) return;
     beta = ms->beta[p];
     oldb = ms->oldb[p];
     if (ms->phibar[p] <= ms->thr) done = 1;
@@ -1431,11 +1433,11 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NT) k_hm_c(CgSys S, const T* __restrict__ v, const T* __restrict__ w1,
                                              const T* __restrict__ w2, T* __restrict__ wn, MState* __restrict__ ms,
                                              int q) {
-  if (ms->done) return;
+  const int seen = ms->done;
   const Part P = S.P;
   const int fl[1] = {0};
   double sv[1];
-  reduce_fields<1>(S.Pc, P.nblk, fl, sv);
+  if (reduce_fields_stop<1>(S.Pc, P.nblk, fl, sv, seen)) return;
   const int p = q ^ 1;
   if (!(sv[0] >= 0.0) || !isfinite(sv[0])) {
     if (lead()) ms->done = isfinite(sv[0]) ? 4 : 5;

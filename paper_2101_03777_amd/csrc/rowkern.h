@@ -179,6 +179,43 @@ __device__ __forceinline__ void block_sum(double (&v)[M]) {
   __syncthreads();
 }
 
+// Stop words.  The first kernel of an iteration decides in every workgroup,
+// from the same partial sums, whether the iteration runs; the workgroup with
+// logical index 0 records the decision in a stop word that the other
+// workgroups of the same launch also read.  The waves of one workgroup may
+// therefore see different values of that word.  block_sum_stop takes each
+// wave's view along with its sums and returns the OR over the workgroup, so
+// that all waves of a workgroup leave together, after the barrier, and every
+// wave that continues used complete sums.  (Any workgroup that saw the word
+// still clear reaches the same decision as the one that wrote it.)
+template <int M>
+__device__ __forceinline__ bool block_sum_stop(double (&v)[M], int seen) {
+  __shared__ double sh[M][NT / 64];
+  __shared__ int sf[NT / 64];
+  int s = seen != 0;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double x = v[m];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[m] = x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s |= __shfl_xor(s, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
+    sf[w] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = (sh[m][0] + sh[m][1]) + (sh[m][2] + sh[m][3]);
+  s = (sf[0] | sf[1]) | (sf[2] | sf[3]);
+  __syncthreads();
+  return s != 0;
+}
+
 // every workgroup reduces the same partial records in the same order
 template <int M>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nblk, int first, double (&v)[M]) {
@@ -201,6 +238,31 @@ __device__ __forceinline__ void reduce_fields(const double* __restrict__ part, i
 #pragma unroll
     for (int m = 0; m < M; ++m) v[m] += part[(int64_t)fields[m] * nblk + i];
   block_sum<M>(v);
+}
+
+// reduce_partials with the workgroup-uniform stop view of block_sum_stop
+template <int M>
+__device__ __forceinline__ bool reduce_partials_stop(const double* __restrict__ part, int nblk, int first,
+                                                     double (&v)[M], int seen) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += NT)
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] += part[(int64_t)i * NPART + first + m];
+  return block_sum_stop<M>(v, seen);
+}
+
+// reduce_fields with the workgroup-uniform stop view of block_sum_stop:
+// returns true if any wave of the workgroup saw the stop word set
+template <int M>
+__device__ __forceinline__ bool reduce_fields_stop(const double* __restrict__ part, int nblk, const int (&fields)[M],
+                                                   double (&v)[M], int seen) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += NT)
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] += part[(int64_t)fields[m] * nblk + i];
+  return block_sum_stop<M>(v, seen);
 }
 
 __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
