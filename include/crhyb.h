@@ -202,6 +202,22 @@ cr_status cr_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* inf
  * equals ||S - G W||_2.  Asynchronous. */
 cr_status cr_recover(cr_system* sys, double* U, double* P, double* jump);
 
+/* cr_recover for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * U and P (bit for bit) and the same copy mismatch up to summation order, but
+ * no device allocation at all.  cr_recover keeps the second velocity copy in a
+ * per-system buffer of n_int_faces*dim doubles allocated on first use; this
+ * variant recomputes the non-owner copies in a second element pass and keeps
+ * only one partial sum per 128 elements, in a static device array of 256 KiB
+ * (32768 doubles) that each device holds until the process ends.
+ * Limit: with jump != NULL, at most 4,194,304 elements, else CR_E_INVAL
+ * (message names the limit); with jump == NULL no limit and no scratch.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (other streams, other threads) race on it.  Each call writes
+ * every partial it reads, so nothing needs clearing between calls.
+ * Asynchronous; arguments, layouts and other errors as cr_recover. */
+cr_status cr_recover_noalloc(cr_system* sys, double* U, double* P, double* jump);
+
 /* Sizes of the system: interior faces, structural non-zeros of G (d x d blocks
  * of the stencil), non-zeros of the coupled matrix [A D^t; D 0]. Any pointer may be NULL. */
 cr_status cr_query_sizes(const cr_system* sys, int64_t* n_int_faces, int64_t* nnz_G,

@@ -31,7 +31,7 @@ EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recov
            "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
            "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
            "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy", "cr_prepare",
-           "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled"]
+           "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled", "cr_recover_noalloc"]
 
 
 class CRError(RuntimeError):
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "cr_update_rhs": (I32, [P, P, P]),
         "cr_solve": (I32, [P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
         "cr_recover": (I32, [P, P, P, P]),
+        "cr_recover_noalloc": (I32, [P, P, P, P]),
         "cr_query_sizes": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
         "cr_export_G": (I32, [P, P, P, P, P]),
         "cr_export_W": (I32, [P, P]),
@@ -372,6 +373,16 @@ class System:
         J = torch.empty((1,), dtype=torch.float64, device="cuda") if jump else None
         _check(self.lib.cr_recover(self.h, _ptr(U), _ptr(P), _ptr(J)))
         return (U, P, J) if jump else (U, P)
+
+    def recover_noalloc(self, U, P, J=None):
+        """cr_recover_noalloc into caller-provided device tensors U [n_int_faces, dim],
+        P [n_elements] and J [1] (or None): no device memory is allocated."""
+        torch = self._torch
+        for t, shape in ((U, (self.n_int_faces, self.dim)), (P, (self.n_elements,)), (J, (1,))):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or tuple(t.shape) != shape):
+                raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
+        _check(self.lib.cr_recover_noalloc(self.h, _ptr(U), _ptr(P), _ptr(J)))
 
     def coupled_solve(self, tol=1e-10, maxit=0, check_every=0, raise_on_error=True):
         torch = self._torch

@@ -507,6 +507,19 @@ cr_status cr_recover(cr_system* s, double* U, double* P, double* jump) {
   return run_recover(s, U, P, jump);
 }
 
+cr_status cr_recover_noalloc(cr_system* s, double* U, double* P, double* jump) {
+  clear_error();
+  if (!s || !U || !P) {
+    set_error("NULL system or output");
+    return CR_E_INVAL;
+  }
+  if (!s->eliminated) {
+    set_error("cr_recover_noalloc before cr_eliminate");
+    return CR_E_INVAL;
+  }
+  return run_recover_noalloc(s, U, P, jump);
+}
+
 cr_status cr_query_sizes(const cr_system* s, int64_t* n_int_faces, int64_t* nnz_G, int64_t* nnz_coupled) {
   clear_error();
   if (!s) {

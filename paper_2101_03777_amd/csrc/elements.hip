@@ -13,11 +13,20 @@
 // element holding both faces and the diagonal block from the face's two
 // elements, so assembly needs no atomics.
 #include <cmath>
+#include <mutex>
 #include <utility>
 
 #include "internal.h"
 #include "geometry.h"
 #include "rowkern.h"
+
+// Workgroup partials of the allocation-free recovery (cr_recover_noalloc):
+// one double per element workgroup of the copy-mismatch pass, so at most
+// NOALLOC_PARTIALS * 128 elements.  Each device holds its own copy for the
+// life of the process; host code uses the address hipGetSymbolAddress returns
+// for the current device, never this name.
+constexpr int64_t NOALLOC_PARTIALS = 32768;  // 256 KiB
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
 
 namespace crh {
 namespace {
@@ -991,20 +1000,16 @@ __global__ void __launch_bounds__(BS) k_face_rhs(int64_t nf, int64_t ne, const i
 // The copy with C = +1 is written to U (canonical order); the other copy goes
 // to Ujump for the mismatch diagnostic.
 // ---------------------------------------------------------------------------
+// One element of the recovery: its pressure p and the velocity copies u of
+// its faces; fc[j] is the canonical id of local face j (-1: exterior).
 template <int D, bool NSK>
-__global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __restrict__ y,
+__device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t fl, const double* __restrict__ y,
                                                 const double* __restrict__ dsq, const double* __restrict__ pack,
                                                 const double* __restrict__ RK, const int32_t* __restrict__ eface,
-                                                const uint32_t* __restrict__ eflags,
-                                                const int32_t* __restrict__ ecaller,
-                                                const int32_t* __restrict__ fcanon, double* __restrict__ U,
-                                                double* __restrict__ P, double* __restrict__ Ujump) {
+                                                const int32_t* __restrict__ fcanon, double (&u)[D + 1][D],
+                                                double& p, int (&fc)[D + 1]) {
   constexpr int N = D + 1;
-  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (k >= ne) return;
-  const uint32_t fl = eflags[k];
   double rhs[N][D];
-  int fc[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const bool in = interior(fl, j);
@@ -1017,8 +1022,7 @@ __global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __rest
       rhs[j][i] = RK[(int64_t)(j * D + i) * ne + k] - c * w;
     }
   }
-  double u[N][D];
-  double p = 0.0;
+  p = 0.0;
   if constexpr (!NSK) {
     StokesFactors<D> F;
     load_stokes_pack<D>(pack, ne, k, F);
@@ -1050,6 +1054,23 @@ __global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __rest
       u[a / 2][a % 2] = t - p * F.l[a];
     }
   }
+}
+
+template <int D, bool NSK>
+__global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __restrict__ y,
+                                                const double* __restrict__ dsq, const double* __restrict__ pack,
+                                                const double* __restrict__ RK, const int32_t* __restrict__ eface,
+                                                const uint32_t* __restrict__ eflags,
+                                                const int32_t* __restrict__ ecaller,
+                                                const int32_t* __restrict__ fcanon, double* __restrict__ U,
+                                                double* __restrict__ P, double* __restrict__ Ujump) {
+  constexpr int N = D + 1;
+  int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k >= ne) return;
+  const uint32_t fl = eflags[k];
+  double u[N][D], p;
+  int fc[N];
+  recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, eface, fcanon, u, p, fc);
   P[ecaller[k]] = p;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -1059,6 +1080,47 @@ __global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __rest
 #pragma unroll
     for (int i = 0; i < D; ++i) dst[(int64_t)fc[j] * D + i] = u[j][i];
   }
+}
+
+// Copy mismatch without a second velocity array: after k_recover has written
+// the owner copies to U, each element recomputes its copies and adds the
+// squared difference of its non-owner copies (C = -1) to U; one partial per
+// workgroup, part[blockIdx.x].
+template <int D, bool NSK>
+__global__ void __launch_bounds__(BS) k_recover_mismatch(int64_t ne, const double* __restrict__ y,
+                                                         const double* __restrict__ dsq,
+                                                         const double* __restrict__ pack,
+                                                         const double* __restrict__ RK,
+                                                         const int32_t* __restrict__ eface,
+                                                         const uint32_t* __restrict__ eflags,
+                                                         const int32_t* __restrict__ fcanon,
+                                                         const double* __restrict__ U, double* __restrict__ part) {
+  constexpr int N = D + 1;
+  __shared__ double sh[BS];
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double s = 0.0;
+  if (k < ne) {
+    const uint32_t fl = eflags[k];
+    double u[N][D], p;
+    int fc[N];
+    recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, eface, fcanon, u, p, fc);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (fc[j] < 0 || csign(fl, j) > 0.0) continue;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double t = u[j][i] - U[(int64_t)fc[j] * D + i];
+        s += t * t;
+      }
+    }
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 // deterministic sum of squared differences: per-block partials then one block
@@ -1331,6 +1393,80 @@ cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {
     const int64_t n = s->nf * d;
     hipLaunchKernelGGL(k_sqdiff_partial, dim3(1024), dim3(256), 0, s->stream, n, U, Uj, Uj + n);
     hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s->stream, 1024, Uj + n, jump);
+  }
+  return check_hip(hipGetLastError(), "recover launch");
+}
+
+// Device address of the scratch array on each device, taken once per device
+// with that device current.
+namespace {
+constexpr int SCRATCH_MAXDEV = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[SCRATCH_MAXDEV] = {};
+
+cr_status scratch_address(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= SCRATCH_MAXDEV) {
+    set_error("device %d out of range for the allocation-free recovery", dev);
+    return CR_E_INVAL;
+  }
+  if (!g_scratch[dev]) {
+    int cur = -1;
+    cr_status st = check_hip(hipGetDevice(&cur), "hipGetDevice");
+    if (st != CR_OK) return st;
+    if (cur != dev) {
+      st = check_hip(hipSetDevice(dev), "hipSetDevice");
+      if (st != CR_OK) return st;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const cr_status back = check_hip(hipSetDevice(cur), "hipSetDevice (restore)");
+      if (back != CR_OK) return back;
+    }
+    st = check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (st != CR_OK) return st;
+    g_scratch[dev] = (double*)p;
+  }
+  *out = g_scratch[dev];
+  return CR_OK;
+}
+}  // namespace
+
+cr_status run_recover_noalloc(cr_system* s, double* U, double* P, double* jump) {
+  const int d = s->d;
+  const bool ns = s->params.problem == CR_NS_NEWTON;
+  const unsigned ge = nblocks(s->ne, BS);
+  double* part = nullptr;
+  if (jump) {
+    if ((int64_t)ge > NOALLOC_PARTIALS) {
+      set_error("cr_recover_noalloc: %lld elements exceed its limit of %lld (one partial per %d elements)",
+                (long long)s->ne, (long long)(NOALLOC_PARTIALS * BS), BS);
+      return CR_E_INVAL;
+    }
+    const cr_status st = scratch_address(s->device, &part);
+    if (st != CR_OK) return st;
+  }
+  if (ns)
+    hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+  else if (d == 2)
+    hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+  else
+    hipLaunchKernelGGL((k_recover<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+  if (jump) {
+    if (ns)
+      hipLaunchKernelGGL((k_recover_mismatch<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
+                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+    else if (d == 2)
+      hipLaunchKernelGGL((k_recover_mismatch<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
+                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+    else
+      hipLaunchKernelGGL((k_recover_mismatch<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
+                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+    hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s->stream, (int)ge, part, jump);
   }
   return check_hip(hipGetLastError(), "recover launch");
 }
