@@ -1,24 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the hybridised Crouzeix-Raviart transient-Stokes solve on one MI355X.
 
-Workload (default): 2D transient Stokes on the unit square, 512 x 512 cells cut
-into 2 triangles (524,288 elements), interior vertices jittered by up to 0.2 h
-(seeded), nu = 1, mu = 1/dt = 1000, homogeneous Dirichlet, right-hand side from
-a seeded smooth manufactured velocity; hybridised SPD system of 1,570,816
-unknowns solved to ||S - G W|| <= 1e-10 ||S|| (FP64 residual) by Jacobi-scaled
-CG with G applied from its element factors: FP32 CG iterations with FP64
-residual replacements (--precision fp64: FP64 iterations).
+Headline workload (default, the largest configuration that fits one GPU): 3D
+transient Stokes on the unit cube, 64^3 cubes each cut into 6 Kuhn tetrahedra
+(1,572,864 elements, 9,363,456 face unknowns), nu = 1, mu = 1/dt = 100,
+homogeneous Dirichlet, right-hand side from a seeded smooth manufactured
+velocity; hybridised SPD system solved to ||S - G W|| <= 1e-9 ||S|| (FP64
+residual) by CG with Jacobi scaling and an aggregate coarse correction, G
+applied from its element factors, FP32 iterations inside FP64 residual
+replacement (--precision fp64: FP64 iterations).
 
 One step = the whole hot path on device-resident inputs: element-wise
 elimination and assembly of G and S, Krylov solve, element-wise recovery of U
-and P.  The value is steps (solves) per second.  Also reported: the dominant
-kernel's achieved bandwidth against the HBM peak (timed with HIP events on the
-solver's stream), the same kernel of the assembled operator, the other Krylov
-precision, the FP64 MINRES solve of the
-original coupled system on the same GPU, and the CPU oracle on a bounded
-sample of the workload.
+and P.  The value is steps (solves) per second.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Also reported on the same line: the dominant kernel's achieved bandwidth
+against the HBM peak and against a measured device copy (HIP events on the
+solver's stream) with the counter-measured traffic; the error of U and P
+against the stored FP64 oracle solution; the Jacobi-only solve and the FP64
+MINRES solve of the original coupled system on the same GPU (like-for-like
+speedup); the FP64-iteration solve; the 2D 512x512x2 workload (its working set
+fits the 256 MB Infinity Cache, so its bandwidth is labelled MALL-resident
+possible); the steady Navier-Stokes Newton step; the serving run; and the CPU
+oracle on a bounded sample of the headline workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube64|square512j]
 """
 from __future__ import annotations
 
@@ -26,6 +32,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -33,13 +40,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# dominant kernel of the timed path: the element kernel of the element-form CG
-KERNEL = {"fp64": "k_ec1<2, double>", "fp32_ir": "k_ec1<2, float>"}
 METRIC = "hybridised solve time & SpMV HBM GB/s vs coupled solve; solves/s, p99 latency"
+
+WORKLOADS = {
+    "cube64": dict(
+        dim=3, mu=100.0, nu=1.0, tol=1e-9, coupled_maxit=100000,
+        label="3D transient Stokes, unit cube 64^3 cubes x 6 Kuhn tetrahedra, nu=1, mu=1/dt=100, manufactured "
+              "RHS; hybridised SPD system, CG with Jacobi scaling and aggregate coarse correction, G applied from "
+              "element factors",
+        bound="hbm"),
+    "square512j": dict(
+        dim=2, mu=1000.0, nu=1.0, tol=1e-10, coupled_maxit=60000,
+        label="2D transient Stokes, unit square 512x512 cells x2 triangles, jitter 0.2h (seed 0), nu=1, "
+              "mu=1/dt=1000, manufactured RHS; hybridised SPD system, CG with Jacobi scaling and aggregate coarse "
+              "correction, G applied from element factors",
+        bound="MALL-resident possible"),
+}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_name(dim, precision):
+    return f"k_ec1<{dim}, {'float' if precision == 'fp32_ir' else 'double'}>"
 
 
 # source of the dominant kernel: its own code, the shared iteration start and
@@ -74,10 +98,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_ec1_{precision}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -87,23 +111,84 @@ def measured_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_oracle_baseline(ne_target, mu, nu, n_sample=128):
-    """Oracle (sparse LU of the coupled system, FP64) on a 128x128x2 sample of the
-    same workload family, scaled linearly in the element count to the target."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def load_workload(name):
+    import synth.workloads as wl
+    return {"cube64": wl.cube64, "square512j": wl.square512j}[name]()
+
+
+def oracle_error(name, U, P):
+    """Error of U and P against the stored FP64 oracle solution of the workload
+    (tests/golden/oracle_<name>.npz: written by tests/golden/make_oracle_samples.py
+    from the oracle alone), on its sampled faces and elements."""
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return {"status": "parity unpinned: no stored oracle solution for this workload"}
+    z = np.load(path)
+    fi = torch.from_numpy(z["face_ids"].astype(np.int64)).to(U.device)
+    ei = torch.from_numpy(z["elem_ids"].astype(np.int64)).to(P.device)
+    Us = U.index_select(0, fi).cpu().numpy()
+    Ps = P.index_select(0, ei).cpu().numpy()
+    Uo, Po = z["U"], z["P"]
+    rec = json.loads(str(z["record"]))
+    return {"U_rel2": float(np.linalg.norm(Us - Uo) / np.linalg.norm(Uo)),
+            "U_max_rel": float(np.abs(Us - Uo).max() / float(z["U_max"])),
+            "P_rel2": float(np.linalg.norm(Ps - Po) / np.linalg.norm(Po)),
+            "P_max_rel": float(np.abs(Ps - Po).max() / float(z["P_max"])),
+            "sample": f"{len(fi)} faces and {len(ei)} elements (seeded, plus the pinned element's corner)",
+            "oracle": rec.get("method"), "oracle_record": {k: rec[k] for k in rec if k not in ("workload", "method")}}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy of nbytes, timed with HIP events: bytes read + written / time."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_oracle_baseline(ne_target, n_sample=10):
+    """The oracle's primary result (assembly and sparse LU of the coupled system,
+    FP64, one thread) on a bounded sample of the headline workload family: the
+    same 3D transient Stokes problem on n_sample^3 cubes x 6 tetrahedra, timed on
+    this host and scaled linearly in the element count to the target."""
     import synth.workloads as wl
     from oracle import cr
-    w = wl.square(n_sample, mu=mu, nu=nu, jitter=0.2, seed=0, quad=3)
-    t0, c0 = time.perf_counter(), time.process_time()
-    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
-    cr.solve_coupled(P)
-    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    from threadpoolctl import threadpool_limits
+    w = wl.cube(n_sample, mu=100.0, quad=2)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+        cr.solve_coupled(P)
+        wall = time.perf_counter() - t0
     ne_s = len(w["elems"])
     t_scaled = wall * ne_target / ne_s
-    return {"value": 1.0 / t_scaled, "unit": "solves/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": (f"oracle coupled sparse-LU solve (assembly + SuperLU + back-substitution, FP64) of the same "
-                       f"workload on {n_sample}x{n_sample}x2 elements ({ne_s}), {wall:.2f} s wall, scaled linearly "
-                       f"by element count to {ne_target} elements (sparse LU grows faster, so this favours the CPU)")}
+    return {"value": 1.0 / t_scaled, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(), "sample_seconds": round(wall, 2),
+            "sample": (f"oracle coupled sparse-LU solve (assembly + SuperLU + back-substitution, FP64, one thread) "
+                       f"of the same 3D transient Stokes problem on {n_sample}^3 x 6 = {ne_s} elements, "
+                       f"{wall:.1f} s, scaled linearly by element count to {ne_target} elements (3D sparse LU grows "
+                       f"much faster than linearly, so this favours the CPU)")}
 
 
 def run_serving(args):
@@ -131,43 +216,144 @@ def run_serving(args):
     return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()}
 
 
-def run_other_workloads(crh, wl, torch):
-    """The 3D and Navier-Stokes workloads through the same library calls (not
-    the benchmark line): 64^3 cubes x 6 tetrahedra transient Stokes (mu = 100),
-    and the steady Navier-Stokes Newton step on 256x256x2 (nu = 0.01)."""
-    out = {}
+def measure_transient(crh, torch, name, args, steps, warmup, precision, copy_gbps, headline):
+    """Steps of eliminate + solve + recover on one transient-Stokes workload, and
+    everything reported beside them for that workload."""
+    import numpy as np
+    cfg = WORKLOADS[name]
     t0 = time.perf_counter()
-    w = wl.cube64()
-    log(f"64^3 x 6 inputs: {time.perf_counter() - t0:.1f} s")
-    s = crh.System(w["coords"], w["elems"], w["mu"], w["nu"])
-    s.eliminate(torch.from_numpy(w["fbar"]).cuda())
-    rec = {"workload": "3D transient Stokes, unit cube 64^3 cubes x 6 Kuhn tetrahedra, nu=1, mu=100, "
-                       "manufactured RHS, CG to rel residual 1e-10",
-           "elements": len(w["elems"]), "unknowns": s.n_int_faces * 3}
-    for prec in ("fp32_ir", "fp64"):
-        info = s.solve("pcg", prec, tol=1e-10)
-        rec[prec] = {"time_to_tol_ms": round(info["t_solve_ms"], 2), "iters": info["iters"],
-                     "rel_residual": info["rel_residual"], "fp64_fallback": info["fp64_fallback"]}
-        log(f"64^3 x 6 {prec}: {info['t_solve_ms']:.1f} ms, {info['iters']} iterations")
-    ms, by = s.time_spmv("fp32_ir", reps=100)
-    rec["k_ec1<3, float>"] = {"avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(by),
-                              "achieved_GBps": round(by / (ms * 1e-3) / 1e9, 1)}
+    w = load_workload(name)
+    log(f"{name}: inputs {len(w['elems'])} elements, {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    s = crh.System(w["coords"], w["elems"], cfg["mu"], cfg["nu"])
+    t_topo = time.perf_counter() - t0
+    log(f"{name}: topology + upload {t_topo:.2f} s, {s.n_int_faces} interior faces")
+    fbar = torch.from_numpy(w["fbar"]).cuda()
+    stream = torch.cuda.current_stream()
+    tol = cfg["tol"]
+
+    def step(record):
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        e0.record(stream)
+        s.eliminate(fbar)
+        e1.record(stream)
+        info = s.solve("pcg", precision, tol=tol)
+        e2.record(stream)
+        U, P = s.recover()
+        e3.record(stream)
+        e3.synchronize()
+        if record is not None:
+            record.append(dict(elim_ms=e0.elapsed_time(e1), solve_ms=e1.elapsed_time(e2),
+                               recover_ms=e2.elapsed_time(e3), total_ms=e0.elapsed_time(e3), **info))
+        return U, P
+
+    for k in range(warmup):
+        step(None)
+        log(f"{name}: warmup {k + 1}/{warmup} done")
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        U, P = step(recs)
+        log(f"{name}: step {k + 1}/{steps}: {recs[-1]['total_ms']:.1f} ms, {recs[-1]['iters']} iterations, "
+            f"rel residual {recs[-1]['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([r["total_ms"] for r in recs])
+    last = recs[-1]
+    solve_ms = float(np.median([r["solve_ms"] for r in recs]))
+
+    err = oracle_error(name, U, P)
+    log(f"{name}: error vs oracle {json.dumps({k: v for k, v in err.items() if k.endswith('rel2') or k.endswith('rel')})}")
+
+    # dominant kernel: the element kernel of the CG iteration (operator applied
+    # from element factors, fused with the direction update), timed with HIP
+    # events on the solver's stream inside the iteration sequence
+    ms_k, bytes_k = s.time_spmv(precision, reps=200)
+    gbs = bytes_k / (ms_k * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, precision),
+            "kernel": kernel_name(cfg["dim"], precision), "avg_launch_us": round(ms_k * 1e3, 2),
+            "algorithmic_bytes_per_launch": int(bytes_k), "measured_copy_GBps": round(copy_gbps, 1),
+            "frac_of_copy": round(gbs / copy_gbps, 4)}
+    if cfg["bound"] != "hbm":
+        roof["label"] = cfg["bound"]
+    log(f"{name}: dominant kernel {ms_k * 1e3:.2f} us/launch, {gbs:.0f} GB/s "
+        f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak, {100 * gbs / copy_gbps:.1f}% of the measured copy)")
+
+    # accuracy diagnostic: copy mismatch of the recovered velocity (equals the residual)
+    s.solve("pcg", precision, tol=tol)
+    _, _, J = s.recover(jump=True)
+    torch.cuda.synchronize()
+
+    # Jacobi only (no coarse correction): the like-for-like comparison with the
+    # coupled solve, which has a diagonal preconditioner
+    info_j = s.solve("pcg", precision, tol=tol, coarse=False, maxit=200000)
+    log(f"{name}: Jacobi-only solve {info_j['t_solve_ms']:.1f} ms, {info_j['iters']} iterations")
+    # the other Krylov precision
+    other = "fp64" if precision == "fp32_ir" else "fp32_ir"
+    info_o = s.solve("pcg", other, tol=tol)
+    log(f"{name}: {other} solve {info_o['t_solve_ms']:.1f} ms, {info_o['iters']} iterations")
+
+    coupled = None
+    if not args.no_coupled:
+        Uc, Pc, ci = s.coupled_solve(tol=tol, maxit=cfg["coupled_maxit"], raise_on_error=False)
+        torch.cuda.synchronize()
+        diff = (torch.linalg.norm(Uc - U) / torch.linalg.norm(U)).item()
+        coupled = {"method": "FP64 MINRES on eq. syslin, diagonal block preconditioner diag(A) + "
+                             "diag(D diag(A)^-1 D^t)",
+                   "time_ms": round(ci["t_solve_ms"], 2), "iters": ci["iters"], "maxit": cfg["coupled_maxit"],
+                   "rel_residual": ci["rel_residual"], "converged": ci["status"] == 0,
+                   "rel_diff_U_vs_hybrid": diff,
+                   "speedup_hybrid_jacobi_only": round(ci["t_solve_ms"] / info_j["t_solve_ms"], 2),
+                   "speedup_hybrid_coarse": round(ci["t_solve_ms"] / solve_ms, 2)}
+        log(f"{name}: coupled MINRES {ci['t_solve_ms']:.1f} ms, {ci['iters']} iterations, "
+            f"residual {ci['rel_residual']:.2e}, converged={ci['status'] == 0}")
+        del Uc, Pc
+
+    out = {
+        "workload": cfg["label"] + f", to rel residual {tol:g} "
+                   f"({'FP32 iterations inside FP64 residual replacement' if precision == 'fp32_ir' else 'FP64'})",
+        "elements": len(w["elems"]), "unknowns": s.n_int_faces * cfg["dim"], "tol": tol, "precision": precision,
+        "solves_per_s": round(steps / wall, 4), "ms_per_step": round(1e3 * wall / steps, 3),
+        "time_to_tol_ms": round(solve_ms, 3), "iters": last["iters"], "outer_iters": last["outer_iters"],
+        "rel_residual": last["rel_residual"], "fp64_fallback": last["fp64_fallback"], "copy_mismatch": J.item(),
+        "eliminate_ms": round(float(np.median([r["elim_ms"] for r in recs])), 3),
+        "recover_ms": round(float(np.median([r["recover_ms"] for r in recs])), 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "topology_host_s": round(t_topo, 3),
+        "err_vs_oracle": err,
+        "roofline": roof,
+        "jacobi_only": {"time_to_tol_ms": round(info_j["t_solve_ms"], 3), "iters": info_j["iters"],
+                        "rel_residual": info_j["rel_residual"]},
+        f"{other}_iterations": {"time_to_tol_ms": round(info_o["t_solve_ms"], 3), "iters": info_o["iters"],
+                                "fp32_iters": info_o["fp32_iters"], "fp64_fallback": info_o["fp64_fallback"],
+                                "rel_residual": info_o["rel_residual"]},
+        "coupled_gpu": coupled,
+        "steps": steps, "warmup": warmup,
+    }
     s.close()
-    out["stokes3d_64"] = rec
+    del U, P, fbar
+    torch.cuda.empty_cache()
+    return out, wall
+
+
+def run_ns(crh, torch):
+    """Steady Navier-Stokes Newton step on 256x256x2 (nu = 0.01), BiCGStab(2), FP64."""
+    import synth.workloads as wl
     t0 = time.perf_counter()
     w = wl.ns256()
     log(f"NS 256x256x2 inputs: {time.perf_counter() - t0:.1f} s")
     s = crh.System(w["coords"], w["elems"], 0.0, w["nu"], problem="ns")
     s.eliminate(torch.from_numpy(w["fbar"]).cuda(), None, torch.from_numpy(w["ulin"]).cuda())
     info = s.solve("bicgstab2", "fp64", tol=1e-9, maxit=600000, raise_on_error=False)
-    out["ns_newton_256"] = {
-        "workload": "2D steady Navier-Stokes Newton step, 256x256x2, nu=0.01, seeded linearisation velocity, "
-                    "E_K from the M1/M2 partition; BiCGStab(2), FP64, to rel residual 1e-9",
-        "elements": len(w["elems"]), "unknowns": s.n_int_faces * 2, "status": info["status"],
-        "time_to_tol_ms": round(info["t_solve_ms"], 1), "iters": info["iters"],
-        "products_with_G": 4 * info["iters"], "rel_residual": info["rel_residual"]}
-    log(f"NS 256x256x2 BiCGStab(2): {info['t_solve_ms']:.0f} ms, {info['iters']} iterations, "
-        f"status {info['status']}")
+    out = {"workload": "2D steady Navier-Stokes Newton step, 256x256x2, nu=0.01, seeded linearisation velocity, "
+                       "E_K from the M1/M2 partition; BiCGStab(2), FP64, to rel residual 1e-9",
+           "elements": len(w["elems"]), "unknowns": s.n_int_faces * 2, "status": info["status"],
+           "time_to_tol_ms": round(info["t_solve_ms"], 1), "iters": info["iters"],
+           "products_with_G": 4 * info["iters"], "rel_residual": info["rel_residual"],
+           "err_vs_oracle": {"status": "parity unpinned: no stored oracle solution for this workload"}}
+    log(f"NS 256x256x2 BiCGStab(2): {info['t_solve_ms']:.0f} ms, {info['iters']} iterations, status {info['status']}")
     s.close()
     return out
 
@@ -175,15 +361,13 @@ def run_other_workloads(crh, wl, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32_ir", choices=["fp32_ir", "fp64"],
                     help="Krylov arithmetic of the timed path (the other one is reported beside it)")
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--n", type=int, default=512, help="cells per side (512 = the benchmark workload)")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--coupled-maxit", type=int, default=60000)
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="time-step requests of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.5,
@@ -191,9 +375,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=8.0, help="device-memory budget for admission")
     ap.add_argument("--serve-precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     ap.add_argument("--no-other", action="store_true",
-                    help="skip the 64^3 x 6 and the Navier-Stokes 256x256x2 solves reported beside the benchmark")
+                    help="skip the second transient workload and the Navier-Stokes step")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="only build the system and time the dominant kernel (for counter collection)")
+                    help="only build the workload's system and time the dominant kernel (for counter collection)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 20 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -202,11 +386,9 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2101_03777_amd as crh
-    import synth.workloads as wl
 
     crh.load()
     torch.cuda.set_device(0)
@@ -219,96 +401,30 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 20}), flush=True)
         return
-    mu, nu, n = 1000.0, 1.0, args.n
-    t0 = time.perf_counter()
-    w = wl.square(n, mu=mu, nu=nu, jitter=0.2, seed=0, quad=3)
-    log(f"inputs {n}x{n}x2: {len(w['elems'])} elements, {time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    s = crh.System(w["coords"], w["elems"], mu, nu)
-    t_topo = time.perf_counter() - t0
-    log(f"topology + upload: {t_topo:.2f} s, {s.n_int_faces} interior faces")
-    fbar = torch.from_numpy(w["fbar"]).cuda()
-    stream = torch.cuda.current_stream()
     if args.kernel_only:
-        s.eliminate(fbar)
+        cfg = WORKLOADS[args.workload]
+        w = load_workload(args.workload)
+        s = crh.System(w["coords"], w["elems"], cfg["mu"], cfg["nu"])
+        s.eliminate(torch.from_numpy(w["fbar"]).cuda())
         ms_k, bytes_k = s.time_spmv(args.precision, reps=200)
-        print(json.dumps({"kernel": KERNEL[args.precision], "precision": args.precision, "avg_us": ms_k * 1e3,
-                          "algorithmic_bytes": bytes_k, "GBps": bytes_k / (ms_k * 1e-3) / 1e9}), flush=True)
+        print(json.dumps({"kernel": kernel_name(cfg["dim"], args.precision), "workload": args.workload,
+                          "precision": args.precision, "avg_us": ms_k * 1e3, "algorithmic_bytes": bytes_k,
+                          "GBps": bytes_k / (ms_k * 1e-3) / 1e9}), flush=True)
         s.close()
         return
 
-    def step(record):
-        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
-        e0.record(stream)
-        s.eliminate(fbar)
-        e1.record(stream)
-        info = s.solve("pcg", args.precision, tol=args.tol)
-        e2.record(stream)
-        U, P = s.recover()
-        e3.record(stream)
-        e3.synchronize()
-        if record is not None:
-            record.append(dict(elim_ms=e0.elapsed_time(e1), solve_ms=e1.elapsed_time(e2),
-                               recover_ms=e2.elapsed_time(e3), total_ms=e0.elapsed_time(e3), **info))
-        return U, P
+    copy_gbps = copy_bandwidth(torch)
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
+    head, wall = measure_transient(crh, torch, args.workload, args, args.steps, args.warmup, args.precision,
+                                   copy_gbps, True)
 
-    for k in range(args.warmup):
-        step(None)
-        log(f"warmup {k + 1}/{args.warmup} done")
-    recs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(recs)
-        log(f"step {k + 1}/{args.steps}: {recs[-1]['total_ms']:.1f} ms, {recs[-1]['iters']} iterations, "
-            f"rel residual {recs[-1]['rel_residual']:.2e}")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = np.array([r["total_ms"] for r in recs])
-    last = recs[-1]
-
-    # dominant kernel: the element kernel of the CG iteration (operator applied
-    # from element factors, fused with the direction update), timed with HIP
-    # events on the solver's stream
-    ms_k, bytes_k = s.time_spmv(args.precision, reps=200)
-    gbs = bytes_k / (ms_k * 1e-3) / 1e9
-    traffic = measured_traffic(f"square{n}j", "ec1_" + args.precision)
-    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL[args.precision],
-                "avg_launch_us": round(ms_k * 1e3, 2), "algorithmic_bytes_per_launch": int(bytes_k)}
-    log(f"dominant kernel: {ms_k * 1e3:.2f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
-    ms_a, bytes_a = s.time_spmv(args.precision, reps=200, operator="assembled")
-    assembled = {"kernel": f"k_cg_spmv<2, {'float' if args.precision == 'fp32_ir' else 'double'}, 0>",
-                 "avg_launch_us": round(ms_a * 1e3, 2), "algorithmic_bytes_per_launch": int(bytes_a),
-                 "achieved_GBps": round(bytes_a / (ms_a * 1e-3) / 1e9, 1)}
-    info_a = s.solve("pcg", args.precision, tol=args.tol, operator="assembled")
-    assembled.update(time_to_tol_ms=round(info_a["t_solve_ms"], 3), iters=info_a["iters"])
-    log(f"assembled operator: {ms_a * 1e3:.2f} us/launch; solve {info_a['t_solve_ms']:.1f} ms, "
-        f"{info_a['iters']} iterations")
-
-    # accuracy diagnostic: copy mismatch of the recovered velocity (equals the residual)
-    s.solve("pcg", args.precision, tol=args.tol)
-    U, P, J = s.recover(jump=True)
-    torch.cuda.synchronize()
-
-    # the other Krylov precision on the same solve
-    other = "fp64" if args.precision == "fp32_ir" else "fp32_ir"
-    s.eliminate(fbar)
-    info64 = s.solve("pcg", other, tol=args.tol)
-    log(f"{other} solve: {info64['t_solve_ms']:.1f} ms, {info64['iters']} iterations "
-        f"({info64['fp32_iters']} in FP32, fallback to FP64: {info64['fp64_fallback']})")
-
-    coupled = None
-    if not args.no_coupled:
-        Uc, Pc, ci = s.coupled_solve(tol=args.tol, maxit=args.coupled_maxit, raise_on_error=False)
-        torch.cuda.synchronize()
-        diff = (torch.linalg.norm(Uc - U) / torch.linalg.norm(U)).item()
-        coupled = {"method": "FP64 MINRES, diagonal block preconditioner diag(A) + diag(D diag(A)^-1 D^t)",
-                   "time_ms": round(ci["t_solve_ms"], 2), "iters": ci["iters"],
-                   "rel_residual": ci["rel_residual"], "converged": ci["status"] == 0,
-                   "rel_diff_U_vs_hybrid": diff}
-        log(f"coupled MINRES: {ci['t_solve_ms']:.1f} ms, {ci['iters']} iterations, "
-            f"residual {ci['rel_residual']:.2e}, converged={ci['status'] == 0}")
+    second = None
+    ns = None
+    if not args.no_other:
+        other = "square512j" if args.workload == "cube64" else "cube64"
+        second, _ = measure_transient(crh, torch, other, args, max(3, args.steps // 2), 1, args.precision, copy_gbps,
+                                      False)
+        ns = run_ns(crh, torch)
 
     serving = None
     if args.serve_requests > 0:
@@ -316,51 +432,42 @@ def main():
         log(f"serving: {serving['requests']} requests, {serving['solves_per_s']:.1f} solves/s, "
             f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms")
 
-    others = None if args.no_other else run_other_workloads(crh, wl, torch)
-
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_oracle_baseline(len(w["elems"]), mu, nu)
-        log(f"cpu oracle: {cpu['value']:.4f} solves/s ({cpu['sample']})")
+        cpu = cpu_oracle_baseline(head["elements"]) if WORKLOADS[args.workload]["dim"] == 3 else None
+        if cpu:
+            log(f"cpu oracle: {cpu['value']:.3g} solves/s ({cpu['sample']})")
 
     out = {
         "metric": METRIC,
-        "value": round(args.steps / wall, 4),
+        "value": head["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "fp32_ir" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D transient Stokes, unit square {n}x{n} cells x2 triangles, jitter 0.2h (seed 0), "
-                               f"nu=1, mu=1/dt=1000, manufactured RHS; hybridised SPD system, Jacobi-scaled CG "
-                               f"({'FP32 inside FP64 iterative refinement' if args.precision == 'fp32_ir' else 'FP64'})"
-                               f" with G applied from element factors, to rel residual {args.tol:g}",
-                   "elements": len(w["elems"]),
-                   "unknowns": s.n_int_faces * 2, "tol": args.tol, "precision": args.precision},
-        "roofline": roofline,
+        "config": {"workload": head["workload"], "elements": head["elements"], "unknowns": head["unknowns"],
+                   "tol": head["tol"], "precision": args.precision},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "time_to_tol_ms": round(float(np.median([r["solve_ms"] for r in recs])), 3),
-        "iters": last["iters"], "outer_iters": last["outer_iters"], "rel_residual": last["rel_residual"],
-        "copy_mismatch": J.item(),
-        "eliminate_ms": round(float(np.median([r["elim_ms"] for r in recs])), 3),
-        "recover_ms": round(float(np.median([r["recover_ms"] for r in recs])), 3),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "topology_host_s": round(t_topo, 3),
-        f"{other}_time_to_tol_ms": round(info64["t_solve_ms"], 3), f"{other}_iters": info64["iters"],
-        f"{other}_fp32_iters": info64["fp32_iters"], f"{other}_fp64_fallback": info64["fp64_fallback"],
-        "assembled_operator": assembled,
-        "coupled_gpu": coupled,
-        "speedup_vs_coupled": (round(coupled["time_ms"] / float(np.median([r['solve_ms'] for r in recs])), 2)
-                               if coupled else None),
+        "err_vs_oracle": head["err_vs_oracle"],
+        "time_to_tol_ms": head["time_to_tol_ms"], "iters": head["iters"], "outer_iters": head["outer_iters"],
+        "rel_residual": head["rel_residual"], "copy_mismatch": head["copy_mismatch"],
+        "eliminate_ms": head["eliminate_ms"], "recover_ms": head["recover_ms"],
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "jacobi_only": head["jacobi_only"],
+        "coupled_gpu": head["coupled_gpu"],
+        "headline_detail": {k: v for k, v in head.items()
+                            if k not in ("roofline", "err_vs_oracle", "coupled_gpu", "jacobi_only")},
+        "second_workload": second,
+        "ns_newton_256": ns,
         "serving": serving,
-        "other_workloads": others,
     }
-    s.close()
     print(json.dumps(out), flush=True)
 
 

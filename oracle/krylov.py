@@ -10,8 +10,11 @@ from __future__ import annotations
 import numpy as np
 
 
-def pcg(G, b, tol=1e-12, maxit=100000, x0=None):
-    """Solve G x = b to ||b - G x|| <= tol ||b||.  Returns (x, iterations, history)."""
+def pcg(G, b, tol=1e-12, maxit=100000, x0=None, callback=None):
+    """Solve G x = b to ||b - G x|| <= tol ||b||.  Returns (x, iterations, history).
+
+    callback(iteration, relative recursive residual), if given, is called after
+    every iteration (progress reporting only)."""
     dinv = 1.0 / G.diagonal()
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - G @ x
@@ -32,4 +35,6 @@ def pcg(G, b, tol=1e-12, maxit=100000, x0=None):
         rz = rz_new
         it += 1
         hist.append(np.linalg.norm(r) / nb)
+        if callback is not None:
+            callback(it, hist[-1])
     return x, it, hist

@@ -549,7 +549,10 @@ __device__ __forceinline__ void ec1_pass(const CgSys& S, int par, int64_t lo, in
   // EB elements (stride NT) per pass: indices, flags, factors, and r and the
   // previous direction at their faces are all loaded before any is used;
   // indices past the range are clamped to its last element (ne >= 1), so the
-  // loads carry no branches
+  // loads carry no branches.  In 3D the element data (read once) is loaded
+  // non-temporally, so that it does not push the gathered face vectors, which
+  // neighbouring elements read again, out of the L2 (measured on 64^3 x 6:
+  // 4.5% fewer bytes fetched, 7% faster; in 2D it is slower)
   for (int64_t Kb = lo + threadIdx.x; Kb < hi; Kb += (int64_t)EB * NT) {
     int32_t g[EB][N];
     uint32_t fl[EB];
@@ -558,11 +561,19 @@ __device__ __forceinline__ void ec1_pass(const CgSys& S, int par, int64_t lo, in
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int64_t K = min(Kb + (int64_t)e * NT, hi - 1);
-      fl[e] = S.eflags[K];
+      if constexpr (D == 3) {
+        fl[e] = __builtin_nontemporal_load(S.eflags + K);
 #pragma unroll
-      for (int l = 0; l < N; ++l) g[e][l] = S.egat[(int64_t)l * ne + K];
+        for (int l = 0; l < N; ++l) g[e][l] = __builtin_nontemporal_load(S.egat + (int64_t)l * ne + K);
 #pragma unroll
-      for (int c = 0; c < L::NF; ++c) fv[e][c] = F[(int64_t)c * ne + K];
+        for (int c = 0; c < L::NF; ++c) fv[e][c] = __builtin_nontemporal_load(F + (int64_t)c * ne + K);
+      } else {
+        fl[e] = S.eflags[K];
+#pragma unroll
+        for (int l = 0; l < N; ++l) g[e][l] = S.egat[(int64_t)l * ne + K];
+#pragma unroll
+        for (int c = 0; c < L::NF; ++c) fv[e][c] = F[(int64_t)c * ne + K];
+      }
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e)

@@ -19,16 +19,9 @@ namespace crh {
 
 namespace {
 
-// recursive coordinate bisection of idx[lo, hi) into `parts` (a power of two)
-// groups at the median of the longest centroid extent; group ids in
-// depth-first order
-void rcb(std::vector<int32_t>& idx, size_t lo, size_t hi, int parts, const std::vector<double>& cen, int d,
-         int& next, std::vector<int32_t>& agg) {
-  if (parts == 1 || hi - lo < 2) {
-    for (size_t i = lo; i < hi; ++i) agg[idx[i]] = next;
-    ++next;
-    return;
-  }
+// Bisects idx[lo, hi) at the median of the longest centroid extent (ties by
+// element id) and returns the split position.
+size_t bisect(std::vector<int32_t>& idx, size_t lo, size_t hi, const std::vector<double>& cen, int d) {
   int ax = 0;
   double best = -1.0;
   for (int a = 0; a < d; ++a) {
@@ -48,8 +41,30 @@ void rcb(std::vector<int32_t>& idx, size_t lo, size_t hi, int parts, const std::
     const double ca = cen[(size_t)a * d + ax], cb = cen[(size_t)b * d + ax];
     return ca < cb || (ca == cb && a < b);
   });
+  return mid;
+}
+
+// recursive coordinate bisection of idx[lo, hi) into `parts` (a power of two)
+// groups; group ids in depth-first order, and idx ends up grouped in that order
+void rcb(std::vector<int32_t>& idx, size_t lo, size_t hi, int parts, const std::vector<double>& cen, int d,
+         int& next, std::vector<int32_t>& agg) {
+  if (parts == 1 || hi - lo < 2) {
+    for (size_t i = lo; i < hi; ++i) agg[idx[i]] = next;
+    ++next;
+    return;
+  }
+  const size_t mid = bisect(idx, lo, hi, cen, d);
   rcb(idx, lo, mid, parts / 2, cen, d, next, agg);
   rcb(idx, mid, hi, parts / 2, cen, d, next, agg);
+}
+
+// the same bisection continued down to `leaf` elements: a depth-first order in
+// which elements that are close in the order are close in space
+void rcb_order(std::vector<int32_t>& idx, size_t lo, size_t hi, const std::vector<double>& cen, int d, size_t leaf) {
+  if (hi - lo <= leaf) return;
+  const size_t mid = bisect(idx, lo, hi, cen, d);
+  rcb_order(idx, lo, mid, cen, d, leaf);
+  rcb_order(idx, mid, hi, cen, d, leaf);
 }
 
 struct LocalFace {
@@ -240,6 +255,7 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
   }
 
   // face renumbering
+  std::vector<int32_t> loc_elem_order;  // element order chosen with the aggregates (empty: none)
   t.face_perm.assign(nf, -1);
   t.face_iperm.assign(nf, -1);
   if (renumber == CR_NATURAL) {
@@ -294,8 +310,16 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     // MAX_AGG = 512: measured on 512x512x2 and 64^3x6; none below 4 parts),
     // numbered in bisection order so that consecutive aggregates are
     // neighbours.  A face belongs to the aggregate of its owner element (the
-    // lower caller id, C = +1).  Faces are grouped by aggregate, in RCM order
-    // inside a group.
+    // lower caller id, C = +1).
+    // With aggregates the element-form CG gathers its vectors element by
+    // element, so the order is chosen for locality of those gathers rather
+    // than for a narrow band: the bisection continues inside each aggregate
+    // down to a few elements (elements close in the order are close in space;
+    // the elements with faces in several aggregates come last within their
+    // aggregate), and faces are numbered in the order the elements first touch
+    // them, grouped by aggregate.  The two elements of most faces then fall in
+    // the same workgroup pass, and the faces a wavefront gathers lie on few
+    // cache lines.
     const int agg_cap = d == 3 ? MAX_AGG : 256;
     const int64_t agg_min = d == 3 ? 1024 : 2048;
     int nagg = 1;
@@ -313,6 +337,37 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
       rcb(idx, 0, (size_t)ne, nagg, cen, d, next, eagg);
       std::vector<int32_t> fagg(nf);
       for (int64_t f = 0; f < nf; ++f) fagg[f] = eagg[t.face_elem[2 * f]];
+      // idx is grouped by aggregate in aggregate order; order each group
+      for (size_t lo = 0; lo < (size_t)ne;) {
+        size_t hi = lo;
+        while (hi < (size_t)ne && eagg[idx[hi]] == eagg[idx[lo]]) ++hi;
+        rcb_order(idx, lo, hi, cen, d, 4);
+        lo = hi;
+      }
+      std::vector<uint8_t> multi(ne, 0);
+      for (int64_t k = 0; k < ne; ++k) {
+        int a0 = -1;
+        for (int j = 0; j < d1; ++j) {
+          const int f = t.elem_face[k * d1 + j];
+          if (f < 0) continue;
+          if (a0 < 0) a0 = fagg[f];
+          else if (fagg[f] != a0) multi[k] = 1;
+        }
+      }
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+        return eagg[a] != eagg[b] ? eagg[a] < eagg[b] : multi[a] < multi[b];
+      });
+      loc_elem_order = idx;
+      order.clear();
+      std::vector<uint8_t> seen(nf, 0);
+      for (int64_t i = 0; i < ne; ++i)
+        for (int j = 0; j < d1; ++j) {
+          const int f = t.elem_face[(int64_t)idx[i] * d1 + j];
+          if (f >= 0 && !seen[f]) {
+            seen[f] = 1;
+            order.push_back(f);
+          }
+        }
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fagg[a] < fagg[b]; });
       t.nagg = nagg;
       t.face_agg.resize(nf);
@@ -339,10 +394,10 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     t.bw_internal = bandwidth(t.face_perm);
   }
 
-  // element order: by smallest internal face id, ties by caller id; with
-  // aggregates, the elements whose faces lie in more than one aggregate come
-  // last within the range of their aggregate, so that few wavefronts of the
-  // element kernel handle the coarse term
+  // element order: with aggregates, the locality order above (the elements
+  // whose faces lie in more than one aggregate last within the range of their
+  // aggregate, so that few wavefronts of the element kernel handle the coarse
+  // term); otherwise by smallest internal face id, ties by caller id
   {
     std::vector<int64_t> key(ne);
     for (int64_t k = 0; k < ne; ++k) {
@@ -363,7 +418,10 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     }
     t.elem_iperm.resize(ne);
     std::iota(t.elem_iperm.begin(), t.elem_iperm.end(), 0);
-    std::stable_sort(t.elem_iperm.begin(), t.elem_iperm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    if (!loc_elem_order.empty())
+      t.elem_iperm = loc_elem_order;
+    else
+      std::stable_sort(t.elem_iperm.begin(), t.elem_iperm.end(), [&](int a, int b) { return key[a] < key[b]; });
     t.elem_perm.resize(ne);
     for (int64_t i = 0; i < ne; ++i) t.elem_perm[t.elem_iperm[i]] = (int32_t)i;
   }
