@@ -73,6 +73,18 @@ enum { CR_FP64 = 0, CR_FP32_IR = 1 };
  *   G_K (Section 3.2 items 4-5), without reading the assembled G (CG on
  *   transient Stokes only). */
 enum { CR_OP_AUTO = 0, CR_OP_ASSEMBLED = 1, CR_OP_ELEMENT = 2 };
+/* preconditioning (cr_solve_opts.precond).  Every method runs on the Jacobi-
+ * scaled system Ds G Ds, one scale per face (Ds_f = (mean over the d components
+ * of |diag G|)^{-1/2}; the paper only asks for a Krylov method, Section 3.2
+ * items 6-7).  CG with the element form adds an additive aggregate coarse
+ * correction M^-1 = I + Z E^-1 Z^t (one column per aggregate: the null vector
+ * of the gauge-shifted G restricted to the aggregate's faces):
+ * CR_PC_DEFAULT: Jacobi scaling, plus the coarse correction where the mesh has
+ *   aggregates (transient Stokes meshes of at least 8192 elements in 2D, 4096 in 3D);
+ * CR_PC_JACOBI: Jacobi scaling only;
+ * CR_PC_COARSE: the coarse correction is required: CR_E_INVAL where it does
+ *   not exist (no aggregates, or another method or operator form). */
+enum { CR_PC_DEFAULT = 0, CR_PC_JACOBI = 1, CR_PC_COARSE = 2 };
 
 typedef struct cr_system cr_system;
 
@@ -97,7 +109,8 @@ typedef struct {
 /* Coefficients of the strong form (Section 2): mu = 1/dt (transient) or 0
  * (steady), nu = 1/Re > 0.  k0 is the element whose pressure is pinned to 0
  * (Section 2 item 5).  problem = CR_NS_NEWTON selects the Newton linearisation
- * of the convection form b_h (eq. defbh) about u_lin (2D only). */
+ * of the convection form b_h (eq. defbh) about u_lin (2D and 3D; in 3D the 12 x 12
+ * local matrices of the elimination are formed and inverted in LDS). */
 typedef struct {
   double mu, nu;
   int32_t k0;
@@ -110,7 +123,7 @@ typedef struct {
  * reverse Cuthill-McKee face order (or natural), element order, and for mu = 0
  * the element partition M1/M2 of Section 3.2 item 7 (greedy maximal independent
  * set in caller order).  Host work plus host-to-device copies on hip_stream.
- * Errors: CR_E_INVAL (dim not 2/3, nu <= 0, mu < 0, k0 out of range, NS in 3D),
+ * Errors: CR_E_INVAL (dim not 2/3, nu <= 0, mu < 0, k0 out of range),
  * CR_E_MESH (see above), CR_E_NOMEM, CR_E_DEVICE.  *out is NULL on error. */
 cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params,
                       const cr_allocator* alloc, void* hip_stream, cr_system** out);
@@ -143,9 +156,13 @@ void cr_prepared_destroy(cr_prepared* prep);
 cr_status cr_eliminate(cr_system* sys, const double* f_mean, const double* u_prev,
                        const double* u_lin);
 
-/* Step a6: new right-hand side with the same G (constant time step, Stokes only):
- * recomputes R_K and s_K from the stored element factors and re-gathers S.
- * Same argument meaning as cr_eliminate.  Asynchronous. */
+/* Step a6: new right-hand side with the same G (constant time step, Stokes only).
+ * In the transient problem of Section 2 the force f carries the velocity of the
+ * previous time step, and R_K is its face moment (eq. defrhs): only R_K and
+ * s_K change from step to step, G does not (Section 3.2 items 4-5).  Recomputes
+ * R_K and s_K from the stored element factors and re-gathers S.  Same argument
+ * meaning as cr_eliminate.  Asynchronous.  Errors: CR_E_INVAL (NULL system or
+ * f_mean, before cr_eliminate, Navier-Stokes). */
 cr_status cr_update_rhs(cr_system* sys, const double* f_mean, const double* u_prev);
 
 typedef struct {
@@ -160,9 +177,11 @@ typedef struct {
   int32_t use_graph;   /* 1: replay the iteration block as a captured hipGraph */
   int32_t warm_start;  /* 1: start from the resident W of the previous solve, 0: from W = 0 */
   int32_t operator_form; /* CR_OP_AUTO, CR_OP_ASSEMBLED or CR_OP_ELEMENT */
-  int32_t coarse;      /* 0: element-form CG adds the coarse correction where the mesh
-                          has aggregates (2D meshes of at least 8192 elements, 3D of at
-                          least 4096); 1: Jacobi only */
+  int32_t precond;     /* CR_PC_DEFAULT, CR_PC_JACOBI or CR_PC_COARSE (below) */
+  const double* w0;    /* device [n_int_faces][dim] initial W (canonical), or NULL; when
+                          given it replaces the resident W and the solve starts from it
+                          (warm_start is then implied).  Ignored by cr_batch_add and
+                          cr_coupled_solve. */
 } cr_solve_opts;
 
 typedef struct {
@@ -185,7 +204,7 @@ typedef struct {
  * Ds_f = (mean over the d components of |diag G|)^{-1/2}.
  * CG with the element form adds an aggregate coarse correction (one column per
  * aggregate: the null vector of the gauge-shifted G restricted to the
- * aggregate's faces; opts.coarse); it changes the iterations, not the solution.
+ * aggregate's faces; opts.precond); it changes the iterations, not the solution.
  * CR_FP32_IR runs the Krylov recurrences in FP32 with FP64 residual
  * replacements; if the FP32 iterations stop reducing the FP64 residual, the
  * remaining iterations run in FP64 (reported in cr_solve_info.fp64_fallback).
@@ -218,15 +237,21 @@ cr_status cr_recover(cr_system* sys, double* U, double* P, double* jump);
  * Asynchronous; arguments, layouts and other errors as cr_recover. */
 cr_status cr_recover_noalloc(cr_system* sys, double* U, double* P, double* jump);
 
-/* Sizes of the system: interior faces, structural non-zeros of G (d x d blocks
- * of the stencil), non-zeros of the coupled matrix [A D^t; D 0]. Any pointer may be NULL. */
+/* Sizes of the system: interior faces (Section 2 item 1), structural non-zeros
+ * of G (d x d blocks of the stencil of A, Section 3.2 item 5: a diagonal block
+ * per face and one block per ordered pair of faces of an element), non-zeros of
+ * the coupled matrix [A D^t; D 0] of eq. syslin.  Any output pointer may be
+ * NULL.  Host only, no device work.  Errors: CR_E_INVAL (NULL system). */
 cr_status cr_query_sizes(const cr_system* sys, int64_t* n_int_faces, int64_t* nnz_G,
                          int64_t* nnz_coupled);
 
-/* Host copy of G (FP64, CSR, canonical face-major numbering, structural
- * entries of the stencil) and of S.  Buffers sized from cr_query_sizes:
- * rowptr [n+1], col [nnz_G], val [nnz_G], S [n] with n = dim * n_int_faces.
- * Synchronises. */
+/* Host copy of the hybridised system G W = S of Section 3.2 item 5 (G =
+ * sum_K H_K G_K H_K^t, S = sum_K H_K s_K), unscaled, FP64 CSR in canonical
+ * face-major numbering (row dim*face + component), structural entries of the
+ * stencil (zeros kept), columns sorted within a row.  Caller-owned host
+ * buffers sized from cr_query_sizes: rowptr [n+1], col [nnz_G], val [nnz_G],
+ * S [n] with n = dim * n_int_faces.  Synchronises.  Errors: CR_E_INVAL (NULL
+ * system or buffer, before cr_eliminate), CR_E_DEVICE. */
 cr_status cr_export_G(const cr_system* sys, int64_t* rowptr, int32_t* col, double* val, double* S);
 
 /* Host copy of the coupled system of Section 3.1 (eq. syslin), Stokes only:
@@ -249,7 +274,10 @@ cr_status cr_export_W(const cr_system* sys, double* W);
  * recover U and P from a W computed elsewhere.  Synchronises. */
 cr_status cr_import_W(cr_system* sys, const double* W);
 
-/* Host copy of the interior faces [n_int_faces][dim] as sorted vertex ids, canonical order. */
+/* Host copy of the interior faces of Section 2 item 1 (faces shared by two
+ * elements) as sorted vertex ids, [n_int_faces][dim] int32, in the canonical
+ * order (lexicographic in those ids) that U, W, u_prev and u_lin use.
+ * Caller-owned host buffer.  Errors: CR_E_INVAL (NULL system or buffer). */
 cr_status cr_interior_faces(const cr_system* sys, int32_t* face_vertices);
 
 /* Host-only topology (step a0 without any device work), for inspection:
@@ -261,10 +289,17 @@ cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t
                       int32_t* perm, int64_t* bandwidth_internal, int64_t* bandwidth_canonical,
                       int32_t* m1);
 
-/* Baseline: FP64 MINRES on the original coupled system [A D^t; D 0] on the same
- * GPU, preconditioned by the positive diagonal diag(A) (+) diag(D diag(A)^{-1} D^t);
- * Stokes only.  Same stopping rule on the coupled residual ||[R;0] - M [U;P]|| / ||R||.
- * U, P as in cr_recover.  Synchronises.  Errors: CR_E_NOCONV (best iterate written). */
+/* Baseline: a Krylov solve of the original coupled system of Section 3.1
+ * (eq. syslin) [A D^t; D 0][U; P] = [R; 0] on the same GPU, FP64, without the
+ * hybridisation, preconditioned by the positive diagonal
+ * diag|A| (+) diag(D diag|A|^{-1} D^t).  Stokes (symmetric): MINRES.  Newton
+ * step (non-symmetric): BiCGStab(2) (opts->method CR_BICGSTAB2, the default
+ * for it) or BiCGStab.  Stops on the coupled residual
+ * ||[R;0] - M [U;P]|| <= tol ||R||; opts->tol, maxit, check_every are used,
+ * the other fields ignored.  U, P as in cr_recover (device, caller-owned).
+ * Its workspace (about 12 vectors of the coupled size) is allocated on first
+ * use.  Synchronises.  Errors: CR_E_NOCONV (iteration limit; best iterate
+ * written), CR_E_BREAKDOWN, CR_E_NONFINITE, CR_E_INVAL (before cr_eliminate). */
 cr_status cr_coupled_solve(cr_system* sys, const cr_solve_opts* opts, cr_solve_info* info,
                            double* U, double* P);
 

@@ -25,6 +25,8 @@ CR_PCG, CR_BICGSTAB, CR_BICGSTAB2, CR_MINRES = 0, 1, 2, 3
 CR_FP64, CR_FP32_IR = 0, 1
 CR_OP_AUTO, CR_OP_ASSEMBLED, CR_OP_ELEMENT = 0, 1, 2
 _OPFORM = {"auto": CR_OP_AUTO, "assembled": CR_OP_ASSEMBLED, "element": CR_OP_ELEMENT}
+CR_PC_DEFAULT, CR_PC_JACOBI, CR_PC_COARSE = 0, 1, 2
+_PRECOND = {"default": CR_PC_DEFAULT, "jacobi": CR_PC_JACOBI, "coarse": CR_PC_COARSE}
 
 # every function declared in include/crhyb.h
 EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recover", "cr_query_sizes",
@@ -62,7 +64,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double), ("inner_tol", C.c_double),
                 ("maxit", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("warm_start", C.c_int32), ("operator_form", C.c_int32),
-                ("coarse", C.c_int32)]
+                ("precond", C.c_int32), ("w0", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -203,12 +205,18 @@ class TorchAllocator:
         return sum(self.live.values())
 
 
+METHODS = {"pcg": CR_PCG, "bicgstab": CR_BICGSTAB, "bicgstab2": CR_BICGSTAB2, "minres": CR_MINRES}
+
+
 def solve_opts(method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-               check_every=0, graph=True, warm_start=False, operator="auto", coarse=True):
-    return SolveOpts({"pcg": CR_PCG, "bicgstab": CR_BICGSTAB, "bicgstab2": CR_BICGSTAB2, "minres": CR_MINRES}[method],
-                     {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol), float(inner_tol),
-                     int(maxit), int(max_outer), int(check_every), int(bool(graph)), int(bool(warm_start)),
-                     _OPFORM[operator], 0 if coarse else 1)
+               check_every=0, graph=True, warm_start=False, operator="auto", coarse=True, precond=None, w0=None):
+    """cr_solve_opts; precond ("default", "jacobi", "coarse") overrides coarse
+    (True: "default", False: "jacobi"); w0 is a device float64 tensor
+    [n_int_faces, dim] (canonical) or None."""
+    pc = _PRECOND[precond] if precond is not None else (CR_PC_DEFAULT if coarse else CR_PC_JACOBI)
+    return SolveOpts(METHODS[method], {"fp64": CR_FP64, "fp32_ir": CR_FP32_IR}[precision], float(tol),
+                     float(inner_tol), int(maxit), int(max_outer), int(check_every), int(bool(graph)),
+                     int(bool(warm_start)), _OPFORM[operator], pc, None if w0 is None else w0.data_ptr())
 
 
 def info_dict(st, info):
@@ -356,9 +364,11 @@ class System:
         _check(self.lib.cr_update_rhs(self.h, _ptr(f), _ptr(up)))
 
     def solve(self, method="pcg", precision="fp32_ir", tol=1e-10, inner_tol=0.0, maxit=0, max_outer=0,
-              check_every=0, graph=True, warm_start=False, raise_on_error=True, operator="auto", coarse=True):
+              check_every=0, graph=True, warm_start=False, raise_on_error=True, operator="auto", coarse=True,
+              precond=None, w0=None):
+        w0 = self._dev(w0, (self.n_int_faces, self.dim))
         o = solve_opts(method, precision, tol, inner_tol, maxit, max_outer, check_every, graph, warm_start,
-                       operator, coarse)
+                       operator, coarse, precond, w0)
         info = SolveInfo()
         st = self.lib.cr_solve(self.h, C.byref(o), C.byref(info))
         out = info_dict(st, info)
@@ -384,11 +394,14 @@ class System:
                 raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
         _check(self.lib.cr_recover_noalloc(self.h, _ptr(U), _ptr(P), _ptr(J)))
 
-    def coupled_solve(self, tol=1e-10, maxit=0, check_every=0, raise_on_error=True):
+    def coupled_solve(self, tol=1e-10, maxit=0, check_every=0, raise_on_error=True, method=None):
+        """cr_coupled_solve: FP64 Krylov on the coupled system (MINRES for Stokes,
+        BiCGStab(2) or method="bicgstab" for the Newton step)."""
         torch = self._torch
         U = torch.empty((self.n_int_faces, self.dim), dtype=torch.float64, device="cuda")
         P = torch.empty((self.n_elements,), dtype=torch.float64, device="cuda")
-        o = SolveOpts(0, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0, CR_OP_AUTO, 0)
+        m = METHODS[method] if method is not None else 0
+        o = SolveOpts(m, CR_FP64, float(tol), 0.0, int(maxit), 1, int(check_every), 0, 0, CR_OP_AUTO, 0, None)
         info = SolveInfo()
         st = self.lib.cr_coupled_solve(self.h, C.byref(o), C.byref(info), _ptr(U), _ptr(P))
         if raise_on_error:

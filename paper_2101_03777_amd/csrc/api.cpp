@@ -79,7 +79,10 @@ cr_status build(cr_system* s) {
   s->ne = ne;
   s->nf = nf;
   const bool ns = s->params.problem == CR_NS_NEWTON;
-  s->npack = ns ? 49 : (d1 * (d1 + 1) / 2 + d1 * d + 1);
+  // Newton step: A^_K^{-1} (NU x NU, NU = (d+1) d), l, r, 1/B; Stokes: S_K^{-1}
+  // (symmetric), V = A^_K^{-1} D_K, 1/B
+  const int nu_loc = d1 * d;
+  s->npack = ns ? nu_loc * nu_loc + 2 * nu_loc + 1 : (d1 * (d1 + 1) / 2 + d1 * d + 1);
   return CR_OK;
 }
 
@@ -125,10 +128,6 @@ cr_status check_params(const cr_mesh_desc* mesh, const cr_params* p) {
   }
   if (p->problem != CR_STOKES && p->problem != CR_NS_NEWTON) {
     set_error("unknown problem kind %d", p->problem);
-    return CR_E_INVAL;
-  }
-  if (p->problem == CR_NS_NEWTON && mesh->dim != 2) {
-    set_error("the Navier-Stokes Newton step is implemented in 2D only");
     return CR_E_INVAL;
   }
   if (p->k0 < 0 || p->k0 >= mesh->n_elements) {

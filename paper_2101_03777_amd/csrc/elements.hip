@@ -294,83 +294,187 @@ __global__ void __launch_bounds__(BS) k_rhs_stokes(int64_t ne, const double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Navier-Stokes Newton step, 2D (N = 3 faces, 6 local unknowns, index j*2+i).
-// A_K = S_K (x) I_2 + d/du [N_K(u, u)] at ubar, where
+// Navier-Stokes Newton step (N = d+1 faces, NU = N d local unknowns, index j*d+i).
+// A_K = S_K (x) I_d + d/du [N_K(u, u)] at ubar, where
 //   N_K(w, z)_{s,i} = 1/2 sum_{t != s} F_{s,t}(w) (z_{t,i} - z_{s,i}),
-//   F_{s,t}(w) = (W_s + W_t - sum_q W_q / 3) . (a_t - a_s) / 3
+//   F_{s,t}(w) = (W_s + W_t - sum_q W_q / N) . (a_t - a_s) / N
 // (second form of eq. defbh and the flux closed form of Section 2 item 6), and
 // R_K = R_f + N_K(ubar, ubar) (Newton right-hand side).  Exterior faces carry
 // U = 0 inside the sums; their rows and columns are removed.
 // ---------------------------------------------------------------------------
+template <int D>
 struct NsPack {
-  static constexpr int NU = 6;
+  static constexpr int N = D + 1;
+  static constexpr int NU = N * D;
   static constexpr int SIZE = NU * NU + 2 * NU + 1;  // A^{-1}, l, r, 1/B
 };
 
-__device__ __forceinline__ void ns_local(const Geo<2>& g, uint32_t fl, const double (&Ub)[3][2], double mu, double nu,
-                                         double (&A)[6][6], double (&Nuu)[3][2]) {
-  const double m = mu * g.vol / 3.0, iv = nu / g.vol;
-  double F[3][3], gx[3][3][2];
+// A(r, c) of a local NU x NU matrix: in registers (2D), or in the calling
+// thread's column of an LDS array (3D: 144 doubles per element)
+template <int NU>
+struct RegMat {
+  double (&m)[NU][NU];
+  __device__ double& operator()(int r, int c) const { return m[r][c]; }
+};
+
+template <int NU>
+struct LdsMat {
+  double* base;  // entry (0, 0) of this thread; consecutive entries `stride` doubles apart
+  int stride;
+  __device__ double& operator()(int r, int c) const { return base[(r * NU + c) * stride]; }
+};
+
+template <int D, class M>
+__device__ __forceinline__ void ns_local(const Geo<D>& g, uint32_t fl, const double (&Ub)[D + 1][D], double mu,
+                                         double nu, const M& A, double (&Nuu)[D + 1][D]) {
+  constexpr int N = D + 1;
+  const double m = mu * g.vol / N, iv = nu / g.vol;
+  double F[N][N], gx[N][N][D], Um[D];
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
+  for (int j = 0; j < D; ++j) {
+    double t = Ub[0][j];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int q = 1; q < N; ++q) t += Ub[q][j];
+    Um[j] = t / N;
+  }
+#pragma unroll
+  for (int s = 0; s < N; ++s)
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
       double v = 0.0;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        gx[s][t][j] = (g.a[t][j] - g.a[s][j]) / 3.0;
-        double w = Ub[s][j] + Ub[t][j] - (Ub[0][j] + Ub[1][j] + Ub[2][j]) / 3.0;
+      for (int j = 0; j < D; ++j) {
+        gx[s][t][j] = (g.a[t][j] - g.a[s][j]) / N;
+        double w = Ub[s][j] + Ub[t][j] - Um[j];
         v += w * gx[s][t][j];
       }
       F[s][t] = s == t ? 0.0 : v;
     }
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < N; ++s)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < D; ++i) {
       double v = 0.0;
 #pragma unroll
-      for (int t = 0; t < 3; ++t) v += 0.5 * F[s][t] * (Ub[t][i] - Ub[s][i]);
+      for (int t = 0; t < N; ++t) v += 0.5 * F[s][t] * (Ub[t][i] - Ub[s][i]);
       Nuu[s][i] = v;
     }
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    double rowF = F[s][0] + F[s][1] + F[s][2];
+  for (int s = 0; s < N; ++s) {
+    double rowF = F[s][0];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 1; t < N; ++t) rowF += F[s][t];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
           double v = 0.0;
           if (i == j) {
-            v += (s == r ? m : 0.0) + iv * (g.a[s][0] * g.a[r][0] + g.a[s][1] * g.a[r][1]);
+            double ar = 0.0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) ar += g.a[s][q] * g.a[r][q];
+            v += (s == r ? m : 0.0) + iv * ar;
             v += 0.5 * ((s == r ? 0.0 : F[s][r]) - (s == r ? rowF : 0.0));
           }
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
+          for (int t = 0; t < N; ++t) {
             if (t == s) continue;
-            double coef = (r == s ? 1.0 : 0.0) + (r == t ? 1.0 : 0.0) - 1.0 / 3.0;
+            double coef = (r == s ? 1.0 : 0.0) + (r == t ? 1.0 : 0.0) - 1.0 / N;
             v += 0.5 * coef * gx[s][t][j] * (Ub[t][i] - Ub[s][i]);
           }
           bool in = interior(fl, s) && interior(fl, r);
-          A[s * 2 + i][r * 2 + j] = in ? v : ((s == r && i == j) ? 1.0 : 0.0);
+          A(s * D + i, r * D + j) = in ? v : ((s == r && i == j) ? 1.0 : 0.0);
         }
   }
 }
 
+template <int D>
 __device__ __forceinline__ void load_ubar(const double* __restrict__ ulin, const int32_t* __restrict__ eface,
-                                          uint32_t fl, int64_t ne, int64_t k, double (&Ub)[3][2]) {
+                                          uint32_t fl, int64_t ne, int64_t k, double (&Ub)[D + 1][D]) {
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    bool in = interior(fl, j);
+  for (int j = 0; j <= D; ++j) {
+    bool in = ulin != nullptr && interior(fl, j);
     int f = in ? eface[j * ne + k] : 0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) Ub[j][i] = in ? ulin[(int64_t)f * 2 + i] : 0.0;
+    for (int i = 0; i < D; ++i) Ub[j][i] = in ? ulin[(int64_t)f * D + i] : 0.0;
   }
 }
 
+// In-place Gauss-Jordan inverse of an NU x NU matrix behind an accessor, with
+// partial pivoting (row exchanges, recorded 4 bits per step, undone as column
+// exchanges in reverse order at the end).  Runtime loops: for matrices kept in
+// LDS.  Returns false on a zero or non-finite pivot.
+template <int NU, class M>
+__device__ bool gj_inverse_inplace(const M& A) {
+  static_assert(NU <= 16, "pivot record holds 4 bits per step");
+  uint64_t piv = 0;
+  bool ok = true;
+  for (int k = 0; k < NU; ++k) {
+    int p = k;
+    double best = fabs(A(k, k));
+    for (int r = k + 1; r < NU; ++r) {
+      const double v = fabs(A(r, k));
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    piv |= (uint64_t)p << (4 * k);
+    if (p != k)
+      for (int c = 0; c < NU; ++c) {
+        const double t = A(k, c);
+        A(k, c) = A(p, c);
+        A(p, c) = t;
+      }
+    const double pv = A(k, k);
+    if (!(pv != 0.0) || !isfinite(pv)) ok = false;
+    const double ip = 1.0 / pv;
+    A(k, k) = 1.0;
+    for (int c = 0; c < NU; ++c) A(k, c) *= ip;
+    for (int r = 0; r < NU; ++r) {
+      if (r == k) continue;
+      const double f = A(r, k);
+      A(r, k) = 0.0;
+      for (int c = 0; c < NU; ++c) A(r, c) -= f * A(k, c);
+    }
+  }
+  for (int k = NU - 1; k >= 0; --k) {
+    const int p = (int)((piv >> (4 * k)) & 15u);
+    if (p != k)
+      for (int r = 0; r < NU; ++r) {
+        const double t = A(r, k);
+        A(r, k) = A(r, p);
+        A(r, p) = t;
+      }
+  }
+  return ok;
+}
+
 // lambda_K = 2 ||A_K||_inf over the interior rows/columns, for K in M1 (Section 3.2 item 7)
+template <int D, class M>
+__device__ __forceinline__ void ns_lambda_elem(int64_t ne, int64_t k, const double* __restrict__ ecoord,
+                                               uint32_t fl, const int32_t* __restrict__ eface,
+                                               const double* __restrict__ ulin, double mu, double nu, const M& A,
+                                               double* __restrict__ lam) {
+  constexpr int NU = NsPack<D>::NU;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  double Ub[D + 1][D], Nuu[D + 1][D];
+  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  double mx = 0.0;
+#pragma unroll
+  for (int r = 0; r < NU; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) s += interior(fl, c / D) ? fabs(A(r, c)) : 0.0;
+    mx = interior(fl, r / D) ? fmax(mx, s) : mx;
+  }
+  lam[k] = 2.0 * mx;
+}
+
 __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __restrict__ ecoord,
                                                   const uint32_t* __restrict__ eflags,
                                                   const int32_t* __restrict__ eface,
@@ -383,24 +487,28 @@ __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __re
     lam[k] = 0.0;
     return;
   }
-  Geo<2> g;
-  load_geometry<2>(ecoord, ne, k, g);
-  double Ub[3][2], A[6][6], Nuu[3][2];
-  if (ulin != nullptr)
-    load_ubar(ulin, eface, fl, ne, k, Ub);
-  else
-#pragma unroll
-    for (int j = 0; j < 3; ++j) Ub[j][0] = Ub[j][1] = 0.0;
-  ns_local(g, fl, Ub, mu, nu, A, Nuu);
-  double mx = 0.0;
-#pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) s += interior(fl, c / 2) ? fabs(A[r][c]) : 0.0;
-    mx = interior(fl, r / 2) ? fmax(mx, s) : mx;
+  double A[6][6];
+  ns_lambda_elem<2>(ne, k, ecoord, fl, eface, ulin, mu, nu, RegMat<6>{A}, lam);
+}
+
+// threads per block of the 3D Newton-step element kernels (LDS: 144 doubles per thread)
+constexpr int BS_NS3 = 64;
+constexpr size_t LDS_NS3 = sizeof(double) * 144 * BS_NS3;
+
+__global__ void __launch_bounds__(BS_NS3) k_ns_lambda3(int64_t ne, const double* __restrict__ ecoord,
+                                                       const uint32_t* __restrict__ eflags,
+                                                       const int32_t* __restrict__ eface,
+                                                       const double* __restrict__ ulin, double mu, double nu,
+                                                       double* __restrict__ lam) {
+  extern __shared__ double lds_ns[];
+  int64_t k = (int64_t)blockIdx.x * BS_NS3 + threadIdx.x;
+  if (k >= ne) return;
+  const uint32_t fl = eflags[k];
+  if (!(fl & F_M1)) {
+    lam[k] = 0.0;
+    return;
   }
-  lam[k] = 2.0 * mx;
+  ns_lambda_elem<3>(ne, k, ecoord, fl, eface, ulin, mu, nu, LdsMat<12>{lds_ns + threadIdx.x, BS_NS3}, lam);
 }
 
 // Stokes steady (mu = 0) lambda: same rule with the Stokes element matrix
@@ -472,11 +580,11 @@ __global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __rest
   load_geometry<2>(ecoord, ne, k, g);
   const uint32_t fl = eflags[k];
   double Ub[3][2], A[6][6], Nuu[3][2];
-  load_ubar(ulin, eface, fl, ne, k, Ub);
+  load_ubar<2>(ulin, eface, fl, ne, k, Ub);
   bool fin = true;
 #pragma unroll
   for (int j = 0; j < 3; ++j) fin = fin && isfinite(Ub[j][0]) && isfinite(Ub[j][1]);
-  ns_local(g, fl, Ub, mu, nu, A, Nuu);
+  ns_local<2>(g, fl, Ub, mu, nu, RegMat<6>{A}, Nuu);
   if (lam != nullptr) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -562,6 +670,122 @@ __global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __rest
   pack[(int64_t)48 * ne + k] = F.invB;
 }
 
+// a1 + a2, 3D Newton step: as k_elim_ns with the 12 x 12 local matrix of a
+// tetrahedron, built and inverted (partial pivoting) in the thread's column of
+// an LDS array, since it does not fit in registers with its inverse.
+__global__ void __launch_bounds__(BS_NS3) k_elim_ns3(int64_t ne, const double* __restrict__ ecoord,
+                                                     const uint32_t* __restrict__ eflags,
+                                                     const int32_t* __restrict__ eface,
+                                                     const int32_t* __restrict__ enb, const double* __restrict__ lam,
+                                                     const double* __restrict__ fbar,
+                                                     const double* __restrict__ uprev,
+                                                     const double* __restrict__ ulin, double mu, double nu,
+                                                     double* __restrict__ pack, double* __restrict__ RK,
+                                                     double* __restrict__ sK, int32_t* err) {
+  constexpr int D = 3, N = 4, NU = 12;
+  extern __shared__ double lds_ns[];
+  int64_t k = (int64_t)blockIdx.x * BS_NS3 + threadIdx.x;
+  if (k >= ne) return;
+  const LdsMat<NU> A{lds_ns + threadIdx.x, BS_NS3};
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  double Ub[N][D], Nuu[N][D];
+  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) fin = fin && isfinite(Ub[j][i]);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  if (lam != nullptr) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double e = 0.0;
+      if (fl & F_M1) {
+        e = -lam[k];
+      } else {
+        int nb = enb[j * ne + k];
+        if (nb >= 0 && (eflags[nb] & F_M1)) e = lam[nb];
+      }
+      if (interior(fl, j))
+#pragma unroll
+        for (int i = 0; i < D; ++i) A(j * D + i, j * D + i) += e;
+    }
+  }
+  const bool ok = gj_inverse_inplace<NU>(A);
+  double Dv[NU], lv[NU], rv[NU];
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) Dv[j * D + i] = interior(fl, j) ? -g.a[j][i] : 0.0;
+  double B = 0.0;
+#pragma unroll
+  for (int a = 0; a < NU; ++a) {
+    double l = 0.0, r = 0.0;
+#pragma unroll
+    for (int b = 0; b < NU; ++b) {
+      l += A(a, b) * Dv[b];
+      r += A(b, a) * Dv[b];
+    }
+    lv[a] = l;
+    rv[a] = r;
+    B += Dv[a] * l;
+  }
+  if (!ok || !isfinite(B) || !(fabs(B) > 0.0)) report(err, ERR_SINGULAR, k);
+  const bool k0 = fl & F_K0;
+  const double invB = k0 ? 0.0 : 1.0 / B;
+  if (k0) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) lv[a] = rv[a] = 0.0;
+  }
+  // right-hand side: eq. defrhs + Newton completion + transient lumped mass
+  double fb[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    fb[i] = fbar[k * D + i];
+    fin = fin && isfinite(fb[i]);
+  }
+  double R[NU];
+  const double m = mu * g.vol / N;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double proj = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) proj += fb[i] * (g.xK[i] - g.X[j][i]);
+    proj *= 1.0 / D;
+    bool in = interior(fl, j);
+    int f = in ? eface[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double rr = g.a[j][i] * proj + Nuu[j][i];
+      if (uprev != nullptr && in) rr += m * uprev[(int64_t)f * D + i];
+      R[j * D + i] = in ? rr : 0.0;
+    }
+  }
+  if (!fin) report(err, ERR_NONFINITE, k);
+  double rR = 0.0;
+#pragma unroll
+  for (int a = 0; a < NU; ++a) rR += rv[a] * R[a];
+  rR *= invB;
+#pragma unroll
+  for (int a = 0; a < NU; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < NU; ++b) t += A(a, b) * R[b];
+    RK[(int64_t)a * ne + k] = R[a];
+    sK[(int64_t)a * ne + k] = csign(fl, a / D) * (t - lv[a] * rR);
+  }
+  for (int a = 0; a < NU; ++a)
+    for (int b = 0; b < NU; ++b) pack[(int64_t)(a * NU + b) * ne + k] = A(a, b);
+#pragma unroll
+  for (int a = 0; a < NU; ++a) {
+    pack[(int64_t)(NU * NU + a) * ne + k] = lv[a];
+    pack[(int64_t)(NU * NU + NU + a) * ne + k] = rv[a];
+  }
+  pack[(int64_t)(NU * NU + 2 * NU) * ne + k] = invB;
+}
+
 // ---------------------------------------------------------------------------
 // a3: gather assembly of G (Section 3.2 item 5: G = sum_K H_K G_K H_K^t) into
 // block-ELL, one thread per interior face row f.  Slot 0 is the diagonal block
@@ -581,6 +805,27 @@ struct BlockSrc<D, false> {
   __device__ void load(const double* pack, int64_t ne, int64_t k) { load_stokes_pack<D>(pack, ne, k, F); }
   __device__ double g(int j, int i, int l, int ip) const {
     return (i == ip ? F.Si[j][l] : 0.0) - F.V[j][i] * F.V[l][ip] * F.invB;
+  }
+};
+
+// Newton step, any d: entries read from the pack where they are used (the 3D
+// pack holds 169 numbers per element)
+template <int D>
+struct BlockSrc<D, true> {
+  static constexpr int NU = NsPack<D>::NU;
+  const double* pack;
+  int64_t ne, k;
+  double invB;
+  __device__ void load(const double* p, int64_t n, int64_t kk) {
+    pack = p;
+    ne = n;
+    k = kk;
+    invB = pack[(int64_t)(NU * NU + 2 * NU) * ne + k];
+  }
+  __device__ double g(int j, int i, int l, int ip) const {
+    const int a = j * D + i, b = l * D + ip;
+    return pack[(int64_t)(a * NU + b) * ne + k] -
+           pack[(int64_t)(NU * NU + a) * ne + k] * pack[(int64_t)(NU * NU + NU + b) * ne + k] * invB;
   }
 };
 
@@ -1041,17 +1286,17 @@ __device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t 
         u[j][i] = t - p * F.V[j][i];
       }
   } else {
-    NsFactors F;
-    load_ns_pack(pack, ne, k, F);
+    // pack: A^{-1} [NU][NU], l [NU], r [NU], 1/B
+    constexpr int NU = NsPack<D>::NU;
 #pragma unroll
-    for (int a = 0; a < 6; ++a) p += F.r[a] * rhs[a / 2][a % 2];
-    p *= F.invB;
+    for (int a = 0; a < NU; ++a) p += pack[(int64_t)(NU * NU + NU + a) * ne + k] * rhs[a / D][a % D];
+    p *= pack[(int64_t)(NU * NU + 2 * NU) * ne + k];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
+    for (int a = 0; a < NU; ++a) {
       double t = 0.0;
 #pragma unroll
-      for (int b = 0; b < 6; ++b) t += F.Ai[a][b] * rhs[b / 2][b % 2];
-      u[a / 2][a % 2] = t - p * F.l[a];
+      for (int b = 0; b < NU; ++b) t += pack[(int64_t)(a * NU + b) * ne + k] * rhs[b / D][b % D];
+      u[a / D][a % D] = t - p * pack[(int64_t)(NU * NU + a) * ne + k];
     }
   }
 }
@@ -1121,6 +1366,17 @@ __global__ void __launch_bounds__(BS) k_recover_mismatch(int64_t ne, const doubl
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// initial W from a caller array in canonical order: y = dsq * W (internal order)
+__global__ void __launch_bounds__(BS) k_import_w(int64_t n, int d, const int32_t* __restrict__ fcanon,
+                                                 const double* __restrict__ dsq, const double* __restrict__ w0,
+                                                 double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t >= n * d) return;
+  const int64_t f = t / d;
+  const int i = (int)(t - f * d);
+  y[t] = dsq[t] * w0[(int64_t)fcanon[f] * d + i];
 }
 
 // deterministic sum of squared differences: per-block partials then one block
@@ -1250,7 +1506,7 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
   if (st != CR_OK) return st;
   const double* up = u_prev ? s->uprev : nullptr;
   const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
-  if (ns) {
+  if (ns && d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_ns_lambda, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->ulin,
                          s->params.mu, s->params.nu, s->lam);
@@ -1260,6 +1516,24 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL((k_face_assemble<2, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+  } else if (ns) {
+    // 3D Newton step: the local 12 x 12 matrices live in LDS (72 KiB per workgroup)
+    st = check_hip(hipFuncSetAttribute((const void*)k_elim_ns3, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)LDS_NS3), "Newton-step LDS size");
+    if (st == CR_OK)
+      st = check_hip(hipFuncSetAttribute((const void*)k_ns_lambda3, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)LDS_NS3), "Newton-step LDS size");
+    if (st != CR_OK) return st;
+    const unsigned g3 = nblocks(s->ne, BS_NS3);
+    if (steady)
+      hipLaunchKernelGGL(k_ns_lambda3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags,
+                         s->eface, s->ulin, s->params.mu, s->params.nu, s->lam);
+    hipLaunchKernelGGL(k_elim_ns3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack,
+                       s->RK, s->sK, s->err);
+    hipLaunchKernelGGL((k_face_assemble<3, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
+                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
+    hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
   } else if (d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
@@ -1370,6 +1644,14 @@ cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_pre
   return st;
 }
 
+cr_status enqueue_import_w(cr_system* s, const double* w0) {
+  const int64_t n = s->nf;
+  hipLaunchKernelGGL(k_import_w, dim3(nblocks(n * s->d, BS)), dim3(BS), 0, s->stream, n, s->d, s->fcanon, s->dsq, w0,
+                     s->y);
+  s->has_solution = true;
+  return check_hip(hipGetLastError(), "import W launch");
+}
+
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {
   const int d = s->d;
   const bool ns = s->params.problem == CR_NS_NEWTON;
@@ -1380,8 +1662,11 @@ cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {
     Uj = s->ujump;
   }
   const unsigned ge = nblocks(s->ne, BS);
-  if (ns)
+  if (ns && d == 2)
     hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+  else if (ns)
+    hipLaunchKernelGGL((k_recover<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
                        s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
   else if (d == 2)
     hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
@@ -1447,8 +1732,11 @@ cr_status run_recover_noalloc(cr_system* s, double* U, double* P, double* jump) 
     const cr_status st = scratch_address(s->device, &part);
     if (st != CR_OK) return st;
   }
-  if (ns)
+  if (ns && d == 2)
     hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
+                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+  else if (ns)
+    hipLaunchKernelGGL((k_recover<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
                        s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   else if (d == 2)
     hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
@@ -1457,8 +1745,11 @@ cr_status run_recover_noalloc(cr_system* s, double* U, double* P, double* jump) 
     hipLaunchKernelGGL((k_recover<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
                        s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   if (jump) {
-    if (ns)
+    if (ns && d == 2)
       hipLaunchKernelGGL((k_recover_mismatch<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
+                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+    else if (ns)
+      hipLaunchKernelGGL((k_recover_mismatch<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
                          s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
     else if (d == 2)
       hipLaunchKernelGGL((k_recover_mismatch<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,

@@ -2041,7 +2041,14 @@ cr_status run_minres(cr_system* s, KWs* w, const cr_solve_opts* o, cr_solve_info
   int total = 0, fp32_total = 0, outer = 0, reason = 0;
   double rel = -1.0, prev_t2 = -1.0;
   bool fell_back = false;
-  if (!o->warm_start || !s->has_solution) {
+  if (o->precond < CR_PC_DEFAULT || o->precond > CR_PC_JACOBI) {
+    set_error("MINRES takes CR_PC_DEFAULT or CR_PC_JACOBI (Jacobi scaling), not %d", o->precond);
+    return CR_E_INVAL;
+  }
+  if (o->w0) {
+    st = enqueue_import_w(s, o->w0);
+    if (st != CR_OK) return st;
+  } else if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, s->stream), "zero W");
     if (st != CR_OK) return st;
   }
@@ -2135,6 +2142,21 @@ cr_status run_minres(cr_system* s, KWs* w, const cr_solve_opts* o, cr_solve_info
 
 }  // namespace
 
+// Whether this solve adds the aggregate coarse correction (opts.precond).
+cr_status pick_coarse(cr_system* s, KWs* w, const cr_solve_opts* o, int op) {
+  if (o->precond < CR_PC_DEFAULT || o->precond > CR_PC_COARSE) {
+    set_error("unknown precond %d", o->precond);
+    return CR_E_INVAL;
+  }
+  w->use_coarse = op == 1 && o->precond != CR_PC_JACOBI && w->coarse_ok;
+  if (o->precond == CR_PC_COARSE && !w->use_coarse) {
+    set_error("CR_PC_COARSE: the coarse correction exists only for CG with the element form on a mesh with "
+              "aggregates (transient Stokes, at least 8192 elements in 2D, 4096 in 3D)");
+    return CR_E_INVAL;
+  }
+  return CR_OK;
+}
+
 cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   auto t_start = std::chrono::steady_clock::now();
   KWs* w = nullptr;
@@ -2150,14 +2172,18 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   int op = 0;
   st = resolve_op(s, o, op);
   if (st != CR_OK) return st;
-  w->use_coarse = op == 1 && o->coarse == 0 && w->coarse_ok;
+  st = pick_coarse(s, w, o, op);
+  if (st != CR_OK) return st;
   Ctl c;
   c.init(o);
   const int blk = o->check_every > 0 ? o->check_every : 32;
   const int npairs = std::max(1, (blk + 1) / 2);
   const int per = 2 * npairs;
   const bool graph = o->use_graph != 0;
-  if (!o->warm_start || !s->has_solution) {
+  if (o->w0) {
+    st = enqueue_import_w(s, o->w0);
+    if (st != CR_OK) return st;
+  } else if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, s->stream), "zero W");
     if (st != CR_OK) return st;
   }
@@ -2562,7 +2588,8 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
   en.o = *o;
   en.c.init(o);
   en.op = op;
-  w->use_coarse = op == 1 && o->coarse == 0 && w->coarse_ok;
+  st = pick_coarse(s, w, o, op);
+  if (st != CR_OK) return st;
   en.t0 = std::chrono::steady_clock::now();
   if (!o->warm_start || !s->has_solution) {
     st = check_hip(hipMemsetAsync(s->y, 0, sizeof(double) * s->nf * s->d, b->stream), "zero W");

@@ -244,3 +244,75 @@ class LinearisationField2D:
             pts = a + qi * e
             ut += wi * (self.u(pts) * t).sum(axis=1)
         return un[:, None] * nrm + ut[:, None] * t
+
+
+class LinearisationField3D:
+    """Seeded smooth divergence-free velocity on the unit cube, u = curl A with
+    a vector potential A = bubble^2 x (8 Fourier modes per component), scaled to
+    max|u| = 1, and its face means with exact normal fluxes: the flux of u
+    through a triangle is the circulation of A around its edges (Stokes'
+    theorem), each edge integral computed once per edge, so that the face
+    values are discretely divergence-free on every tetrahedron up to rounding.
+    The tangential part is the face mean of u by quadrature."""
+
+    def __init__(self, seed: int = 0, modes: int = 8):
+        rng = np.random.default_rng(seed)
+        X = sp.symbols("x0:3", real=True)
+        bubble = X[0] * (1 - X[0]) * X[1] * (1 - X[1]) * X[2] * (1 - X[2])
+        A = []
+        for _ in range(3):
+            s = sp.Integer(0)
+            for _ in range(modes):
+                a = sp.Float(rng.normal())
+                k = [int(rng.integers(1, 4)) for _ in range(3)]
+                th = sp.Float(rng.uniform(0.0, 2.0 * math.pi))
+                s = s + a * sp.sin(2 * sp.pi * (k[0] * X[0] + k[1] * X[1] + k[2] * X[2]) + th)
+            A.append(4096 * bubble ** 2 * s)
+        u = [sp.diff(A[2], X[1]) - sp.diff(A[1], X[2]),
+             sp.diff(A[0], X[2]) - sp.diff(A[2], X[0]),
+             sp.diff(A[1], X[0]) - sp.diff(A[0], X[1])]
+        self._A = sp.lambdify(X, A, modules="numpy")
+        self._u = sp.lambdify(X, u, modules="numpy")
+        g = np.linspace(0.0, 1.0, 41)
+        gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+        pts = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+        self.scale = 1.0
+        self.scale = 1.0 / float(np.sqrt((self.u(pts) ** 2).sum(axis=1)).max())
+
+    @staticmethod
+    def _vec(fn, pts):
+        v = fn(pts[:, 0], pts[:, 1], pts[:, 2])
+        return np.stack([np.broadcast_to(np.asarray(c, dtype=np.float64), pts[:, 0].shape) for c in v], axis=1)
+
+    def A(self, pts):
+        return self.scale * self._vec(self._A, pts)
+
+    def u(self, pts):
+        return self.scale * self._vec(self._u, pts)
+
+    def _edge(self, a, b):
+        """Integral of A . dl along the straight edge from a to b (5-point Gauss)."""
+        q, w = _gl01(5)
+        e = b - a
+        out = np.zeros(len(a))
+        for qi, wi in zip(q, w):
+            out += wi * (self.A(a + qi * e) * e).sum(axis=1)
+        return out
+
+    def face_means(self, coords, face_vertices):
+        """Mean of u over each triangle [nf, 3]; face_vertices [nf, 3] (any order)."""
+        fv = np.sort(np.asarray(face_vertices), axis=1)
+        p0, p1, p2 = coords[fv[:, 0]], coords[fv[:, 1]], coords[fv[:, 2]]
+        nv = 0.5 * np.cross(p1 - p0, p2 - p0)
+        area = np.sqrt((nv ** 2).sum(axis=1))
+        n = nv / area[:, None]
+        # circulation along p0 -> p1 -> p2 -> p0, every edge taken from its lower to
+        # its higher vertex id (the same number wherever the edge appears)
+        circ = self._edge(p0, p1) + self._edge(p1, p2) - self._edge(p0, p2)
+        un = circ / area
+        lam, wq = simplex_rule(2, 4)
+        um = np.zeros((len(fv), 3))
+        for l, wi in zip(lam, wq):
+            um += wi * self.u(l[0] * p0 + l[1] * p1 + l[2] * p2)
+        ut = um - (um * n).sum(axis=1)[:, None] * n
+        return un[:, None] * n + ut

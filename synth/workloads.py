@@ -11,6 +11,8 @@ Workloads (structured stand-ins for the paper's meshes, Section 4):
   cube64     3D 64^3 cubes x6 tetrahedra, mu = 100, nu = 1
   ns256      2D 256x256 cells x2, steady (mu = 0), nu = 0.01, Newton step
              about a seeded divergence-free velocity (8 Fourier modes)
+  ns_cube(n) 3D n^3 cubes x6, steady, nu = 0.01, Newton step about a seeded
+             divergence-free velocity (curl of an 8-mode vector potential)
 The right-hand side is the element mean of the force implied by a seeded
 smooth manufactured velocity (Manufactured).
 """
@@ -18,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .fields import LinearisationField2D, Manufactured, element_means
+from .fields import LinearisationField2D, LinearisationField3D, Manufactured, element_means
 from .mesh import cube_mesh, square_mesh
 
 
@@ -78,6 +80,20 @@ def ns_square(n, nu=0.01, seed=0, quad=3):
 
 def ns256():
     return ns_square(256)
+
+
+def ns_cube(n, nu=0.01, seed=0, quad=2):
+    """3D steady Navier-Stokes Newton step on n^3 cubes x 6 tetrahedra: manufactured
+    force, linearisation velocity = face means of a seeded divergence-free field
+    (LinearisationField3D, max|u| = 1, so nu = 1/Re)."""
+    coords, elems = cube_mesh(n)
+    man = Manufactured(3, seed=seed, mu=0.0, nu=nu)
+    fbar = element_means(coords, elems, man.f, n=quad)
+    lin = LinearisationField3D(seed=seed)
+    faces = interior_face_list(elems)
+    ubar = lin.face_means(coords, faces)
+    return dict(coords=coords, elems=elems, mu=0.0, nu=float(nu), fbar=fbar,
+                problem="ns", ulin=ubar, faces=faces)
 
 
 def serving_sessions(n_requests=2000, seed=1, n_min=32, n_max=512, rate=20.0, dt_range=(1e-3, 1e-1),

@@ -31,6 +31,16 @@ def relerr(a, b):
     b = np.asarray(b, dtype=np.float64).ravel()
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
+def assert_close(a, b, bar):
+    """Relative 2-norm and max-norm error of a against the oracle's b, both <= bar."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    e2 = relerr(a, b)
+    mb = np.abs(b).max()
+    emax = np.abs(a - b).max() / (mb if mb > 0 else 1.0)
+    assert e2 <= bar and emax <= bar, (e2, emax, bar)
+
+
 
 def coupled_rows(P, U, Pk, faces):
     """Rows (f, i) of R - A U - D^t P for the given faces, from the oracle's element
@@ -139,8 +149,8 @@ def test_c3_small_parity(gpu, precision, bar):
     torch.cuda.synchronize()
     P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
     Uo, Po = cr.solve_coupled(P)
-    assert relerr(U.cpu().numpy(), Uo) <= bar
-    assert relerr(Pk.cpu().numpy(), Po) <= bar
+    assert_close(U.cpu().numpy(), Uo, bar)
+    assert_close(Pk.cpu().numpy(), Po, bar)
     s.close()
 
 
@@ -158,8 +168,8 @@ def test_c4_ns_newton_step_parity(gpu, precision, bar, method):
     torch.cuda.synchronize()
     P = cr.make_problem(w["coords"], w["elems"], 0.0, w["nu"], w["fbar"], ulin=w["ulin"])
     Uo, Po = cr.solve_coupled(P)
-    assert relerr(U.cpu().numpy(), Uo) <= bar
-    assert relerr(Pk.cpu().numpy(), Po) <= bar
+    assert_close(U.cpu().numpy(), Uo, bar)
+    assert_close(Pk.cpu().numpy(), Po, bar)
     s.close()
 
 
@@ -250,8 +260,8 @@ def test_multistep_update_rhs_parity(gpu):
         torch.cuda.synchronize()
         P = cr.make_problem(coords, elems, mu, nu, fbar, u_prev=uo)
         uo, po = cr.solve_coupled(P)
-        assert relerr(U.cpu().numpy(), uo) <= 1e-10
-        assert relerr(Pk.cpu().numpy(), po) <= 1e-10
+        assert_close(U.cpu().numpy(), uo, 1e-10)
+        assert_close(Pk.cpu().numpy(), po, 1e-10)
     s.close()
 
 

@@ -24,6 +24,16 @@ def relerr(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
+def assert_close(a, b, bar):
+    """Relative 2-norm and max-norm error of a against the oracle's b, both <= bar."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    e2 = relerr(a, b)
+    mb = np.abs(b).max()
+    emax = np.abs(a - b).max() / (mb if mb > 0 else 1.0)
+    assert e2 <= bar and emax <= bar, (e2, emax, bar)
+
+
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
@@ -48,10 +58,18 @@ def make_case(name):
     if name == "ns10":
         w = wl.ns_square(10, nu=0.01, seed=2)
         return w["coords"], w["elems"], 0.0, w["nu"], w["fbar"], w["ulin"], "ns"
+    if name == "ns3d":
+        # 3D steady Newton step (E_K from the M1/M2 partition), 3^3 x 6 tetrahedra
+        w = wl.ns_cube(3, nu=0.05, seed=4)
+        return w["coords"], w["elems"], 0.0, w["nu"], w["fbar"], 5.0 * w["ulin"], "ns"
+    if name == "ns3d_t":
+        # 3D transient Newton step (mu = 20: E_K = 0)
+        w = wl.ns_cube(3, nu=0.05, seed=6)
+        return w["coords"], w["elems"], 20.0, w["nu"], w["fbar"], 5.0 * w["ulin"], "ns"
     raise KeyError(name)
 
 
-CASES = ["square16", "jitter12", "cube3", "steady10", "ns10"]
+CASES = ["square16", "jitter12", "cube3", "steady10", "ns10", "ns3d", "ns3d_t"]
 
 
 def oracle_problem(case, k0=0):
@@ -96,8 +114,8 @@ def test_recover_from_oracle_W(gpu, name):
     s.import_W(W_o)
     U, Pk, J = s.recover(jump=True)
     torch.cuda.synchronize()
-    assert relerr(U.cpu().numpy(), U_o) <= 1e-10
-    assert relerr(Pk.cpu().numpy(), P_o) <= 1e-10
+    assert_close(U.cpu().numpy(), U_o, 1e-10)
+    assert_close(Pk.cpu().numpy(), P_o, 1e-10)
     assert float(Pk[0]) == 0.0
     # copy mismatch equals the residual of W (zero up to rounding here)
     assert float(J.item()) <= 1e-9 * np.linalg.norm(H.S)
@@ -157,14 +175,14 @@ def test_pcg_solution_parity(gpu, name, precision, bar, operator):
     assert info["rel_residual"] <= 1e-13
     U, Pk = s.recover()
     torch.cuda.synchronize()
-    assert relerr(U.cpu().numpy(), U_o) <= bar
-    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    assert_close(U.cpu().numpy(), U_o, bar)
+    assert_close(Pk.cpu().numpy(), P_o, bar)
     s.close()
 
 
 @pytest.mark.parametrize("method", ["bicgstab", "bicgstab2"])
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
-@pytest.mark.parametrize("name", ["steady10", "ns10"])
+@pytest.mark.parametrize("name", ["steady10", "ns10", "ns3d", "ns3d_t"])
 def test_bicgstab_solution_parity(gpu, name, precision, bar, method):
     case = make_case(name)
     print(f"case {name} {precision} {method}", flush=True)
@@ -175,8 +193,8 @@ def test_bicgstab_solution_parity(gpu, name, precision, bar, method):
     assert info["rel_residual"] <= 1e-13
     U, Pk = s.recover()
     torch.cuda.synchronize()
-    assert relerr(U.cpu().numpy(), U_o) <= bar
-    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    assert_close(U.cpu().numpy(), U_o, bar)
+    assert_close(Pk.cpu().numpy(), P_o, bar)
     s.close()
 
 
@@ -220,8 +238,8 @@ def test_minres_solution_parity(gpu, name, precision, bar):
     assert info["rel_residual"] <= 1e-13
     U, Pk = s.recover()
     torch.cuda.synchronize()
-    assert relerr(U.cpu().numpy(), U_o) <= bar
-    assert relerr(Pk.cpu().numpy(), P_o) <= bar
+    assert_close(U.cpu().numpy(), U_o, bar)
+    assert_close(Pk.cpu().numpy(), P_o, bar)
     with pytest.raises(gpu.CRError):
         s.solve("minres", "fp64", tol=1e-10, operator="element")
     s.close()
@@ -263,8 +281,8 @@ def test_coarse_correction_parity(gpu, precision, bar):
         U, Pk = s.recover()
         torch.cuda.synchronize()
         print(f"{n}x{n}x2 {precision}: coarse {a['iters']} iterations", flush=True)
-        assert relerr(U.cpu().numpy(), U_o) <= bar
-        assert relerr(Pk.cpu().numpy(), P_o) <= bar
+        assert_close(U.cpu().numpy(), U_o, bar)
+        assert_close(Pk.cpu().numpy(), P_o, bar)
         Wa = s.export_W()
         b = s.solve("pcg", precision, tol=1e-13, coarse=False)
         print(f"{n}x{n}x2 {precision}: Jacobi only {b['iters']} iterations", flush=True)
@@ -351,7 +369,7 @@ def test_degenerate_meshes_and_data(gpu, method, precision, bar):
         assert info["status"] == 0
         assert float(Pk[k0]) == 0.0
         assert np.abs(U.cpu().numpy() - U_o).max() <= bar * max(np.abs(U_o).max(), np.abs(P_o).max())
-        assert relerr(Pk.cpu().numpy(), P_o) <= bar
+        assert_close(Pk.cpu().numpy(), P_o, bar)
         # zero data: the solution is zero, with no iteration
         s.eliminate(dev(np.zeros_like(fbar)))
         z = s.solve(method, precision, tol=1e-13)
@@ -373,6 +391,50 @@ def test_coupled_minres_baseline_parity(gpu, name):
     U, Pk, info = s.coupled_solve(tol=1e-13, maxit=500000)
     torch.cuda.synchronize()
     assert info["rel_residual"] <= 1e-13
-    assert relerr(U.cpu().numpy(), U_o) <= 1e-10
-    assert relerr(Pk.cpu().numpy(), P_o) <= 1e-10
+    assert_close(U.cpu().numpy(), U_o, 1e-10)
+    assert_close(Pk.cpu().numpy(), P_o, 1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("method,case", [("pcg", "jitter12"), ("minres", "square16"), ("pcg", "cube3")])
+def test_initial_guess_w0(gpu, method, case):
+    """cr_solve_opts.w0: the solution W handed back as the initial guess stops at
+    once with the same W; a perturbed W converges to the same W again."""
+    c = make_case(case)
+    s = gpu_system(gpu, c)
+    a = s.solve(method, "fp64", tol=1e-12)
+    W = s.export_W()
+    s.solve(method, "fp64", tol=1e-12)  # the resident W is now this solution again
+    b = s.solve(method, "fp64", tol=1e-12, w0=dev(W))
+    assert b["status"] == 0 and b["iters"] <= 2, b
+    assert relerr(s.export_W(), W) <= 1e-12
+    Wp = W * (1.0 + 0.1 * np.random.default_rng(5).normal(size=W.shape))
+    c2 = s.solve(method, "fp64", tol=1e-12, w0=dev(Wp))
+    assert c2["status"] == 0 and 0 < c2["iters"]
+    assert relerr(s.export_W(), W) <= 1e-9
+    # w0 = 0 is the cold start
+    d0 = s.solve(method, "fp64", tol=1e-12, w0=dev(np.zeros_like(W)))
+    assert d0["iters"] == a["iters"]
+    s.close()
+
+
+def test_precond_options(gpu):
+    """precond: "coarse" needs aggregates (refused on a small mesh, accepted on
+    64x64x2); "jacobi" and "default" reach the same W."""
+    c = make_case("jitter12")
+    s = gpu_system(gpu, c)
+    with pytest.raises(gpu.CRError, match="coarse correction exists only"):
+        s.solve("pcg", "fp64", tol=1e-12, precond="coarse")
+    with pytest.raises(gpu.CRError, match="MINRES takes"):
+        s.solve("minres", "fp64", tol=1e-12, precond="coarse")
+    s.close()
+    coords, elems = synth.square_mesh(64, jitter=0.2, seed=2)
+    fbar = np.random.default_rng(2).normal(size=(len(elems), 2))
+    s = gpu.System(coords, elems, 1000.0, 1.0)
+    s.eliminate(dev(fbar))
+    a = s.solve("pcg", "fp64", tol=1e-12, precond="coarse")
+    Wa = s.export_W()
+    b = s.solve("pcg", "fp64", tol=1e-12, precond="jacobi")
+    assert relerr(s.export_W(), Wa) <= 1e-9
+    assert a["iters"] < b["iters"]
     s.close()

@@ -333,12 +333,16 @@ def _cases():
     c3, e3 = synth.cube_mesh(2)
     f3 = np.random.default_rng(12).normal(size=(len(e3), 3))
     ns = wl.ns_square(8, nu=0.02, seed=3)
+    ns3 = wl.ns_cube(2, nu=0.05, seed=4)
     return {
         "stokes2d": cr.make_problem(coords, elems, 200.0, 1.0, f2, k0=5),
         "stokes3d": cr.make_problem(c3, e3, 40.0, 1.0, f3),
         "steady2d": cr.make_problem(coords, elems, 0.0, 1.0, f2),
         "ns2d": cr.make_problem(ns["coords"], ns["elems"], 0.0, ns["nu"], ns["fbar"], ulin=ns["ulin"]),
         "ns2d_transient": cr.make_problem(ns["coords"], ns["elems"], 30.0, ns["nu"], ns["fbar"], ulin=ns["ulin"]),
+        "ns3d": cr.make_problem(ns3["coords"], ns3["elems"], 0.0, ns3["nu"], ns3["fbar"], ulin=5.0 * ns3["ulin"]),
+        "ns3d_transient": cr.make_problem(ns3["coords"], ns3["elems"], 20.0, ns3["nu"], ns3["fbar"],
+                                          ulin=5.0 * ns3["ulin"]),
     }
 
 
@@ -600,6 +604,22 @@ def test_convection_skew_and_flux_sum():
     Ub = cr.local_face_values(m, ns["ulin"])
     assert np.abs(cr.divergence(P, ns["ulin"])).max() < 1e-15
     F = cr.fluxes(m, Ub) * (1 - np.eye(3))
+    assert np.abs(F.sum(axis=2) + (Ub * m.a).sum(axis=2)).max() < 1e-15
+    N = cr.convection(m, Ub, Ub)
+    bh = (N * Ub.reshape(m.ne, -1)).sum()
+    assert abs(bh) < 1e-14 * np.abs(N).sum() * np.abs(Ub).max()
+
+
+def test_convection_skew_and_flux_sum_3d():
+    """The same two identities in 3D, for the face means of a divergence-free
+    field whose normal parts come from edge circulations (discretely
+    divergence-free on every tetrahedron)."""
+    ns = wl.ns_cube(3, nu=0.02, seed=5)
+    P = cr.make_problem(ns["coords"], ns["elems"], 0.0, ns["nu"], ns["fbar"], ulin=ns["ulin"])
+    m = P.mesh
+    Ub = cr.local_face_values(m, ns["ulin"])
+    assert np.abs(cr.divergence(P, ns["ulin"])).max() < 1e-15 * max(1.0, np.abs(ns["ulin"]).max())
+    F = cr.fluxes(m, Ub) * (1 - np.eye(4))
     assert np.abs(F.sum(axis=2) + (Ub * m.a).sum(axis=2)).max() < 1e-15
     N = cr.convection(m, Ub, Ub)
     bh = (N * Ub.reshape(m.ne, -1)).sum()
