@@ -43,14 +43,17 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "hybridised solve time & SpMV HBM GB/s vs coupled solve; solves/s, p99 latency"
 
 WORKLOADS = {
+    # tol: the residual tolerance at which U and P match the FP64 oracle to 1e-9
+    # (2-norm and max-norm, measured against the stored oracle solution);
+    # config_tol: the residual tolerance the configuration states, timed beside it
     "cube64": dict(
-        dim=3, mu=100.0, nu=1.0, tol=1e-9, coupled_maxit=100000,
+        dim=3, mu=100.0, nu=1.0, tol=1e-13, config_tol=1e-9, coupled_maxit=40000,
         label="3D transient Stokes, unit cube 64^3 cubes x 6 Kuhn tetrahedra, nu=1, mu=1/dt=100, manufactured "
               "RHS; hybridised SPD system, CG with Jacobi scaling and aggregate coarse correction, G applied from "
               "element factors",
         bound="hbm"),
     "square512j": dict(
-        dim=2, mu=1000.0, nu=1.0, tol=1e-10, coupled_maxit=60000,
+        dim=2, mu=1000.0, nu=1.0, tol=1e-11, config_tol=1e-10, coupled_maxit=100000,
         label="2D transient Stokes, unit square 512x512 cells x2 triangles, jitter 0.2h (seed 0), nu=1, "
               "mu=1/dt=1000, manufactured RHS; hybridised SPD system, CG with Jacobi scaling and aggregate coarse "
               "correction, G applied from element factors",
@@ -286,13 +289,24 @@ def measure_transient(crh, torch, name, args, steps, warmup, precision, copy_gbp
     _, _, J = s.recover(jump=True)
     torch.cuda.synchronize()
 
+    # the configuration's stated residual tolerance: time and error
+    info_c = s.solve("pcg", precision, tol=cfg["config_tol"])
+    Uc_, Pc_ = s.recover()
+    at_config = {"tol": cfg["config_tol"], "time_to_tol_ms": round(info_c["t_solve_ms"], 3),
+                 "iters": info_c["iters"], "rel_residual": info_c["rel_residual"],
+                 "err_vs_oracle": {k: v for k, v in oracle_error(name, Uc_, Pc_).items()
+                                   if k in ("U_rel2", "U_max_rel", "P_rel2", "P_max_rel", "status")}}
+    log(f"{name}: at residual {cfg['config_tol']:g}: {info_c['t_solve_ms']:.1f} ms, {info_c['iters']} iterations, "
+        f"error {json.dumps(at_config['err_vs_oracle'])}")
+    del Uc_, Pc_
+
     # Jacobi only (no coarse correction): the like-for-like comparison with the
     # coupled solve, which has a diagonal preconditioner
-    info_j = s.solve("pcg", precision, tol=tol, coarse=False, maxit=200000)
+    info_j = s.solve("pcg", precision, tol=tol, precond="jacobi", maxit=200000, raise_on_error=False)
     log(f"{name}: Jacobi-only solve {info_j['t_solve_ms']:.1f} ms, {info_j['iters']} iterations")
     # the other Krylov precision
     other = "fp64" if precision == "fp32_ir" else "fp32_ir"
-    info_o = s.solve("pcg", other, tol=tol)
+    info_o = s.solve("pcg", other, tol=tol, maxit=200000, raise_on_error=False)
     log(f"{name}: {other} solve {info_o['t_solve_ms']:.1f} ms, {info_o['iters']} iterations")
 
     coupled = None
@@ -300,19 +314,33 @@ def measure_transient(crh, torch, name, args, steps, warmup, precision, copy_gbp
         Uc, Pc, ci = s.coupled_solve(tol=tol, maxit=cfg["coupled_maxit"], raise_on_error=False)
         torch.cuda.synchronize()
         diff = (torch.linalg.norm(Uc - U) / torch.linalg.norm(U)).item()
+        ce = oracle_error(name, Uc, Pc)
         coupled = {"method": "FP64 MINRES on eq. syslin, diagonal block preconditioner diag(A) + "
                              "diag(D diag(A)^-1 D^t)",
-                   "time_ms": round(ci["t_solve_ms"], 2), "iters": ci["iters"], "maxit": cfg["coupled_maxit"],
-                   "rel_residual": ci["rel_residual"], "converged": ci["status"] == 0,
+                   "tol": tol, "time_ms": round(ci["t_solve_ms"], 2), "iters": ci["iters"],
+                   "maxit": cfg["coupled_maxit"], "rel_residual": ci["rel_residual"], "converged": ci["status"] == 0,
                    "rel_diff_U_vs_hybrid": diff,
+                   "err_vs_oracle": {k: v for k, v in ce.items()
+                                     if k in ("U_rel2", "U_max_rel", "P_rel2", "P_max_rel", "status")},
                    "speedup_hybrid_jacobi_only": round(ci["t_solve_ms"] / info_j["t_solve_ms"], 2),
                    "speedup_hybrid_coarse": round(ci["t_solve_ms"] / solve_ms, 2)}
         log(f"{name}: coupled MINRES {ci['t_solve_ms']:.1f} ms, {ci['iters']} iterations, "
             f"residual {ci['rel_residual']:.2e}, converged={ci['status'] == 0}")
         del Uc, Pc
+        # the coupled solve at the configuration's residual tolerance as well
+        Uc, Pc, ci2 = s.coupled_solve(tol=cfg["config_tol"], maxit=cfg["coupled_maxit"], raise_on_error=False)
+        ce2 = oracle_error(name, Uc, Pc)
+        coupled["at_config_tol"] = {
+            "tol": cfg["config_tol"], "time_ms": round(ci2["t_solve_ms"], 2), "iters": ci2["iters"],
+            "rel_residual": ci2["rel_residual"], "converged": ci2["status"] == 0,
+            "err_vs_oracle": {k: v for k, v in ce2.items()
+                              if k in ("U_rel2", "U_max_rel", "P_rel2", "P_max_rel", "status")}}
+        log(f"{name}: coupled MINRES at {cfg['config_tol']:g}: {ci2['t_solve_ms']:.1f} ms, {ci2['iters']} iterations")
+        del Uc, Pc
 
     out = {
-        "workload": cfg["label"] + f", to rel residual {tol:g} "
+        "workload": cfg["label"] + f", to rel residual {tol:g} (the tolerance at which U and P match the FP64 "
+                   f"oracle to 1e-9; the stated {cfg['config_tol']:g} is timed in at_config_tol) "
                    f"({'FP32 iterations inside FP64 residual replacement' if precision == 'fp32_ir' else 'FP64'})",
         "elements": len(w["elems"]), "unknowns": s.n_int_faces * cfg["dim"], "tol": tol, "precision": precision,
         "solves_per_s": round(steps / wall, 4), "ms_per_step": round(1e3 * wall / steps, 3),
@@ -323,9 +351,10 @@ def measure_transient(crh, torch, name, args, steps, warmup, precision, copy_gbp
         "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "topology_host_s": round(t_topo, 3),
         "err_vs_oracle": err,
+        "at_config_tol": at_config,
         "roofline": roof,
         "jacobi_only": {"time_to_tol_ms": round(info_j["t_solve_ms"], 3), "iters": info_j["iters"],
-                        "rel_residual": info_j["rel_residual"]},
+                        "rel_residual": info_j["rel_residual"], "converged": info_j["status"] == 0},
         f"{other}_iterations": {"time_to_tol_ms": round(info_o["t_solve_ms"], 3), "iters": info_o["iters"],
                                 "fp32_iters": info_o["fp32_iters"], "fp64_fallback": info_o["fp64_fallback"],
                                 "rel_residual": info_o["rel_residual"]},
@@ -462,8 +491,9 @@ def main():
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "jacobi_only": head["jacobi_only"],
         "coupled_gpu": head["coupled_gpu"],
+        "at_config_tol": head["at_config_tol"],
         "headline_detail": {k: v for k, v in head.items()
-                            if k not in ("roofline", "err_vs_oracle", "coupled_gpu", "jacobi_only")},
+                            if k not in ("roofline", "err_vs_oracle", "coupled_gpu", "jacobi_only", "at_config_tol")},
         "second_workload": second,
         "ns_newton_256": ns,
         "serving": serving,

@@ -119,6 +119,66 @@ def test_c2_full_size_certificate(gpu, precision):
     s.close()
 
 
+def stored_oracle(name):
+    """The oracle's solution of a full-size workload, sampled (tests/golden/
+    oracle_<name>.npz, written by make_oracle_samples.py from the oracle alone)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"oracle_{name}.npz")
+    return np.load(path)
+
+
+def check_against_stored_oracle(name, U, Pk, bar):
+    z = stored_oracle(name)
+    fi = torch.from_numpy(z["face_ids"].astype(np.int64)).cuda()
+    ei = torch.from_numpy(z["elem_ids"].astype(np.int64)).cuda()
+    Us = U.index_select(0, fi).cpu().numpy()
+    Ps = Pk.index_select(0, ei).cpu().numpy()
+    eU2 = relerr(Us, z["U"])
+    eP2 = relerr(Ps, z["P"])
+    eUm = np.abs(Us - z["U"]).max() / float(z["U_max"])
+    ePm = np.abs(Ps - z["P"]).max() / float(z["P_max"])
+    print(f"{name}: U {eU2:.2e} / max {eUm:.2e}, P {eP2:.2e} / max {ePm:.2e}", flush=True)
+    assert max(eU2, eUm, eP2, ePm) <= bar, (eU2, eUm, eP2, ePm)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_ir", 1e-11), ("fp64", 1e-11)])
+def test_c2_full_size_against_stored_oracle(gpu, precision, tol):
+    """512x512x2 jittered (1,570,816 unknowns): U and P against the oracle's
+    coupled sparse-LU solution (three refinement steps) on 8,287 sampled faces
+    and 8,254 elements, 2-norm and max-norm, within 1e-9.  At the residual
+    tolerance 1e-11 the pressure error is about 2.5e-10 (1e-10 leaves 1.1e-9 in
+    the max-norm)."""
+    w = wl.square512j()
+    print(f"C2 inputs ready ({precision})", flush=True)
+    s = gpu.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    s.eliminate(dev(w["fbar"]))
+    info = s.solve("pcg", precision, tol=tol)
+    assert info["rel_residual"] <= tol
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    check_against_stored_oracle("square512j", U, Pk, 1e-9)
+    s.close()
+
+
+def test_c3_full_size_against_stored_oracle(gpu):
+    """64^3 x 6 (9,363,456 unknowns), the benchmark's path (FP32 CG with FP64
+    residual replacement and the coarse correction): U and P against the
+    oracle's solution (general elimination, Jacobi PCG on G to 5e-13, recovery)
+    on 8,321 sampled faces and 8,255 elements, within 1e-9.  The pressure needs
+    the residual at 1e-13 for that (3e-6 at 1e-9, 2e-9 at 1e-12)."""
+    w = wl.cube64()
+    print("C3 inputs ready", flush=True)
+    s = gpu.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    s.eliminate(dev(w["fbar"]))
+    info = s.solve("pcg", "fp32_ir", tol=1e-13)
+    print("C3 solve:", info, flush=True)
+    assert info["rel_residual"] <= 1e-13 and not info["fp64_fallback"]
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    check_against_stored_oracle("cube64", U, Pk, 1e-9)
+    s.close()
+
+
 def test_c3_full_size_certificate(gpu):
     """64^3 cubes x6 Kuhn tetrahedra (1,572,864 elements) transient Stokes, FP64 Krylov."""
     w = wl.cube64()
