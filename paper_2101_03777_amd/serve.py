@@ -57,6 +57,8 @@ class Session:
         self.req_t0 = None
         self.bytes = 0
         self.admitted_at = None
+        self.t_build = None   # build (prepare on a worker, then upload and elimination) started
+        self.t_enter = None   # the current request joined the batch
 
     @property
     def estimate(self):
@@ -100,6 +102,7 @@ class Server:
         owner = {}
         building = []
         latencies, waits, records = [], [], []
+        budget_blocks = slot_blocks = 0  # passes in which the queue head waited for memory / for a slot
         in_use = 0
         n_active = 0
         peak_active = 0
@@ -119,13 +122,18 @@ class Server:
             # admission by memory budget and batch capacity, in arrival order:
             # the host part is prepared on a worker thread, the system joins the
             # batch when it is ready
-            while queue and n_active + len(building) < self.max_active:
+            while queue:
+                if n_active + len(building) >= self.max_active:
+                    slot_blocks += 1
+                    break
                 s = queue[0]
                 if s.estimate > self.budget:
                     raise ValueError(f"session {s.sid} needs {s.estimate} bytes, above the budget {self.budget}")
                 if in_use + s.estimate > self.budget:
+                    budget_blocks += 1
                     break
                 queue.popleft()
+                s.t_build = time.perf_counter() - t0
                 building.append((s, self.pool.submit(self._prepare, s)))
                 in_use += s.estimate
             waiting = []
@@ -136,6 +144,7 @@ class Server:
                 self._admit(s, fut.result())
                 in_use += s.bytes - s.estimate
                 s.admitted_at = time.perf_counter() - t0
+                s.t_enter = s.admitted_at
                 owner[s.sys.h.value] = s
                 waits.append(s.admitted_at - s.arrival)
                 n_active += 1
@@ -152,27 +161,38 @@ class Server:
                     continue
                 break
             self.batch.advance(self.iters)
+            t_pop = time.perf_counter() - t0
             while True:
                 item = self.batch.pop()
                 if item is None:
                     break
                 sysobj, info = item
                 s = owner[sysobj.h.value]
+                t_rec = time.perf_counter() - t0
                 U, P = s.sys.recover()
                 self.torch.cuda.current_stream().synchronize()
                 t_done = time.perf_counter() - t0
                 latencies.append(t_done - s.req_t0)
+                first = s.done_steps == 0
                 records.append(dict(sid=s.sid, step=s.done_steps, latency=t_done - s.req_t0, iters=info["iters"],
                                     status=info["status"], rel_residual=info["rel_residual"],
-                                    fp64_fallback=info["fp64_fallback"], n_elements=len(s.elems)))
+                                    fp64_fallback=info["fp64_fallback"], n_elements=len(s.elems),
+                                    # where the latency went: waiting for memory or a slot (first
+                                    # step), building the system (first step) or the right-hand
+                                    # side update (later steps), iterating in the batch until the
+                                    # advance that finished it, and the recovery
+                                    wait=(s.t_build - s.req_t0) if first else 0.0,
+                                    build=(s.t_enter - s.t_build) if first else (s.t_enter - s.req_t0),
+                                    iterate=t_pop - s.t_enter, recover=t_done - t_rec))
                 if on_result is not None:
                     on_result(s, s.done_steps, U, P, info)
                 s.done_steps += 1
                 done += 1
                 if s.done_steps < s.steps:
+                    s.req_t0 = t_done
                     s.sys.update_rhs(s.fdev, U)
                     self.batch.add(s.sys, **self.opts, warm_start=True)
-                    s.req_t0 = t_done
+                    s.t_enter = time.perf_counter() - t0
                 else:
                     del owner[s.sys.h.value]
                     s.sys.close()
@@ -181,10 +201,18 @@ class Server:
                     n_active -= 1
         wall = time.perf_counter() - t0
         lat = np.array(latencies) if latencies else np.zeros(1)
+
+        def pct(key, q):
+            v = [r[key] for r in records]
+            return round(1e3 * float(np.percentile(v, q)), 2) if v else 0.0
+
+        breakdown = {key: {"p50_ms": pct(key, 50), "p99_ms": pct(key, 99)}
+                     for key in ("wait", "build", "iterate", "recover")}
         return dict(requests=done, sessions=len(arr), wall_s=wall, solves_per_s=done / wall if wall > 0 else 0.0,
                     p50_ms=1e3 * float(np.percentile(lat, 50)), p99_ms=1e3 * float(np.percentile(lat, 99)),
                     mean_ms=1e3 * float(lat.mean()), max_queue_wait_ms=1e3 * float(max(waits) if waits else 0.0),
                     peak_active=peak_active, peak_bytes=int(peak_bytes), budget_bytes=self.budget,
+                    budget_blocks=budget_blocks, slot_blocks=slot_blocks, latency_breakdown=breakdown,
                     failed=sum(1 for r in records if r["status"] != 0),
                     fp64_fallbacks=sum(1 for r in records if r["fp64_fallback"]), records=records)
 

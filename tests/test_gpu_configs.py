@@ -413,3 +413,97 @@ def test_prepared_assembly_equals_direct(gpu):
         assert out[0][2] == 0 and out[1][2] == 0
         assert out[0][1] == out[1][1]
         assert np.array_equal(out[0][0], out[1][0])
+
+
+def test_batch_fp64_fallback_equals_solo(gpu):
+    """A system whose FP32 iterations stall switches to FP64 iterations inside
+    the batch (its replacements are serviced with its own kernels and it is
+    regrouped into the FP64 grid), next to FP32 systems: every system's W and
+    iteration count equal its solo solve bitwise, the forced system reports the
+    fallback, and its U and P match the oracle.  The stall is forced from the
+    host: inner_tol = 0.9 asks for a replacement after every 10% drop of the
+    recursive residual, so the second replacement fails to halve the FP64
+    residual, which is the stall rule."""
+    systems, opts = [], []
+    for n, mu, inner in [(10, 300.0, 0.0), (14, 1000.0, 0.9), (20, 50.0, 0.0), (64, 1000.0, 0.0)]:
+        co, el = synth.square_mesh(n, jitter=0.2, seed=40 + n)
+        fb = np.random.default_rng(40 + n).normal(size=(len(el), 2))
+        s = gpu.System(co, el, mu, 1.0)
+        s.eliminate(dev(fb))
+        systems.append((s, co, el, mu, fb))
+        opts.append(dict(method="pcg", precision="fp32_ir", tol=1e-12, inner_tol=inner))
+    solo = []
+    for (s, *_), o in zip(systems, opts):
+        info = s.solve(**o)
+        solo.append((s.export_W(), info["iters"], info["fp64_fallback"]))
+    assert [f for _, _, f in solo] == [False, True, False, False]
+    b = gpu.Batch(8)
+    for (s, *_), o in zip(systems, opts):
+        b.add(s, **o)
+    got = {}
+    while len(got) < len(systems):
+        b.advance(16)
+        while (r := b.pop()) is not None:
+            got[r[0].h.value] = (r[0].export_W(), r[1]["iters"], r[1]["status"], r[1]["fp64_fallback"])
+    for (s, *_), (W, it, fb) in zip(systems, solo):
+        Wb, itb, st, fbb = got[s.h.value]
+        assert st == 0 and itb == it and fbb == fb
+        assert np.array_equal(W, Wb)
+    b.close()
+    s, co, el, mu, fb = systems[1]
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    Uo, Po = cr.solve_coupled(cr.make_problem(co, el, mu, 1.0, fb))
+    assert_close(U.cpu().numpy(), Uo, 1e-9)
+    assert_close(Pk.cpu().numpy(), Po, 1e-9)
+    for s, *_ in systems:
+        s.close()
+
+
+def test_serving_budget_limits_admission(gpu):
+    """With room for about three of the sessions' systems in the device-memory
+    budget and many batch slots, the budget (not the slot count) holds
+    sessions back, and every request still completes."""
+    from paper_2101_03777_amd.serve import Server, Session, BYTES_PER_ELEMENT_2D
+    ss = wl.serving_sessions(60, seed=5, n_min=24, n_max=40, rate=1000.0, max_steps=4)
+    sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"], d["arrival"])
+                for i, d in enumerate(ss)]
+    big = max(len(d["elems"]) for d in ss) * BYTES_PER_ELEMENT_2D
+    budget = int(3.5 * big)
+    srv = Server(hbm_budget=budget, max_active=64, precision="fp32_ir", tol=1e-9)
+    st = srv.run(sessions)
+    srv.close()
+    print({k: v for k, v in st.items() if k != "records"}, flush=True)
+    assert st["requests"] == sum(d["steps"] for d in ss) and st["failed"] == 0
+    assert st["budget_blocks"] > 0 and st["slot_blocks"] == 0
+    assert st["peak_active"] < 64 and st["peak_active"] <= budget // (min(len(d["elems"]) for d in ss) *
+                                                                      BYTES_PER_ELEMENT_2D)
+
+
+def test_serving_against_oracle(gpu):
+    """Served time steps against the oracle's own chain of coupled solves
+    (backward Euler, u_prev = the oracle's previous U): U and P within 1e-9 at
+    every step, in 2-norm and max-norm."""
+    from paper_2101_03777_amd.serve import Server, Session
+    ss = wl.serving_sessions(9, seed=7, n_min=8, n_max=16, rate=1000.0, max_steps=3)
+    sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"], d["arrival"])
+                for i, d in enumerate(ss)]
+    served = {}
+
+    def keep(sess, step, U, P, info):
+        served[(sess.sid, step)] = (U.cpu().numpy(), P.cpu().numpy(), info["status"])
+
+    srv = Server(hbm_budget=1 << 30, max_active=8, precision="fp32_ir", tol=1e-12)
+    st = srv.run(sessions, on_result=keep)
+    srv.close()
+    assert st["failed"] == 0
+    for i, d in enumerate(ss):
+        u_prev = None
+        for step in range(d["steps"]):
+            P = cr.make_problem(d["coords"], d["elems"], 1.0 / d["dt"], d["nu"], d["fbar"], u_prev=u_prev)
+            Uo, Po = cr.solve_coupled(P)
+            Us, Ps, status = served[(i, step)]
+            assert status == 0
+            assert_close(Us, Uo, 1e-9)
+            assert_close(Ps, Po, 1e-9)
+            u_prev = Uo
