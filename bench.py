@@ -195,28 +195,66 @@ def cpu_oracle_baseline(ne_target, n_sample=10):
 
 
 def run_serving(args):
-    """Continuous-batching serving run: transient-Stokes time-step requests of
-    sessions arriving as a Poisson process (N x N x 2 meshes, N log-uniform in
-    [32, 512], dt uniform in [1e-3, 1e-1], 1 to 20 steps per session), admitted by
-    a device-memory budget, solved to 1e-9 in one shared batch."""
+    """Continuous-batching serving of transient-Stokes time-step requests:
+    sessions arrive as a Poisson process (N x N x 2 meshes, N log-uniform in
+    [32, 512], dt uniform in [1e-3, 1e-1], 1 to 20 steps per session), are
+    admitted by a device-memory budget and solved to 1e-9 in one shared batch.
+    First the saturated throughput (all sessions of the first requests offered
+    at once), then the offered load swept at 0.5, 0.8 and 1.0 of it on those
+    requests, then the full run at 0.5 of it (the full list holds more large
+    meshes than its first requests; at 0.8 its queue grows).  The arrival times of one seeded
+    session list are rescaled for each offered load."""
+    import numpy as np
     import synth.workloads as wl
     from paper_2101_03777_amd.serve import Server, Session
     t0 = time.perf_counter()
-    ss = wl.serving_sessions(args.serve_requests, seed=1, rate=args.serve_rate)
+    ss = wl.serving_sessions(args.serve_requests, seed=1, rate=1.0)
     log(f"serving inputs: {len(ss)} sessions, {sum(d['steps'] for d in ss)} requests, "
         f"{time.perf_counter() - t0:.1f} s")
-    sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"], d["arrival"])
-                for i, d in enumerate(ss)]
-    srv = Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_active=128, precision=args.serve_precision,
-                 tol=1e-9)
-    st = srv.run(sessions)
-    srv.close()
-    recs = st.pop("records")
-    st.update(precision=args.serve_precision, tol=1e-9, arrival_rate_sessions_per_s=args.serve_rate,
-              total_iterations=int(sum(r["iters"] for r in recs)),
-              workload="transient Stokes time steps, N x N x 2 meshes, N log-uniform in [32, 512], dt uniform in "
-                       "[1e-3, 1e-1] (mu = 1/dt), 1-20 steps per session, Poisson session arrivals, seed 1")
-    return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()}
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def prefix(n_req):
+        out, tot = [], 0
+        for d in ss:
+            if tot >= n_req:
+                break
+            out.append(d)
+            tot += d["steps"]
+        return out
+
+    def serve(data, req_rate):
+        # arrivals of the unit-rate session list scaled to req_rate requests/s
+        # (inf: every session offered at time 0)
+        steps = np.mean([d["steps"] for d in data])
+        scale = 0.0 if not np.isfinite(req_rate) else steps / req_rate
+        sessions = [Session(i, d["coords"], d["elems"], d["dt"], d["nu"], d["fbar"], d["steps"],
+                            d["arrival"] * scale) for i, d in enumerate(data)]
+        srv = Server(hbm_budget=budget, max_active=128, precision=args.serve_precision, tol=1e-9)
+        st = srv.run(sessions)
+        srv.close()
+        recs = st.pop("records")
+        st["offered_requests_per_s"] = None if not np.isfinite(req_rate) else req_rate
+        st["total_iterations"] = int(sum(r["iters"] for r in recs))
+        return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()}
+
+    out = {"workload": "transient Stokes time steps, N x N x 2 meshes, N log-uniform in [32, 512], dt uniform in "
+                       "[1e-3, 1e-1] (mu = 1/dt), 1-20 steps per session, Poisson session arrivals, seed 1",
+           "precision": args.serve_precision, "tol": 1e-9, "budget_bytes": budget}
+    small = prefix(args.serve_sweep_requests)
+    sat = serve(small, float("inf"))
+    out["saturated"] = sat
+    cap = sat["solves_per_s"]
+    log(f"serving saturated: {cap:.1f} solves/s ({sat['requests']} requests offered at once)")
+    for frac in (0.5, 0.8, 1.0):
+        r = serve(small, frac * cap)
+        out[f"load_{frac:g}"] = r
+        log(f"serving at {frac:g} of saturation: {r['solves_per_s']:.1f} solves/s, p50 {r['p50_ms']:.0f} ms, "
+            f"p99 {r['p99_ms']:.0f} ms")
+    full = serve(ss, 0.5 * cap)
+    out["run_all_at_0.5"] = full
+    log(f"serving {full['requests']} requests at 0.5 of saturation: {full['solves_per_s']:.1f} solves/s, "
+        f"p50 {full['p50_ms']:.0f} ms, p99 {full['p99_ms']:.0f} ms")
+    return out
 
 
 def measure_transient(crh, torch, name, args, steps, warmup, precision, copy_gbps, headline):
@@ -399,9 +437,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="time-step requests of the serving run (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=2.5,
-                    help="session arrivals per second (Poisson); 2.5 offers about 26 requests/s, below saturation")
-    ap.add_argument("--serve-budget-gb", type=float, default=8.0, help="device-memory budget for admission")
+    ap.add_argument("--serve-sweep-requests", type=int, default=500,
+                    help="requests of the saturation measurement and of each swept load")
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0, help="device-memory budget for admission")
     ap.add_argument("--serve-precision", default="fp32_ir", choices=["fp32_ir", "fp64"])
     ap.add_argument("--no-other", action="store_true",
                     help="skip the second transient workload and the Navier-Stokes step")
@@ -458,8 +496,6 @@ def main():
     serving = None
     if args.serve_requests > 0:
         serving = run_serving(args)
-        log(f"serving: {serving['requests']} requests, {serving['solves_per_s']:.1f} solves/s, "
-            f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms")
 
     cpu = None
     if not args.no_cpu:
