@@ -292,11 +292,12 @@ cr_status cr_topology(const cr_mesh_desc* mesh, const cr_params* params, int64_t
 /* Baseline: a Krylov solve of the original coupled system of Section 3.1
  * (eq. syslin) [A D^t; D 0][U; P] = [R; 0] on the same GPU, FP64, without the
  * hybridisation, preconditioned by the positive diagonal
- * diag|A| (+) diag(D diag|A|^{-1} D^t).  Stokes (symmetric): MINRES.  Newton
- * step (non-symmetric): BiCGStab(2) (opts->method CR_BICGSTAB2, the default
- * for it) or BiCGStab.  Stops on the coupled residual
- * ||[R;0] - M [U;P]|| <= tol ||R||; opts->tol, maxit, check_every are used,
- * the other fields ignored.  U, P as in cr_recover (device, caller-owned).
+ * diag|A| (+) diag(D diag|A|^{-1} D^t).  Stokes (symmetric): MINRES on the
+ * preconditioned system.  Newton step (non-symmetric A, Jacobian of the
+ * convection form included): BiCGStab on the system scaled symmetrically by
+ * the square root of that diagonal, in passes that restart from the true
+ * residual.  Stops on the coupled residual ||[R;0] - M [U;P]|| <= tol ||R||;
+ * opts->tol, maxit, max_outer, check_every are used, the other fields ignored.  U, P as in cr_recover (device, caller-owned).
  * Its workspace (about 12 vectors of the coupled size) is allocated on first
  * use.  Synchronises.  Errors: CR_E_NOCONV (iteration limit; best iterate
  * written), CR_E_BREAKDOWN, CR_E_NONFINITE, CR_E_INVAL (before cr_eliminate). */

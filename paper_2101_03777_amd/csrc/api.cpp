@@ -672,10 +672,6 @@ cr_status cr_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* 
     set_error("cr_coupled_solve needs the element data of cr_eliminate");
     return CR_E_INVAL;
   }
-  if (s->params.problem != CR_STOKES) {
-    set_error("the coupled MINRES baseline is for the Stokes problem");
-    return CR_E_INVAL;
-  }
   return run_coupled_solve(s, o, info, U, P);
 }
 

@@ -1,8 +1,11 @@
-// Baseline: FP64 MINRES on the original coupled system (Section 3.1, eq. syslin)
+// Baseline: FP64 Krylov solve of the original coupled system (Section 3.1, eq. syslin)
 //     [A  D^t] [U]   [R]
 //     [D   0 ] [P] = [0]
-// on the same GPU, for the Stokes problem (A = S (x) I_d), preconditioned by
-// the positive diagonal diag(A) (+) diag(D diag(A)^{-1} D^t).  This is the
+// on the same GPU.  Stokes (A = S (x) I_d, symmetric): MINRES preconditioned by
+// the positive diagonal diag(A) (+) diag(D diag(A)^{-1} D^t).  Newton step (A =
+// the Jacobian of the convection form added to S (x) I_d, non-symmetric):
+// BiCGStab on the system scaled symmetrically by the square root of the
+// positive diagonal diag|A| (+) diag(D diag|A|^{-1} D^t).  This is the
 // comparison the hybrid method is measured against; it is not on the hybrid
 // path.
 //
@@ -24,6 +27,7 @@
 #include <cmath>
 #include <vector>
 
+#include "convection.h"
 #include "geometry.h"
 #include "internal.h"
 #include "rowkern.h"
@@ -452,6 +456,463 @@ __global__ void k_mr_scatter(int64_t nf, int64_t ne, const double* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Newton step: A in d x d blocks per face pair (block-ELL with the column table
+// of G: slot 0 the diagonal block, slots 1..d the other faces of the owner
+// element, d+1..2d those of the other element), from the element matrices
+// A_K of the Jacobian (formed once per solve in a scratch array).
+// ---------------------------------------------------------------------------
+template <int D, class M>
+__device__ __forceinline__ void ns_amat_elem(int64_t ne, int64_t k, const double* __restrict__ ecoord,
+                                             const uint32_t* __restrict__ eflags, const int32_t* __restrict__ eface,
+                                             const double* __restrict__ ulin, double mu, double nu, const M& A,
+                                             double* __restrict__ amat) {
+  constexpr int NU = NsPack<D>::NU;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  double Ub[D + 1][D], Nuu[D + 1][D];
+  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  for (int a = 0; a < NU; ++a)
+    for (int b = 0; b < NU; ++b) amat[(int64_t)(a * NU + b) * ne + k] = A(a, b);
+}
+
+__global__ void __launch_bounds__(128) k_ns_amat2(int64_t ne, const double* __restrict__ ecoord,
+                                                  const uint32_t* __restrict__ eflags,
+                                                  const int32_t* __restrict__ eface, const double* __restrict__ ulin,
+                                                  double mu, double nu, double* __restrict__ amat) {
+  const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (k >= ne) return;
+  double A[6][6];
+  ns_amat_elem<2>(ne, k, ecoord, eflags, eface, ulin, mu, nu, RegMat<6>{A}, amat);
+}
+
+constexpr int BS_AM3 = 64;
+__global__ void __launch_bounds__(BS_AM3) k_ns_amat3(int64_t ne, const double* __restrict__ ecoord,
+                                                     const uint32_t* __restrict__ eflags,
+                                                     const int32_t* __restrict__ eface,
+                                                     const double* __restrict__ ulin, double mu, double nu,
+                                                     double* __restrict__ amat) {
+  extern __shared__ double lds_am[];
+  const int64_t k = (int64_t)blockIdx.x * BS_AM3 + threadIdx.x;
+  if (k >= ne) return;
+  ns_amat_elem<3>(ne, k, ecoord, eflags, eface, ulin, mu, nu, LdsMat<12>{lds_am + threadIdx.x, BS_AM3}, amat);
+}
+
+// face rows of the Newton-step coupled matrix: blocks of A, owner face vector,
+// assembled R, and the velocity part of the preconditioner 1/|A_(f,i),(f,i)|
+template <int D>
+__global__ void __launch_bounds__(128) k_coupled_faces_ns(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
+                                                          const uint32_t* __restrict__ eflags,
+                                                          const int32_t* __restrict__ fel,
+                                                          const int32_t* __restrict__ floc,
+                                                          const double* __restrict__ RK,
+                                                          const double* __restrict__ amat,
+                                                          double* __restrict__ Ablk, double* __restrict__ an,
+                                                          double* __restrict__ bvec, double* __restrict__ dinv) {
+  constexpr int N = D + 1, DD = D * D, NU = N * D;
+  const int64_t f = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t e2[2] = {fel[f], fel[nf + f]};
+  const int lc = floc[f];
+  const int jj[2] = {lc & 0xff, (lc >> 8) & 0xff};
+  double diag[D][D], R[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    R[i] = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < D; ++ip) diag[i][ip] = 0.0;
+  }
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int64_t K = e2[side];
+    const int j = jj[side];
+    const uint32_t fl = eflags[K];
+    auto a = [&](int r, int c) { return amat[(int64_t)(r * NU + c) * ne + K]; };
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      R[i] += RK[(int64_t)(j * D + i) * ne + K];
+#pragma unroll
+      for (int ip = 0; ip < D; ++ip) diag[i][ip] += a(j * D + i, j * D + ip);
+    }
+    int slot = 1 + side * D;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      if (l == j) continue;
+      const bool in = interior(fl, l);
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int ip = 0; ip < D; ++ip)
+          Ablk[(int64_t)(slot * DD + i * D + ip) * nf + f] = in ? a(j * D + i, l * D + ip) : 0.0;
+      ++slot;
+    }
+    if (side == 0) {
+      Geo<D> g;
+      load_geometry<D>(ecoord, ne, K, g);
+#pragma unroll
+      for (int i = 0; i < D; ++i) an[f * D + i] = g.a[j][i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+#pragma unroll
+    for (int ip = 0; ip < D; ++ip) Ablk[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
+    bvec[f * D + i] = R[i];
+    dinv[f * D + i] = 1.0 / fabs(diag[i][i]);
+  }
+}
+
+// element rows (D U): coefficients and the pressure part of the
+// preconditioner 1 / sum_{j,i} a_{K,j,i}^2 / |A_(f_j,i),(f_j,i)|
+template <int D>
+__global__ void __launch_bounds__(128) k_coupled_elems_ns(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
+                                                          const uint32_t* __restrict__ eflags,
+                                                          const int32_t* __restrict__ eface,
+                                                          const double* __restrict__ Ablk, double* __restrict__ ea,
+                                                          double* __restrict__ bvec, double* __restrict__ dinv) {
+  constexpr int N = D + 1;
+  const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (k >= ne) return;
+  Geo<D> g;
+  load_geometry<D>(ecoord, ne, k, g);
+  const uint32_t fl = eflags[k];
+  const bool k0 = fl & F_K0;
+  double sch = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool in = interior(fl, j) && !k0;
+    const int64_t f = interior(fl, j) ? eface[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      ea[(int64_t)(j * D + i) * ne + k] = in ? g.a[j][i] : 0.0;
+      if (in) sch += g.a[j][i] * g.a[j][i] / fabs(Ablk[(int64_t)(i * D + i) * nf + f]);
+    }
+  }
+  bvec[nf * D + k] = 0.0;
+  dinv[nf * D + k] = k0 ? 0.0 : 1.0 / sch;
+}
+
+// one velocity row of y = M v (Newton step): block row of A, then D^t P
+template <int D, class In, class Pin>
+__device__ __forceinline__ void coupled_face_row_ns(const double* __restrict__ Ablk, const int32_t* __restrict__ cols,
+                                                    const double* __restrict__ an, const int32_t* __restrict__ fel,
+                                                    int64_t nf, int64_t f, const In& in, const Pin& pin,
+                                                    double (&y)[D]) {
+  constexpr int DD = D * D;
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[i] = 0.0;
+#pragma unroll
+  for (int s = 0; s <= 2 * D; ++s) {
+    const int64_t c = s == 0 ? f : cols[(int64_t)(s - 1) * nf + f];
+    Vec<double, D> xc = in(c);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) y[i] += Ablk[(int64_t)(s * DD + i * D + j) * nf + f] * xc.v[j];
+  }
+  const double dp = pin(fel[f]) - pin(fel[nf + f]);
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[i] -= an[f * D + i] * dp;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab on the scaled coupled system K~ x~ = b~, K~ = Q K Q, b~ = Q b,
+// x = Q x~, Q = diag(sqrt(dinv)); the iterate is kept unscaled (x += Q (alpha
+// p + omega s)).  Three kernels per iteration, parity-slotted scalars, p and v
+// double-buffered by parity (the product kernels gather the new direction
+// p = r + beta (p_old - omega v_old) and s = r - alpha v at neighbouring rows
+// on the fly).  Passes restart from the true residual b - K x until it meets
+// the tolerance.
+// ---------------------------------------------------------------------------
+struct BState {
+  double rho[2], alpha[2], omega[2];
+  int it[2];
+  int done;    // 1 pass converged, 3 limit, 4 breakdown, 5 non-finite
+  int iters;
+  double thr, tres2, bnorm2;
+  // host parameters
+  double tol2;
+  int maxit;
+  int pad;
+};
+
+template <int D>
+struct QU {  // Q v at face c
+  const double* __restrict__ v;
+  const double* __restrict__ q;
+  __device__ Vec<double, D> operator()(int64_t c) const {
+    Vec<double, D> a = ldv<double, D>(v, c), w = ldv<double, D>(q, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.v[i] *= w.v[i];
+    return a;
+  }
+};
+struct QP {
+  const double* __restrict__ v;
+  const double* __restrict__ q;
+  __device__ double operator()(int64_t k) const { return v[k] * q[k]; }
+};
+// Q (r + beta (p - omega v)) and Q (r - alpha v) at face c / element k
+template <int D>
+struct QPNewU {
+  const double *r, *p, *v, *q;
+  double beta, omega;
+  __device__ Vec<double, D> operator()(int64_t c) const {
+    Vec<double, D> a = ldv<double, D>(r, c), pp = ldv<double, D>(p, c), vv = ldv<double, D>(v, c),
+                   w = ldv<double, D>(q, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.v[i] = w.v[i] * (a.v[i] + beta * (pp.v[i] - omega * vv.v[i]));
+    return a;
+  }
+};
+struct QPNewP {
+  const double *r, *p, *v, *q;
+  double beta, omega;
+  __device__ double operator()(int64_t k) const { return q[k] * (r[k] + beta * (p[k] - omega * v[k])); }
+};
+template <int D>
+struct QSNewU {
+  const double *r, *v, *q;
+  double alpha;
+  __device__ Vec<double, D> operator()(int64_t c) const {
+    Vec<double, D> a = ldv<double, D>(r, c), vv = ldv<double, D>(v, c), w = ldv<double, D>(q, c);
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.v[i] = w.v[i] * (a.v[i] - alpha * vv.v[i]);
+    return a;
+  }
+};
+struct QSNewP {
+  const double *r, *v, *q;
+  double alpha;
+  __device__ double operator()(int64_t k) const { return q[k] * (r[k] - alpha * v[k]); }
+};
+
+struct NsMat {
+  const double* Ablk;
+  const int32_t* cols;
+  const double* an;
+  const int32_t* fel;
+  const double* ea;
+  const int32_t* eface;
+};
+
+// pass start: res = b - K x (unscaled, true residual), r = rhat = Q res, p = v = 0.
+// Partials: [0] rhat.r, [1] r.r, [2] res.res, [3] b.b
+template <int D>
+__global__ void __launch_bounds__(NT) k_cb_init(CDims C, NsMat M, const double* __restrict__ b,
+                                                const double* __restrict__ q, const double* __restrict__ x,
+                                                double* __restrict__ r, double* __restrict__ rhat,
+                                                double* __restrict__ p0, double* __restrict__ p1,
+                                                double* __restrict__ v0, double* __restrict__ v1,
+                                                double* __restrict__ pa, BState* __restrict__ st) {
+  int64_t lo, hi;
+  int lb;
+  const bool fb = face_block(C, lo, hi, lb);
+  const int64_t off = C.nf * D;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto put = [&](int64_t i, double res, double bi) {
+    const double ri = q[i] * res;
+    r[i] = ri;
+    rhat[i] = ri;
+    p0[i] = p1[i] = v0[i] = v1[i] = 0.0;
+    acc[0] += ri * ri;
+    acc[1] += ri * ri;
+    acc[2] += res * res;
+    acc[3] += bi * bi;
+  };
+  if (fb) {
+    for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+      double y[D];
+      coupled_face_row_ns<D>(M.Ablk, M.cols, M.an, M.fel, C.nf, f, PlainU<D>{x}, PlainP{x + off}, y);
+#pragma unroll
+      for (int i = 0; i < D; ++i) put(f * D + i, b[f * D + i] - y[i], b[f * D + i]);
+    }
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += NT)
+      put(off + k, -coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x}), 0.0);
+  }
+  block_sum<4>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pa[(int64_t)lb * NPART + m] = acc[m];
+  if (lead()) {
+    st->it[1] = 0;
+    st->iters = 0;
+    st->done = 0;
+    st->rho[1] = 1.0;
+    st->alpha[1] = 1.0;
+    st->omega[1] = 1.0;
+  }
+}
+
+// CB1 (parity par): rho = rhat.r; stopping; beta; v = K~ p with p = r + beta (p_old - omega v_old)
+// formed at every gathered row; p stored; partial rhat.v
+template <int D>
+__global__ void __launch_bounds__(NT) k_cb_1(CDims C, NsMat M, const double* __restrict__ q,
+                                             const double* __restrict__ r, const double* __restrict__ rhat,
+                                             const double* __restrict__ pold, const double* __restrict__ vold,
+                                             double* __restrict__ pnew, double* __restrict__ vnew,
+                                             const double* __restrict__ pa, double* __restrict__ pb,
+                                             BState* __restrict__ st, int par) {
+  const int seen = st->done;
+  const int it = st->it[par ^ 1];
+  const bool first = it == 0;
+  const double rho_old = st->rho[par ^ 1], alpha_old = st->alpha[par ^ 1], omega_old = st->omega[par ^ 1];
+  double s[4];
+  if (reduce_partials_stop<4>(pa, C.nbf + C.nbe, 0, s, seen)) return;
+  const double rho = s[0], rr = s[1];
+  int done = 0;
+  if (first) {
+    // pass start: the partials also hold the true residual and ||b||
+    const double thr = 0.01 * st->tol2 * s[3] * (s[2] > 0.0 ? rr / s[2] : 1.0);
+    if (lead()) {
+      st->tres2 = s[2];
+      st->bnorm2 = s[3];
+      st->thr = thr;
+    }
+    if (s[2] <= st->tol2 * s[3]) done = 1;
+  } else if (rr <= st->thr) {
+    done = 1;
+  }
+  if (!done) {
+    if (!isfinite(rho) || !isfinite(rr)) done = 5;
+    else if (it >= st->maxit) done = 3;
+    else if (!(fabs(rho) > 1e-300) || (!first && !(fabs(omega_old) > 0.0))) done = 4;
+  }
+  if (lead()) {
+    st->iters = it;
+    if (done) st->done = done;
+  }
+  if (done) return;
+  const double beta = first ? 0.0 : (rho / rho_old) * (alpha_old / omega_old);
+  if (lead()) {
+    st->rho[par] = rho;
+    st->it[par] = it + 1;
+  }
+  int64_t lo, hi;
+  int lb;
+  const bool fb = face_block(C, lo, hi, lb);
+  const int64_t off = C.nf * D;
+  const QPNewU<D> inu{r, pold, vold, q, beta, omega_old};
+  const QPNewP inp{r + off, pold + off, vold + off, q + off, beta, omega_old};
+  double acc[1] = {0.0};
+  if (fb) {
+    for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+      double y[D];
+      coupled_face_row_ns<D>(M.Ablk, M.cols, M.an, M.fel, C.nf, f, inu, inp, y);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int64_t e = f * D + i;
+        pnew[e] = r[e] + beta * (pold[e] - omega_old * vold[e]);
+        const double vv = q[e] * y[i];
+        vnew[e] = vv;
+        acc[0] += rhat[e] * vv;
+      }
+    }
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += NT) {
+      const int64_t e = off + k;
+      pnew[e] = r[e] + beta * (pold[e] - omega_old * vold[e]);
+      const double vv = q[e] * coupled_elem_row<D>(M.ea, M.eface, C.ne, k, inu);
+      vnew[e] = vv;
+      acc[0] += rhat[e] * vv;
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) pb[(int64_t)lb * NPART] = acc[0];
+}
+
+// CB2: alpha = rho / rhat.v; t = K~ s with s = r - alpha v formed at gathered rows; s stored;
+// partials t.s, t.t
+template <int D>
+__global__ void __launch_bounds__(NT) k_cb_2(CDims C, NsMat M, const double* __restrict__ q,
+                                             const double* __restrict__ r, const double* __restrict__ v,
+                                             double* __restrict__ sv, double* __restrict__ t,
+                                             const double* __restrict__ pb, double* __restrict__ pc,
+                                             BState* __restrict__ st, int par) {
+  const int seen = st->done;
+  const double rho = st->rho[par];
+  double sm[1];
+  if (reduce_partials_stop<1>(pb, C.nbf + C.nbe, 0, sm, seen)) return;
+  const double rv = sm[0];
+  if (!(fabs(rv) > 1e-300) || !isfinite(rv)) {
+    if (lead()) st->done = isfinite(rv) ? 4 : 5;
+    return;
+  }
+  const double alpha = rho / rv;
+  if (lead()) st->alpha[par] = alpha;
+  int64_t lo, hi;
+  int lb;
+  const bool fb = face_block(C, lo, hi, lb);
+  const int64_t off = C.nf * D;
+  const QSNewU<D> inu{r, v, q, alpha};
+  const QSNewP inp{r + off, v + off, q + off, alpha};
+  double acc[2] = {0.0, 0.0};
+  if (fb) {
+    for (int64_t f = lo + threadIdx.x; f < hi; f += NT) {
+      double y[D];
+      coupled_face_row_ns<D>(M.Ablk, M.cols, M.an, M.fel, C.nf, f, inu, inp, y);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int64_t e = f * D + i;
+        const double si = r[e] - alpha * v[e], ti = q[e] * y[i];
+        sv[e] = si;
+        t[e] = ti;
+        acc[0] += ti * si;
+        acc[1] += ti * ti;
+      }
+    }
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += NT) {
+      const int64_t e = off + k;
+      const double si = r[e] - alpha * v[e], ti = q[e] * coupled_elem_row<D>(M.ea, M.eface, C.ne, k, inu);
+      sv[e] = si;
+      t[e] = ti;
+      acc[0] += ti * si;
+      acc[1] += ti * ti;
+    }
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    pc[(int64_t)lb * NPART] = acc[0];
+    pc[(int64_t)lb * NPART + 1] = acc[1];
+  }
+}
+
+// CB3: omega = t.s / t.t; x += Q (alpha p + omega s); r = s - omega t; partials rhat.r, r.r
+__global__ void __launch_bounds__(NT) k_cb_3(CDims C, int64_t n, const double* __restrict__ q,
+                                             const double* __restrict__ p, const double* __restrict__ sv,
+                                             const double* __restrict__ t, const double* __restrict__ rhat,
+                                             double* __restrict__ r, double* __restrict__ x,
+                                             const double* __restrict__ pc, double* __restrict__ pa,
+                                             BState* __restrict__ st, int par) {
+  const int seen = st->done;
+  const double alpha = st->alpha[par];
+  double sm[2];
+  if (reduce_partials_stop<2>(pc, C.nbf + C.nbe, 0, sm, seen)) return;
+  const double omega = sm[1] > 0.0 ? sm[0] / sm[1] : 0.0;
+  if (lead()) st->omega[par] = omega;
+  const int nb = C.nbf + C.nbe;
+  const int lb = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)lb * per, hi = min(n, lo + per);
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+    x[i] += q[i] * (alpha * p[i] + omega * sv[i]);
+    const double ri = sv[i] - omega * t[i];
+    r[i] = ri;
+    acc[0] += rhat[i] * ri;
+    acc[1] += ri * ri;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    pa[(int64_t)lb * NPART] = acc[0];
+    pa[(int64_t)lb * NPART + 1] = acc[1];
+  }
+}
+
 struct CWs {
   CDims dims{};
   int64_t n = 0;
@@ -471,6 +932,14 @@ struct CWs {
   CState* hst = nullptr;
   hipEvent_t ev[2] = {};
   bool assembled = false;
+  // Newton step (BiCGStab): A blocks, element matrices, Q = sqrt(dinv), the
+  // second direction buffer and the state; the other vectors reuse R and W
+  double* Ablk = nullptr;
+  double* amat = nullptr;
+  double* q = nullptr;
+  double* v1 = nullptr;
+  BState* bst = nullptr;
+  BState* hbst = nullptr;
 };
 
 CDims make_dims(int64_t nf, int64_t ne) {
@@ -530,6 +999,7 @@ cr_status ensure_cws(cr_system* s, CWs*& w) {
 
 void free_cws(CWs* w) {
   if (!w) return;
+  if (w->hbst) (void)hipHostFree(w->hbst);
   for (auto& e : w->ev)
     if (e) (void)hipEventDestroy(e);
   if (w->hst) (void)hipHostFree(w->hst);
@@ -653,9 +1123,151 @@ cr_status coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* inf
   return CR_E_NOCONV;
 }
 
+__global__ void k_sqrt_vec(int64_t n, const double* __restrict__ a, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = sqrt(a[i]);
+}
+
+// the Newton-step coupled matrix, its right-hand side and the scaling, on the device
+template <int D>
+cr_status coupled_assemble_ns(cr_system* s, CWs*& w) {
+  cr_status st = ensure_cws(s, w);
+  if (st != CR_OK) return st;
+  constexpr int NU = NsPack<D>::NU;
+  if (!w->Ablk) {
+    w->Ablk = (double*)dev_alloc(s, sizeof(double) * (2 * D + 1) * D * D * s->nf);
+    w->amat = (double*)dev_alloc(s, sizeof(double) * NU * NU * s->ne);
+    w->q = (double*)dev_alloc(s, sizeof(double) * w->n);
+    w->v1 = (double*)dev_alloc(s, sizeof(double) * w->n);
+    w->bst = (BState*)dev_alloc(s, sizeof(BState));
+    if (!w->Ablk || !w->amat || !w->q || !w->v1 || !w->bst) return CR_E_NOMEM;
+    st = check_hip(hipHostMalloc((void**)&w->hbst, 2 * sizeof(BState), hipHostMallocDefault), "pinned");
+    if (st != CR_OK) return st;
+  }
+  if constexpr (D == 2) {
+    hipLaunchKernelGGL(k_ns_amat2, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->ne, s->ecoord,
+                       s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, w->amat);
+  } else {
+    const size_t lds = sizeof(double) * 144 * BS_AM3;
+    st = check_hip(hipFuncSetAttribute((const void*)k_ns_amat3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                   "coupled Newton-step LDS size");
+    if (st != CR_OK) return st;
+    hipLaunchKernelGGL(k_ns_amat3, dim3((unsigned)((s->ne + BS_AM3 - 1) / BS_AM3)), dim3(BS_AM3), lds, s->stream,
+                       s->ne, s->ecoord, s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, w->amat);
+  }
+  hipLaunchKernelGGL(k_coupled_faces_ns<D>, dim3((unsigned)((s->nf + 127) / 128)), dim3(128), 0, s->stream, s->nf,
+                     s->ne, s->ecoord, s->eflags, s->fel, s->floc, s->RK, w->amat, w->Ablk, w->an, w->b, w->dinv);
+  hipLaunchKernelGGL(k_coupled_elems_ns<D>, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->nf,
+                     s->ne, s->ecoord, s->eflags, s->eface, w->Ablk, w->ea, w->b, w->dinv);
+  hipLaunchKernelGGL(k_sqrt_vec, dim3((unsigned)((w->n + 255) / 256)), dim3(256), 0, s->stream, w->n, w->dinv, w->q);
+  return check_hip(hipGetLastError(), "coupled Newton-step assembly");
+}
+
+template <int D>
+cr_status coupled_bicgstab(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
+  auto t0 = std::chrono::steady_clock::now();
+  CWs* w = nullptr;
+  cr_status st = coupled_assemble_ns<D>(s, w);
+  if (st != CR_OK) return st;
+  const CDims C = w->dims;
+  const NsMat M{w->Ablk, s->cols, w->an, s->fel, w->ea, s->eface};
+  double* r = w->R[0];
+  double* rhat = w->R[1];
+  double* sv = w->R[2];
+  double* t = w->W[2];
+  double* pv[2] = {w->W[0], w->W[1]};
+  double* vv[2] = {w->v, w->v1};
+  st = check_hip(hipMemsetAsync(w->x, 0, sizeof(double) * w->n, s->stream), "coupled x");
+  const double tol = o->tol > 0 ? o->tol : 1e-10;
+  const int maxit = o->maxit > 0 ? o->maxit : 200000;
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 50;
+  const int blk = std::max(2, ((o->check_every > 0 ? o->check_every : 48) + 1) / 2 * 2);
+  int total = 0, outer = 0, reason = 0, stuck = 0;
+  double rel = -1.0;
+  const dim3 grid(C.nbf + C.nbe), tb(NT);
+  while (st == CR_OK) {
+    const bool last = outer >= max_outer || total >= maxit;
+    BState* h = &w->hbst[1];
+    h->tol2 = tol * tol;
+    h->maxit = last ? 0 : maxit - total;
+    const size_t off = offsetof(BState, tol2);
+    st = check_hip(hipMemcpyAsync((char*)w->bst + off, (char*)h + off, sizeof(BState) - off, hipMemcpyHostToDevice,
+                                  s->stream), "coupled params");
+    if (st != CR_OK) break;
+    hipLaunchKernelGGL(k_cb_init<D>, grid, tb, 0, s->stream, C, M, w->b, w->q, w->x, r, rhat, pv[0], pv[1], vv[0],
+                       vv[1], w->pa, w->bst);
+    ++outer;
+    int k = 0;
+    const int max_iter_pass = (last ? 0 : maxit - total) + 2;
+    BState ks{};
+    for (;;) {
+      for (int j = 0; j < blk; ++j, ++k) {
+        const int par = k & 1;
+        hipLaunchKernelGGL(k_cb_1<D>, grid, tb, 0, s->stream, C, M, w->q, r, rhat, pv[par ^ 1], vv[par ^ 1], pv[par],
+                           vv[par], w->pa, w->pb, w->bst, par);
+        hipLaunchKernelGGL(k_cb_2<D>, grid, tb, 0, s->stream, C, M, w->q, r, vv[par], sv, t, w->pb, w->pc, w->bst,
+                           par);
+        hipLaunchKernelGGL(k_cb_3, grid, tb, 0, s->stream, C, w->n, w->q, pv[par], sv, t, rhat, r, w->x, w->pc,
+                           w->pa, w->bst, par);
+      }
+      st = check_hip(hipGetLastError(), "coupled launch");
+      if (st == CR_OK)
+        st = check_hip(hipMemcpyAsync(&w->hbst[0], w->bst, sizeof(BState), hipMemcpyDeviceToHost, s->stream),
+                       "coupled state copy");
+      if (st == CR_OK) st = check_hip(hipStreamSynchronize(s->stream), "coupled poll");
+      if (st != CR_OK) break;
+      ks = w->hbst[0];
+      if (ks.done || k >= max_iter_pass) break;
+    }
+    if (st != CR_OK) break;
+    total += ks.iters;
+    rel = ks.bnorm2 > 0 ? std::sqrt(ks.tres2 / ks.bnorm2) : std::sqrt(ks.tres2);
+    if (ks.done == 1 && ks.iters == 0) {
+      reason = 1;  // the true residual at the start of this pass meets the tolerance
+      break;
+    }
+    if (ks.done == 5) {
+      reason = 5;
+      break;
+    }
+    if (ks.iters == 0 && ks.done == 4 && ++stuck >= 3) {
+      reason = 4;
+      break;
+    }
+    if (last || (ks.done == 3)) {
+      reason = 3;
+      if (!last) continue;  // one more pass evaluates the true residual of the final iterate
+      break;
+    }
+  }
+  if (st == CR_OK) {
+    hipLaunchKernelGGL(k_mr_scatter<D>, dim3((unsigned)((s->nf + s->ne + 255) / 256)), dim3(256), 0, s->stream, s->nf,
+                       s->ne, w->x, s->fcanon, s->ecaller, U, P);
+    st = check_hip(hipStreamSynchronize(s->stream), "coupled scatter");
+  }
+  if (st != CR_OK) return st;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->iters = total;
+    info->outer_iters = outer;
+    info->rel_residual = rel;
+    info->t_solve_ms = ms;
+    info->reason = reason;
+  }
+  if (reason == 1) return CR_OK;
+  if (reason == 4 || reason == 5) {
+    set_error("coupled BiCGStab breakdown after %d iterations (relative residual %.3e)", total, rel);
+    return reason == 4 ? CR_E_BREAKDOWN : CR_E_NONFINITE;
+  }
+  set_error("coupled BiCGStab: relative residual %.3e after %d iterations", rel, total);
+  return CR_E_NOCONV;
+}
+
 }  // namespace
 
 cr_status run_coupled_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info, double* U, double* P) {
+  if (s->params.problem == CR_NS_NEWTON)
+    return s->d == 2 ? coupled_bicgstab<2>(s, o, info, U, P) : coupled_bicgstab<3>(s, o, info, U, P);
   return s->d == 2 ? coupled_solve<2>(s, o, info, U, P) : coupled_solve<3>(s, o, info, U, P);
 }
 

@@ -24,7 +24,12 @@ the whole U and P, and the solve record.  The samples are 8192 seeded random
 faces and elements plus every face of elements 0..63 and those elements (the
 pinned element K0 = 0 sits in the corner, next to the boundary).
 
-Usage: python tests/golden/make_oracle_samples.py square512j|cube64
+  ns256       2D steady Navier-Stokes Newton step, 256 x 256 cells x 2, nu = 0.01,
+              seeded divergence-free linearisation velocity: the coupled system
+              (A with the Jacobian of the convection form) by sparse LU with three
+              refinement steps.
+
+Usage: python tests/golden/make_oracle_samples.py square512j|cube64|ns256
 """
 from __future__ import annotations
 
@@ -118,5 +123,19 @@ def cube64():
     store("cube64", P.mesh, U, Pk, rec)
 
 
+def ns256():
+    import synth.workloads as wl
+    from oracle import cr
+    w = wl.ns256()
+    t0 = time.perf_counter()
+    P = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"], ulin=w["ulin"])
+    U, Pk = cr.solve_coupled(P, refine=3)
+    t1 = time.perf_counter()
+    res, div = cr.coupled_residual(P, U, Pk)
+    rec = {"workload": "ns256", "method": "coupled sparse LU (SuperLU, COLAMD), 3 refinement steps",
+           "seconds": round(t1 - t0, 1), "coupled_rel_residual": res, "max_div_rel": div, "cpu": cpu_model()}
+    store("ns256", P.mesh, U, Pk, rec)
+
+
 if __name__ == "__main__":
-    {"square512j": square512j, "cube64": cube64}[sys.argv[1]]()
+    {"square512j": square512j, "cube64": cube64, "ns256": ns256}[sys.argv[1]]()

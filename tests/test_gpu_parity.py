@@ -396,6 +396,27 @@ def test_coupled_minres_baseline_parity(gpu, name):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ns10", "ns3d", "ns3d_t"])
+def test_coupled_newton_baseline_parity(gpu, name):
+    """The GPU coupled-system baseline of the Newton step (BiCGStab on the
+    scaled coupled system, Jacobian blocks of A) reaches the oracle's coupled
+    solution."""
+    case = make_case(name)
+    print(f"case {name} coupled Newton step", flush=True)
+    P = oracle_problem(case)
+    U_o, P_o = cr.solve_coupled(P)
+    s = gpu_system(gpu, case)
+    # FP64 BiCGStab on the coupled system levels off near 5e-13 here, so the
+    # tolerance is 1e-11 and the bar on the solution 1e-9
+    U, Pk, info = s.coupled_solve(tol=1e-11, maxit=200000)
+    torch.cuda.synchronize()
+    print(info, flush=True)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-11
+    assert_close(U.cpu().numpy(), U_o, 1e-9)
+    assert_close(Pk.cpu().numpy(), P_o, 1e-9)
+    s.close()
+
+
 @pytest.mark.parametrize("method,case", [("pcg", "jitter12"), ("minres", "square16"), ("pcg", "cube3")])
 def test_initial_guess_w0(gpu, method, case):
     """cr_solve_opts.w0: the solution W handed back as the initial guess stops at
