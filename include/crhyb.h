@@ -116,6 +116,11 @@ typedef struct {
   int32_t k0;
   int32_t problem;
   int32_t renumber;
+  /* mu = 0 only: E_K = -lambda_K I on the elements of M1 (Section 3.2 item 7)
+   * with lambda_K = lambda_scale * ||A_K||_inf over the interior rows; the
+   * paper asks for lambda above every eigenvalue modulus of A_K, which the
+   * infinity norm bounds, so lambda_scale must exceed 1.  <= 0: 2. */
+  double lambda_scale;
 } cr_params;
 
 /* Step a0: face topology, renumbering and upload of the mesh.
@@ -123,7 +128,7 @@ typedef struct {
  * reverse Cuthill-McKee face order (or natural), element order, and for mu = 0
  * the element partition M1/M2 of Section 3.2 item 7 (greedy maximal independent
  * set in caller order).  Host work plus host-to-device copies on hip_stream.
- * Errors: CR_E_INVAL (dim not 2/3, nu <= 0, mu < 0, k0 out of range),
+ * Errors: CR_E_INVAL (dim not 2/3, nu <= 0, mu < 0, k0 out of range, 0 < lambda_scale <= 1),
  * CR_E_MESH (see above), CR_E_NOMEM, CR_E_DEVICE.  *out is NULL on error. */
 cr_status cr_assemble(const cr_mesh_desc* mesh, const cr_params* params,
                       const cr_allocator* alloc, void* hip_stream, cr_system** out);

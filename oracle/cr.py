@@ -296,6 +296,7 @@ class Problem:
     R: np.ndarray          # [ne, d1*d]
     k0: int = 0
     ulin: np.ndarray = None
+    lam_scale: float = 2.0    # lambda_K = lam_scale * ||A_K||_inf on M1 (mu = 0), see element_E
 
     @property
     def d(self):
@@ -316,7 +317,7 @@ class Problem:
         return self._l2g
 
 
-def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad_rule=None):
+def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad_rule=None, lam_scale=2.0):
     """Element data of eq. syslin: A_K, D_K, R_K (Section 3.1).
 
     Stokes: A_K = S_K on each diagonal component block.  Navier-Stokes Newton
@@ -337,7 +338,7 @@ def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad
         A = A + convection_jacobian(m, Ub)
         R = R + convection(m, Ub, Ub)
     return Problem(mesh=m, mu=float(mu), nu=float(nu), A=A, D=element_D(m), R=R, k0=int(k0),
-                   ulin=None if ulin is None else np.asarray(ulin))
+                   ulin=None if ulin is None else np.asarray(ulin), lam_scale=float(lam_scale))
 
 
 def restrict(P: Problem, k):
@@ -435,8 +436,8 @@ def element_E(P: Problem):
     """Diagonal E_K of eq. prope, as [ne, d1*d] (Section 3.2, items 6 and 7).
 
     mu > 0: E_K = 0.  mu = 0: K in M1 gets E_K = -lambda_K Id
-    with lambda_K = 2 ||A_K||_inf (interior rows), which exceeds the modulus of
-    every eigenvalue of A_K; K in M2 gets +lambda_L on each face shared with an
+    with lambda_K = c ||A_K||_inf (interior rows; c = P.lam_scale > 1, 2 by
+    default), which exceeds the modulus of every eigenvalue of A_K; K in M2 gets +lambda_L on each face shared with an
     M1 element L and 0 elsewhere, so that E_K + E_L = 0 on every face.  (A
     per-element lambda is a reading: the paper names one lambda larger than the
     eigenvalues of A_K.)
@@ -451,7 +452,7 @@ def element_E(P: Problem):
     lam = np.zeros(m.ne)
     for k in np.nonzero(in1)[0]:
         idx = np.nonzero(mask[k])[0]
-        lam[k] = 2.0 * np.abs(P.A[k][np.ix_(idx, idx)]).sum(axis=1).max()
+        lam[k] = P.lam_scale * np.abs(P.A[k][np.ix_(idx, idx)]).sum(axis=1).max()
         E[k, idx] = -lam[k]
     for k in np.nonzero(~in1)[0]:
         for j in range(m.d + 1):

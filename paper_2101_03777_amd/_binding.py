@@ -49,7 +49,7 @@ class MeshDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("mu", C.c_double), ("nu", C.c_double), ("k0", C.c_int32), ("problem", C.c_int32),
-                ("renumber", C.c_int32)]
+                ("renumber", C.c_int32), ("lambda_scale", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -151,10 +151,10 @@ def _mesh(coords, elems):
     return m, (coords, elems)
 
 
-def _params(mu, nu, k0, problem, renumber):
+def _params(mu, nu, k0, problem, renumber, lambda_scale=0.0):
     prob = {"stokes": CR_STOKES, "ns": CR_NS_NEWTON}[problem] if isinstance(problem, str) else int(problem)
     ren = {"rcm": CR_RCM, "natural": CR_NATURAL}[renumber] if isinstance(renumber, str) else int(renumber)
-    return Params(float(mu), float(nu), int(k0), prob, ren)
+    return Params(float(mu), float(nu), int(k0), prob, ren, float(lambda_scale))
 
 
 def topology(coords, elems, mu=1.0, nu=1.0, k0=0, problem="stokes", renumber="rcm"):
@@ -285,12 +285,12 @@ class Prepared:
     so it can be built on a worker thread while the device is busy.  Pass it to
     System(prepared=...), which consumes it."""
 
-    def __init__(self, coords, elems, mu, nu, k0=0, problem="stokes", renumber="rcm"):
+    def __init__(self, coords, elems, mu, nu, k0=0, problem="stokes", renumber="rcm", lambda_scale=0.0):
         self.lib = load()
         self.dim = int(np.asarray(coords).shape[1])
         self.n_elements = int(np.asarray(elems).shape[0])
         m, keep = _mesh(coords, elems)
-        p = _params(mu, nu, k0, problem, renumber)
+        p = _params(mu, nu, k0, problem, renumber, lambda_scale)
         h = C.c_void_p()
         _check(self.lib.cr_prepare(C.byref(m), C.byref(p), C.byref(h)))
         self.h = h
@@ -311,7 +311,7 @@ class System:
     """One hybridised Crouzeix-Raviart system resident on the current GPU."""
 
     def __init__(self, coords=None, elems=None, mu=None, nu=None, k0=0, problem="stokes", renumber="rcm",
-                 stream=None, allocator="torch", prepared=None):
+                 stream=None, allocator="torch", prepared=None, lambda_scale=0.0):
         import torch
         self._torch = torch
         self.lib = load()
@@ -332,7 +332,7 @@ class System:
             _check(self.lib.cr_assemble_prepared(prepared.take(), al, C.c_void_p(handle), C.byref(h)))
         else:
             m, keep = _mesh(coords, elems)
-            p = _params(mu, nu, k0, problem, renumber)
+            p = _params(mu, nu, k0, problem, renumber, lambda_scale)
             _check(self.lib.cr_assemble(C.byref(m), C.byref(p), al, C.c_void_p(handle), C.byref(h)))
         self.h = h
         nf, ng, nc = C.c_int64(), C.c_int64(), C.c_int64()

@@ -126,6 +126,11 @@ cr_status check_params(const cr_mesh_desc* mesh, const cr_params* p) {
     set_error("need nu > 0 and mu >= 0 (got mu=%g nu=%g)", p->mu, p->nu);
     return CR_E_INVAL;
   }
+  if (p->lambda_scale > 0.0 && !(p->lambda_scale > 1.0)) {
+    set_error("lambda_scale %g: lambda_K must exceed ||A_K||_inf (scale > 1, or <= 0 for the default 2)",
+              p->lambda_scale);
+    return CR_E_INVAL;
+  }
   if (p->problem != CR_STOKES && p->problem != CR_NS_NEWTON) {
     set_error("unknown problem kind %d", p->problem);
     return CR_E_INVAL;

@@ -353,12 +353,12 @@ __device__ bool gj_inverse_inplace(const M& A) {
   return ok;
 }
 
-// lambda_K = 2 ||A_K||_inf over the interior rows/columns, for K in M1 (Section 3.2 item 7)
+// lambda_K = lscale ||A_K||_inf over the interior rows/columns, for K in M1 (Section 3.2 item 7)
 template <int D, class M>
 __device__ __forceinline__ void ns_lambda_elem(int64_t ne, int64_t k, const double* __restrict__ ecoord,
                                                uint32_t fl, const int32_t* __restrict__ eface,
-                                               const double* __restrict__ ulin, double mu, double nu, const M& A,
-                                               double* __restrict__ lam) {
+                                               const double* __restrict__ ulin, double mu, double nu, double lscale,
+                                               const M& A, double* __restrict__ lam) {
   constexpr int NU = NsPack<D>::NU;
   Geo<D> g;
   load_geometry<D>(ecoord, ne, k, g);
@@ -373,14 +373,14 @@ __device__ __forceinline__ void ns_lambda_elem(int64_t ne, int64_t k, const doub
     for (int c = 0; c < NU; ++c) s += interior(fl, c / D) ? fabs(A(r, c)) : 0.0;
     mx = interior(fl, r / D) ? fmax(mx, s) : mx;
   }
-  lam[k] = 2.0 * mx;
+  lam[k] = lscale * mx;
 }
 
 __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __restrict__ ecoord,
                                                   const uint32_t* __restrict__ eflags,
                                                   const int32_t* __restrict__ eface,
                                                   const double* __restrict__ ulin, double mu, double nu,
-                                                  double* __restrict__ lam) {
+                                                  double lscale, double* __restrict__ lam) {
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (k >= ne) return;
   const uint32_t fl = eflags[k];
@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __re
     return;
   }
   double A[6][6];
-  ns_lambda_elem<2>(ne, k, ecoord, fl, eface, ulin, mu, nu, RegMat<6>{A}, lam);
+  ns_lambda_elem<2>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, RegMat<6>{A}, lam);
 }
 
 // threads per block of the 3D Newton-step element kernels (LDS: 144 doubles per thread)
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(BS_NS3) k_ns_lambda3(int64_t ne, const double*
                                                        const uint32_t* __restrict__ eflags,
                                                        const int32_t* __restrict__ eface,
                                                        const double* __restrict__ ulin, double mu, double nu,
-                                                       double* __restrict__ lam) {
+                                                       double lscale, double* __restrict__ lam) {
   extern __shared__ double lds_ns[];
   int64_t k = (int64_t)blockIdx.x * BS_NS3 + threadIdx.x;
   if (k >= ne) return;
@@ -409,14 +409,15 @@ __global__ void __launch_bounds__(BS_NS3) k_ns_lambda3(int64_t ne, const double*
     lam[k] = 0.0;
     return;
   }
-  ns_lambda_elem<3>(ne, k, ecoord, fl, eface, ulin, mu, nu, LdsMat<12>{lds_ns + threadIdx.x, BS_NS3}, lam);
+  ns_lambda_elem<3>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, LdsMat<12>{lds_ns + threadIdx.x, BS_NS3},
+                    lam);
 }
 
 // Stokes steady (mu = 0) lambda: same rule with the Stokes element matrix
 template <int D>
 __global__ void __launch_bounds__(BS) k_stokes_lambda(int64_t ne, const double* __restrict__ ecoord,
                                                       const uint32_t* __restrict__ eflags, double mu, double nu,
-                                                      double* __restrict__ lam) {
+                                                      double lscale, double* __restrict__ lam) {
   constexpr int N = D + 1;
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (k >= ne) return;
@@ -442,7 +443,7 @@ __global__ void __launch_bounds__(BS) k_stokes_lambda(int64_t ne, const double* 
     }
     mx = interior(fl, j) ? fmax(mx, s) : mx;
   }
-  lam[k] = 2.0 * mx;
+  lam[k] = lscale * mx;
 }
 
 struct NsFactors {
@@ -1407,10 +1408,11 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
   if (st != CR_OK) return st;
   const double* up = u_prev ? s->uprev : nullptr;
   const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
+  const double lscale = s->params.lambda_scale > 0.0 ? s->params.lambda_scale : 2.0;
   if (ns && d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_ns_lambda, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->ulin,
-                         s->params.mu, s->params.nu, s->lam);
+                         s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_ns, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->enb,
                        steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack, s->RK,
                        s->sK, s->err);
@@ -1428,7 +1430,7 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     const unsigned g3 = nblocks(s->ne, BS_NS3);
     if (steady)
       hipLaunchKernelGGL(k_ns_lambda3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags,
-                         s->eface, s->ulin, s->params.mu, s->params.nu, s->lam);
+                         s->eface, s->ulin, s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_ns3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack,
                        s->RK, s->sK, s->err);
@@ -1438,7 +1440,7 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
   } else if (d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
-                         s->params.mu, s->params.nu, s->lam);
+                         s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
                        s->sK, s->err);
@@ -1451,7 +1453,7 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
   } else {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
-                         s->params.mu, s->params.nu, s->lam);
+                         s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
                        s->sK, s->err);
