@@ -40,6 +40,8 @@ class Mesh:
     a: np.ndarray               # [ne, d+1, d] a_{K,sigma} = |sigma| n_{K,sigma}, outward
     area: np.ndarray            # [ne, d+1] |sigma|
     sign: np.ndarray = field(default=None)  # [ne, d+1] C_K entry of local face j (0 if exterior)
+    bfaces: np.ndarray = field(default=None)      # [nbf, d] exterior faces, sorted vertex ids, lexicographic
+    elem_bface: np.ndarray = field(default=None)  # [ne, d+1] exterior face of local face j, -1 if interior
 
     @property
     def ne(self):
@@ -110,6 +112,10 @@ def build_mesh(coords, elems) -> Mesh:
     m = Mesh(coords=coords, elems=elems, d=d, faces=faces, elem_face=elem_face,
              face_elems=owners, vol=vol, xK=xK, xs=xs, a=a, area=area)
     m.sign = default_signs(m)
+    bcanon = -np.ones(len(uniq), dtype=np.int64)
+    bcanon[~interior] = np.arange(int((~interior).sum()))
+    m.bfaces = uniq[~interior]
+    m.elem_bface = bcanon[inv].reshape(ne, d1)
     return m
 
 
@@ -297,6 +303,11 @@ class Problem:
     k0: int = 0
     ulin: np.ndarray = None
     lam_scale: float = 2.0    # lambda_K = lam_scale * ||A_K||_inf on M1 (mu = 0), see element_E
+    e: np.ndarray = None      # [ne] right-hand side of D_K^t U_K = e_K (boundary data; None: zero)
+    gbnd: np.ndarray = None   # [nbf, d] velocity on the exterior faces (None: zero)
+
+    def ediv(self):
+        return np.zeros(self.mesh.ne) if self.e is None else self.e
 
     @property
     def d(self):
@@ -317,7 +328,14 @@ class Problem:
         return self._l2g
 
 
-def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad_rule=None, lam_scale=2.0):
+def boundary_local_values(m: Mesh, gbnd):
+    """Exterior-face values [nbf, d] gathered into [ne, d1, d], zeros on interior faces."""
+    g = np.asarray(gbnd)
+    return np.where(m.elem_bface[:, :, None] >= 0, g[np.maximum(m.elem_bface, 0)], 0.0)
+
+
+def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad_rule=None, lam_scale=2.0,
+                 gbnd=None):
     """Element data of eq. syslin: A_K, D_K, R_K (Section 3.1).
 
     Stokes: A_K = S_K on each diagonal component block.  Navier-Stokes Newton
@@ -333,12 +351,25 @@ def make_problem(coords, elems, mu, nu, fbar, u_prev=None, ulin=None, k0=0, quad
     S = element_S(m, mu, nu, quad_rule)
     A = np.einsum("est,ij->esitj", S, np.eye(d)).reshape(m.ne, (d + 1) * d, (d + 1) * d)
     R = element_R(m, np.asarray(fbar, dtype=np.float64), mu, u_prev)
+    Gl = None if gbnd is None else boundary_local_values(m, gbnd)
     if ulin is not None:
         Ub = local_face_values(m, ulin)
+        if Gl is not None:
+            Ub = Ub + Gl  # the linearisation velocity takes the boundary data on exterior faces
         A = A + convection_jacobian(m, Ub)
         R = R + convection(m, Ub, Ub)
-    return Problem(mesh=m, mu=float(mu), nu=float(nu), A=A, D=element_D(m), R=R, k0=int(k0),
-                   ulin=None if ulin is None else np.asarray(ulin), lam_scale=float(lam_scale))
+    D = element_D(m)
+    e = None
+    if Gl is not None:
+        # known exterior-face values move to the right-hand side: the velocity
+        # rows lose A_K[., bnd] g, and the divergence row of K reads
+        # D_K^t U_K = -D_K[bnd] . g =: e_K over its interior faces
+        g = Gl.reshape(m.ne, -1)
+        R = R - np.einsum("eab,eb->ea", A, g)
+        e = -(D * g).sum(axis=1)
+    return Problem(mesh=m, mu=float(mu), nu=float(nu), A=A, D=D, R=R, k0=int(k0),
+                   ulin=None if ulin is None else np.asarray(ulin), lam_scale=float(lam_scale), e=e,
+                   gbnd=None if gbnd is None else np.asarray(gbnd, dtype=np.float64))
 
 
 def restrict(P: Problem, k):
@@ -382,6 +413,14 @@ def assemble_coupled(P: Problem):
     return A, D, R, prow
 
 
+def divergence_rhs(P: Problem, prow):
+    """Right-hand side of the divergence rows (K != K0, row order prow): e_K."""
+    e = np.zeros(P.mesh.ne - 1)
+    keep = prow >= 0
+    e[prow[keep]] = P.ediv()[keep]
+    return e
+
+
 def solve_coupled(P: Problem, refine=0):
     """Solve [A D^t; D 0][U; P] = [R; 0] with sparse LU (SuperLU).
 
@@ -394,7 +433,7 @@ def solve_coupled(P: Problem, refine=0):
     A, D, R, prow = assemble_coupled(P)
     n = A.shape[0]
     M = sps.bmat([[A, D.T], [D, None]], format="csc")
-    rhs = np.concatenate([R, np.zeros(D.shape[0])])
+    rhs = np.concatenate([R, divergence_rhs(P, prow)])
     lu = spla.splu(M, permc_spec="COLAMD")
     sol = lu.solve(rhs)
     for _ in range(int(refine)):
@@ -483,7 +522,7 @@ def eliminate(P: Problem, E=None, signs=None):
     structure used), B_K = D_K^t A^_K^{-1} D_K, and
         G_K = C_K (A^_K^{-1} - A^_K^{-1} D_K D_K^t A^_K^{-1} / B_K) C_K   (K != K0)
         G_K0 = C_K0 A^_K0^{-1} C_K0
-        s_K  = C_K (A^_K^{-1} R_K - A^_K^{-1} D_K D_K^t A^_K^{-1} R_K / B_K)
+        s_K  = C_K (A^_K^{-1} R_K - A^_K^{-1} D_K (D_K^t A^_K^{-1} R_K - e_K) / B_K)
     with the non-symmetric reading A^{-1} D D^t A^{-1} = l r^t, l = A^{-1} D,
     r = A^{-t} D, which is what the elimination computes.  G = sum H_K G_K H_K^t
     and S = sum H_K s_K.
@@ -495,6 +534,7 @@ def eliminate(P: Problem, E=None, signs=None):
     if signs is None:
         signs = m.sign
     n = m.nf * d
+    ek = P.ediv()
     rows, cols, vals = [], [], []
     S = np.zeros(n)
     out = Hybrid(G=None, S=None, Ainv=[], l=[], r=[], B=np.zeros(m.ne), C=[], Rl=[], Dl=[], gidx=[])
@@ -510,7 +550,7 @@ def eliminate(P: Problem, E=None, signs=None):
         B = Dk @ l
         if k != P.k0:
             Gk = Ck @ (Ainv - np.outer(l, r) / B) @ Ck
-            sk = Ck @ (Ainv @ Rk - l * (r @ Rk) / B)
+            sk = Ck @ (Ainv @ Rk - l * (r @ Rk - ek[k]) / B)
         else:
             Gk = Ck @ Ainv @ Ck
             sk = Ck @ Ainv @ Rk
@@ -534,8 +574,8 @@ def eliminate(P: Problem, E=None, signs=None):
 def recover(P: Problem, H: Hybrid, W):
     """Recovery of P and U^ from W (Section 3.2, items 2 and 4).
 
-    P_K = r_K^t (R_K - C_K W_K) / B_K for K != K0 (the divergence row
-    D_K^t U^_K = 0 solved for P_K), P_K0 = 0, and
+    P_K = (r_K^t (R_K - C_K W_K) - e_K) / B_K for K != K0 (the divergence row
+    D_K^t U^_K = e_K solved for P_K; e_K = 0 without boundary data), P_K0 = 0, and
     U^_K = A^_K^{-1} (R_K - D_K P_K - C_K W_K), W_K = H_K^t W.
     Returns (U [nf, d] taken from the copy of the element with C = +1,
     P [ne], Uhat list of local copies).
@@ -545,12 +585,13 @@ def recover(P: Problem, H: Hybrid, W):
     W = np.asarray(W).ravel()
     U = np.zeros(m.nf * d)
     Pk = np.zeros(m.ne)
+    ek = P.ediv()
     Uhat = []
     for k in range(m.ne):
         Wk = W[H.gidx[k]]
         rhs = H.Rl[k] - H.C[k] @ Wk
         if k != P.k0:
-            Pk[k] = H.r[k] @ rhs / H.B[k]
+            Pk[k] = (H.r[k] @ rhs - ek[k]) / H.B[k]
         uk = H.Ainv[k] @ (rhs - H.Dl[k] * Pk[k])
         Uhat.append(uk)
         own = np.diag(H.C[k]) > 0
@@ -585,11 +626,11 @@ def divergence(P: Problem, U):
 
 
 def coupled_residual(P: Problem, U, Pk):
-    """Relative residuals of eq. syslin: (||R - A U - D^t P|| / ||R||, max_K |D_K U| / max|D_K|)."""
+    """Relative residuals of eq. syslin: (||R - A U - D^t P|| / ||R||, max_K |D_K U - e_K| / max|D_K|)."""
     A, D, R, prow = assemble_coupled(P)
     Pv = Pk[prow >= 0][np.argsort(prow[prow >= 0])]
     u = np.asarray(U).ravel()
     r1 = R - A @ u - D.T @ Pv
-    div = divergence(P, U)
+    div = divergence(P, U) - P.ediv()
     scale = np.abs(P.D).max() * np.abs(u).max() if np.abs(u).max() > 0 else 1.0
     return np.linalg.norm(r1) / np.linalg.norm(R), np.abs(div).max() / scale

@@ -2,7 +2,7 @@
 
 Test infrastructure only.  The discrete velocity is affine on each element,
 u_h|_K = sum_sigma U_sigma phi_sigma with the CR basis of Section 2 item 1
-(U = 0 on exterior faces); the discrete pressure is constant per element
+(U = 0, or the given boundary data, on exterior faces); the discrete pressure is constant per element
 (Section 2 item 5) and is compared after removing its |K|-weighted mean, as
 Section 2 item 5 suggests for retrieving an element of L^2_0.
 """
@@ -10,13 +10,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from .cr import Mesh, cr_basis, local_face_values
+from .cr import Mesh, boundary_local_values, cr_basis, local_face_values
 
 
-def errors(m: Mesh, U, Pk, exact_u, exact_grad, exact_p, quad):
+def errors(m: Mesh, U, Pk, exact_u, exact_grad, exact_p, quad, gbnd=None):
     """Broken L2 and H1 velocity errors and L2 pressure error.
 
     quad = (barycentric points [nq, d+1], weights [nq] summing to 1).
+    gbnd: the velocity on the exterior faces [nbf, d] (None: zero).
     Returns dict(l2u, h1u, l2p) of absolute errors.
     """
     lam, wt = quad
@@ -25,6 +26,8 @@ def errors(m: Mesh, U, Pk, exact_u, exact_grad, exact_p, quad):
     pts = np.einsum("qj,ejd->eqd", lam, X)
     ne, nq, d = pts.shape
     Ul = local_face_values(m, U)                                   # [ne, d1, d]
+    if gbnd is not None:
+        Ul = Ul + boundary_local_values(m, gbnd)
     phi = c[:, None, :] + np.einsum("eqd,esd->eqs", pts - m.xK[:, None, :], grad)
     uh = np.einsum("eqs,esi->eqi", phi, Ul)
     guh = np.einsum("esi,esj->eij", Ul, grad)                       # d u_i / d x_j

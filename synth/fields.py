@@ -316,3 +316,70 @@ class LinearisationField3D:
             um += wi * self.u(l[0] * p0 + l[1] * p1 + l[2] * p2)
         ut = um - (um * n).sum(axis=1)[:, None] * n
         return un[:, None] * n + ut
+
+
+def face_means(coords, faces, fn, n: int = 5):
+    """Mean of a vector field fn(pts [m, dim]) -> [m, k] over each face [nf, dim]
+    (vertex ids): Gauss-Legendre on segments (2D), the collapsed rule on triangles (3D)."""
+    faces = np.asarray(faces)
+    dim = coords.shape[1]
+    P = coords[faces]  # [nf, dim(vertices), dim]
+    if dim == 2:
+        q, w = _gl01(n)
+        out = None
+        for qi, wi in zip(q, w):
+            v = wi * np.asarray(fn(P[:, 0] + qi * (P[:, 1] - P[:, 0])))
+            out = v if out is None else out + v
+        return out
+    lam, w = simplex_rule(2, n)
+    out = None
+    for l, wi in zip(lam, w):
+        v = wi * np.asarray(fn(l[0] * P[:, 0] + l[1] * P[:, 1] + l[2] * P[:, 2]))
+        out = v if out is None else out + v
+    return out
+
+
+class GreenTaylor2D:
+    """The Green-Taylor vortex on the unit square, an exact solution of the
+    Navier-Stokes equations with zero force for any viscosity nu:
+      u = amp (-cos(pi x) sin(pi y), sin(pi x) cos(pi y)) exp(-2 pi^2 nu t),
+      p = -amp^2 (cos(2 pi x) + cos(2 pi y)) / 4 exp(-4 pi^2 nu t).
+    Its velocity does not vanish on the boundary of the square (non-homogeneous
+    Dirichlet data, zero net flux).  Also the force that makes (u, p) a
+    solution of the Stokes problem mu u - nu Lap u + grad p = f at time t."""
+
+    def __init__(self, amp: float = 1.0, nu: float = 1.0):
+        self.amp = float(amp)
+        self.nu = float(nu)
+
+    def _decay(self, t, k=2):
+        return math.exp(-k * math.pi ** 2 * self.nu * t)
+
+    def u(self, pts, t=0.0):
+        x, y = pts[:, 0], pts[:, 1]
+        e = self.amp * self._decay(t)
+        return np.stack([-np.cos(np.pi * x) * np.sin(np.pi * y), np.sin(np.pi * x) * np.cos(np.pi * y)], axis=1) * e
+
+    def grad_u(self, pts, t=0.0):
+        """[m, 2 (component), 2 (derivative)]"""
+        x, y = pts[:, 0], pts[:, 1]
+        e = self.amp * self._decay(t) * np.pi
+        g = np.empty((len(x), 2, 2))
+        g[:, 0, 0] = np.sin(np.pi * x) * np.sin(np.pi * y) * e
+        g[:, 0, 1] = -np.cos(np.pi * x) * np.cos(np.pi * y) * e
+        g[:, 1, 0] = np.cos(np.pi * x) * np.cos(np.pi * y) * e
+        g[:, 1, 1] = -np.sin(np.pi * x) * np.sin(np.pi * y) * e
+        return g
+
+    def p(self, pts, t=0.0):
+        x, y = pts[:, 0], pts[:, 1]
+        return -self.amp ** 2 * (np.cos(2 * np.pi * x) + np.cos(2 * np.pi * y)) / 4.0 * self._decay(t, 4)
+
+    def stokes_force(self, mu, t=0.0):
+        """f = mu u - nu Lap u + grad p at time t (Lap u = -2 pi^2 u)."""
+        def fn(pts):
+            x, y = pts[:, 0], pts[:, 1]
+            gp = self.amp ** 2 * np.pi / 2.0 * self._decay(t, 4) * np.stack([np.sin(2 * np.pi * x),
+                                                                             np.sin(2 * np.pi * y)], axis=1)
+            return (mu + 2.0 * np.pi ** 2 * self.nu) * self.u(pts, t) + gp
+        return fn

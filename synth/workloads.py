@@ -38,6 +38,16 @@ def interior_face_list(elems):
     return uniq[counts == 2].astype(np.int32)
 
 
+def exterior_face_list(elems):
+    """Exterior (boundary) faces as sorted vertex tuples in lexicographic order:
+    the order of the boundary data of the solver interface."""
+    d1 = elems.shape[1]
+    loc = np.stack([np.delete(elems, j, axis=1) for j in range(d1)], axis=1)
+    keys = np.sort(loc.reshape(-1, d1 - 1), axis=1)
+    uniq, counts = np.unique(keys, axis=0, return_counts=True)
+    return uniq[counts == 1].astype(np.int32)
+
+
 def transient_stokes(mesh, mu, nu, seed=0, quad=4):
     coords, elems = mesh
     dim = coords.shape[1]

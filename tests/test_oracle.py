@@ -645,3 +645,117 @@ def test_oracle_pcg_matches_direct():
     x, it, hist = krylov.pcg(H.G, H.S, tol=1e-13)
     assert np.abs(x - W).max() < 1e-9 * np.abs(W).max()
     assert hist[-1] <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Non-homogeneous Dirichlet data (the tests of Section 4 impose the exact
+# velocity on the boundary): known exterior-face values move to the right-hand
+# side of the velocity rows, and the divergence row of K becomes
+# D_K^t U_K = e_K = -D_K[bnd] . g.
+# --------------------------------------------------------------------------
+
+def _bnd_mesh(dim):
+    if dim == 2:
+        return synth.square_mesh(6, jitter=0.2, seed=21)
+    return synth.cube_mesh(2)
+
+
+def _face_pts(coords, faces):
+    return coords[np.asarray(faces)].mean(axis=1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("kind", ["transient", "steady", "ns"])
+def test_boundary_constant_velocity_exact(dim, kind):
+    """A constant velocity c imposed on the boundary, zero force (and, transient,
+    c as the previous step; Newton step about c) gives U = c and P = 0 exactly:
+    constants are in the kernel of the stiffness rows, have zero divergence on
+    every element, and make the convection differences vanish."""
+    coords, elems = _bnd_mesh(dim)
+    c = np.arange(1.0, dim + 1.0) * 0.7
+    bf = wl.exterior_face_list(elems)
+    nf = len(wl.interior_face_list(elems))
+    g = np.tile(c, (len(bf), 1))
+    mu = {"transient": 50.0, "steady": 0.0, "ns": 0.0}[kind]
+    up = np.tile(c, (nf, 1)) if kind == "transient" else None
+    ulin = np.tile(c, (nf, 1)) if kind == "ns" else None
+    P = cr.make_problem(coords, elems, mu, 0.3, np.zeros((len(elems), dim)), u_prev=up, ulin=ulin, gbnd=g)
+    U, Pk = cr.solve_coupled(P)
+    assert np.abs(U - c).max() < 1e-11 * np.abs(c).max()
+    assert np.abs(Pk).max() < 1e-10
+    Uh, Ph, W, H, Uhat = cr.solve_hybrid(P)
+    assert np.abs(Uh - c).max() < 1e-11 * np.abs(c).max()
+    assert np.abs(Ph).max() < 1e-10
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mu", [0.0, 40.0])
+def test_boundary_affine_velocity_exact(dim, mu):
+    """An affine, divergence-free, harmonic velocity (2D: (y, x); 3D: (y, z, x))
+    with zero pressure solves the Stokes problem with zero force (transient:
+    with itself as the previous step); the CR scheme reproduces it exactly:
+    U = its face means, P = 0."""
+    coords, elems = _bnd_mesh(dim)
+    perm = [1, 0] if dim == 2 else [1, 2, 0]
+    u = lambda x: x[:, perm]
+    bf = wl.exterior_face_list(elems)
+    fi = wl.interior_face_list(elems)
+    g = u(_face_pts(coords, bf))
+    ue = u(_face_pts(coords, fi))
+    P = cr.make_problem(coords, elems, mu, 1.0, np.zeros((len(elems), dim)), u_prev=ue if mu > 0 else None, gbnd=g)
+    U, Pk = cr.solve_coupled(P)
+    assert np.abs(U - ue).max() < 1e-11
+    assert np.abs(Pk).max() < 1e-10
+    Uh, Ph, W, H, Uhat = cr.solve_hybrid(P)
+    assert np.abs(Uh - ue).max() < 1e-11
+    assert np.abs(Ph).max() < 1e-10
+    # the velocity including the boundary data is divergence-free on every element
+    assert np.abs(cr.divergence(P, Uh) - P.ediv()).max() < 1e-12
+
+
+@pytest.mark.parametrize("dim,kind", [(2, "stokes"), (3, "stokes"), (2, "steady"), (2, "ns"), (3, "ns")])
+def test_boundary_hybrid_equals_coupled(dim, kind):
+    """Section 3.2 item 2 with boundary data: the hybrid system's (U, P) is the
+    coupled solution; the copies agree; D_K U_K = e_K on every element but K0,
+    and on K0 up to the data's net flux."""
+    coords, elems = _bnd_mesh(dim)
+    rng = np.random.default_rng(5 + dim)
+    bf = wl.exterior_face_list(elems)
+    nf = len(wl.interior_face_list(elems))
+    g = rng.normal(size=(len(bf), dim))
+    f = rng.normal(size=(len(elems), dim))
+    mu = {"stokes": 30.0, "steady": 0.0, "ns": 0.0}[kind]
+    ulin = rng.normal(size=(nf, dim)) if kind == "ns" else None
+    P = cr.make_problem(coords, elems, mu, 0.5, f, ulin=ulin, gbnd=g)
+    U, Pk = cr.solve_coupled(P)
+    Uh, Ph, W, H, Uhat = cr.solve_hybrid(P)
+    assert np.abs(Uh - U).max() <= 1e-10 * np.abs(U).max()
+    assert np.abs(Ph - Pk).max() <= 1e-10 * np.abs(Pk).max()
+    assert np.abs(cr.jump(P, H, Uhat)).max() < 1e-10 * np.abs(U).max()
+    div = cr.divergence(P, Uh) - P.ediv()
+    scale = np.abs(P.D).max() * max(np.abs(Uh).max(), np.abs(g).max())
+    others = np.arange(P.mesh.ne) != P.k0
+    assert np.abs(div[others]).max() < 1e-11 * scale
+    # K0's divergence row is not imposed: it takes up the net flux of the (random)
+    # data, sum_K e_K, since sum_K D_K^t U_K = 0 (the two a's of a face cancel)
+    assert abs(div[P.k0] + P.ediv().sum()) < 1e-10 * scale
+
+
+def test_green_taylor_stokes_orders_with_boundary_data():
+    """Orders with non-homogeneous data: the Green-Taylor vortex as a Stokes
+    solution (force mu u - nu Lap u + grad p), its face means imposed on the
+    boundary; velocity L2 order -> 2, broken H1 -> 1, pressure > 1
+    (Section 4.1, Table tab0 prints ratios near 2 for velocity and pressure)."""
+    from synth.fields import GreenTaylor2D, face_means
+    gt = GreenTaylor2D(amp=1.0, nu=1.0)
+    quad = synth.simplex_rule(2, 5)
+    errs = []
+    for n in (8, 16, 32):
+        coords, elems = synth.square_mesh(n)
+        fbar = synth.element_means(coords, elems, gt.stokes_force(10.0), n=4)
+        g = face_means(coords, wl.exterior_face_list(elems), gt.u)
+        P = cr.make_problem(coords, elems, 10.0, 1.0, fbar, gbnd=g)
+        U, Pk = cr.solve_coupled(P)
+        errs.append(norms.errors(P.mesh, U, Pk, gt.u, gt.grad_u, gt.p, quad, gbnd=g))
+    o = _orders(errs)
+    assert o[-1]["l2u"] > 1.8 and 0.9 < o[-1]["h1u"] < 1.2 and o[-1]["l2p"] > 1.0, o
