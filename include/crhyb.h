@@ -285,6 +285,29 @@ cr_status cr_import_W(cr_system* sys, const double* W);
  * Caller-owned host buffer.  Errors: CR_E_INVAL (NULL system or buffer). */
 cr_status cr_interior_faces(const cr_system* sys, int32_t* face_vertices);
 
+/* Exterior faces of the mesh (faces of one element, Section 2 item 1) as
+ * sorted vertex ids [n_bnd_faces][dim] int32, lexicographic in those ids: the
+ * order of the boundary data of cr_set_boundary.  face_vertices may be NULL
+ * (count only).  Host only.  Errors: CR_E_INVAL (NULL system). */
+cr_status cr_boundary_faces(const cr_system* sys, int64_t* n_bnd_faces, int32_t* face_vertices);
+
+/* Non-homogeneous Dirichlet data, as in the tests of Section 4 (the exact
+ * velocity imposed on the boundary): g is a DEVICE array [n_bnd_faces][dim]
+ * of face-mean velocities on the exterior faces (cr_boundary_faces order),
+ * copied on the system's stream; NULL returns to homogeneous data.  It takes
+ * effect at the next cr_eliminate / cr_update_rhs: the columns of the exterior
+ * faces of A_K times the data leave the velocity rows of R_K, the divergence
+ * row of K reads D_K^t U_K = e_K with e_K = -D_K[exterior] . g, and the
+ * elimination and recovery of Section 3.2 items 2 and 4 carry e_K (P_K =
+ * (r_K^t (R_K - C_K W_K) - e_K) / B_K).  For the Newton step the exterior faces
+ * of the linearisation velocity take the data too.  The divergence row of K0
+ * is not imposed, so it absorbs the net flux of the data (zero for exact data
+ * of a divergence-free field).  With boundary data, CG applies the assembled
+ * rows of G (the element form and its coarse correction need homogeneous
+ * data).  Errors: CR_E_INVAL (NULL system, no exterior face), CR_E_NOMEM,
+ * CR_E_DEVICE. */
+cr_status cr_set_boundary(cr_system* sys, const double* g);
+
 /* Host-only topology (step a0 without any device work), for inspection:
  * n_int_faces, the internal position of every canonical face (perm [n_int_faces],
  * may be NULL), the half bandwidth of the face adjacency in internal order and in

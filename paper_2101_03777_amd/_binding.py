@@ -33,7 +33,8 @@ EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recov
            "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
            "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
            "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy", "cr_prepare",
-           "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled", "cr_recover_noalloc"]
+           "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled", "cr_recover_noalloc",
+           "cr_boundary_faces", "cr_set_boundary"]
 
 
 class CRError(RuntimeError):
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
         "cr_export_coupled": (I32, [P, P, P, P, P]),
         "cr_import_W": (I32, [P, P]),
         "cr_interior_faces": (I32, [P, P]),
+        "cr_boundary_faces": (I32, [P, C.POINTER(I64), P]),
+        "cr_set_boundary": (I32, [P, P]),
         "cr_topology": (I32, [C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(I64), P, C.POINTER(I64),
                               C.POINTER(I64), P]),
         "cr_coupled_solve": (I32, [P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P, P]),
@@ -438,6 +441,30 @@ class System:
     def import_W(self, W):
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.n_int_faces, self.dim)
         _check(self.lib.cr_import_W(self.h, _ptr(W)))
+
+    def boundary_faces(self):
+        """Exterior faces [n_bnd_faces, dim] (sorted vertex ids), the order of set_boundary's data."""
+        n = C.c_int64()
+        _check(self.lib.cr_boundary_faces(self.h, C.byref(n), None))
+        fv = np.empty((n.value, self.dim), dtype=np.int32)
+        _check(self.lib.cr_boundary_faces(self.h, C.byref(n), _ptr(fv)))
+        return fv
+
+    def set_boundary(self, g):
+        """Non-homogeneous Dirichlet data: face means [n_bnd_faces, dim] (device
+        tensor or numpy array), or None for homogeneous data."""
+        if g is None:
+            _check(self.lib.cr_set_boundary(self.h, None))
+            self._gb = None
+            return
+        torch = self._torch
+        if isinstance(g, np.ndarray):
+            g = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float64)).cuda()
+        n = C.c_int64()
+        _check(self.lib.cr_boundary_faces(self.h, C.byref(n), None))
+        g = self._dev(g, (n.value, self.dim))
+        self._gb = g
+        _check(self.lib.cr_set_boundary(self.h, _ptr(g)))
 
     def interior_faces(self):
         fv = np.empty((self.n_int_faces, self.dim), dtype=np.int32)

@@ -640,6 +640,53 @@ cr_status cr_interior_faces(const cr_system* s, int32_t* face_vertices) {
   return CR_OK;
 }
 
+cr_status cr_boundary_faces(const cr_system* s, int64_t* n_bnd_faces, int32_t* face_vertices) {
+  clear_error();
+  if (!s) {
+    set_error("NULL system");
+    return CR_E_INVAL;
+  }
+  if (n_bnd_faces) *n_bnd_faces = s->topo.nbf;
+  if (face_vertices) std::copy(s->topo.bface_vertices.begin(), s->topo.bface_vertices.end(), face_vertices);
+  return CR_OK;
+}
+
+cr_status cr_set_boundary(cr_system* s, const double* g) {
+  clear_error();
+  if (!s) {
+    set_error("NULL system");
+    return CR_E_INVAL;
+  }
+  if (!g) {
+    s->has_bnd = false;
+    return CR_OK;
+  }
+  const int d = s->d, d1 = d + 1;
+  const int64_t ne = s->ne, nbf = s->topo.nbf;
+  if (nbf == 0) {
+    set_error("the mesh has no exterior face");
+    return CR_E_INVAL;
+  }
+  cr_status st = CR_OK;
+  if (!s->ebf) {
+    // exterior face of each local face, internal element order
+    std::vector<int32_t> h((size_t)d1 * ne);
+    for (int64_t k = 0; k < ne; ++k) {
+      const int64_t c = s->topo.elem_iperm[k];
+      for (int j = 0; j < d1; ++j) h[(size_t)j * ne + k] = s->topo.elem_bface[(size_t)c * d1 + j];
+    }
+    st = upload(s, s->ebf, h);
+    if (st == CR_OK) st = alloc_n(s, s->gbnd, (size_t)nbf * d);
+    if (st == CR_OK) st = alloc_n(s, s->ek, (size_t)ne);
+    if (st != CR_OK) return st;
+  }
+  st = check_hip(hipMemcpyAsync(s->gbnd, g, sizeof(double) * nbf * d, hipMemcpyDeviceToDevice, s->stream),
+                 "boundary data");
+  if (st != CR_OK) return st;
+  s->has_bnd = true;
+  return CR_OK;
+}
+
 cr_status cr_time_spmv(cr_system* s, int32_t precision, int32_t operator_form, int32_t reps, double* avg_ms,
                        double* bytes) {
   clear_error();

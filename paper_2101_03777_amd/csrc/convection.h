@@ -21,6 +21,28 @@ struct NsPack {
 
 // A(r, c) of a local NU x NU matrix: in registers (2D), or in the calling
 // thread's column of an LDS array (3D: 144 doubles per element)
+// Non-homogeneous Dirichlet data seen from an element: the exterior face of
+// each local face (-1 interior; ebf == nullptr: no data), the data in canonical
+// exterior order, and the divergence right-hand side e_K written by the
+// elimination.
+struct Bnd {
+  const int32_t* ebf;  // [d+1][ne]
+  const double* g;     // [nbf][d]
+  double* ek;          // [ne]
+};
+
+// the data at the element's local faces, zero on interior faces
+template <int D>
+__device__ __forceinline__ void load_bnd(const Bnd& b, uint32_t fl, int64_t ne, int64_t k, double (&Gb)[D + 1][D]) {
+#pragma unroll
+  for (int j = 0; j <= D; ++j) {
+    const bool ext = b.ebf != nullptr && !((fl >> j) & 1u);
+    const int64_t e = ext ? b.ebf[j * ne + k] : 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) Gb[j][i] = ext ? b.g[e * D + i] : 0.0;
+  }
+}
+
 template <int NU>
 struct RegMat {
   double (&m)[NU][NU];
@@ -34,10 +56,19 @@ struct LdsMat {
   __device__ double& operator()(int r, int c) const { return base[(r * NU + c) * stride]; }
 };
 
+// Ub: the linearisation velocity at the local faces (the boundary data on
+// exterior faces); Gb: the boundary data (zero on interior faces).  Rows and
+// columns of exterior faces are removed from A, and Rb receives the columns of
+// exterior faces times their data, -sum_r A[s, r] g_r, for the right-hand side.
 template <int D, class M>
 __device__ __forceinline__ void ns_local(const Geo<D>& g, uint32_t fl, const double (&Ub)[D + 1][D], double mu,
-                                         double nu, const M& A, double (&Nuu)[D + 1][D]) {
+                                         double nu, const M& A, double (&Nuu)[D + 1][D],
+                                         const double (&Gb)[D + 1][D], double (&Rb)[D + 1][D]) {
   constexpr int N = D + 1;
+#pragma unroll
+  for (int s = 0; s < N; ++s)
+#pragma unroll
+    for (int i = 0; i < D; ++i) Rb[s][i] = 0.0;
   const double m = mu * g.vol / N, iv = nu / g.vol;
   double F[N][N], gx[N][N][D], Um[D];
 #pragma unroll
@@ -95,20 +126,24 @@ __device__ __forceinline__ void ns_local(const Geo<D>& g, uint32_t fl, const dou
             v += 0.5 * coef * gx[s][t][j] * (Ub[t][i] - Ub[s][i]);
           }
           bool in = interior(fl, s) && interior(fl, r);
+          if (interior(fl, s) && !interior(fl, r)) Rb[s][i] -= v * Gb[r][j];
           A(s * D + i, r * D + j) = in ? v : ((s == r && i == j) ? 1.0 : 0.0);
         }
   }
 }
 
+// the linearisation velocity at the local faces: interior faces from ulin,
+// exterior faces from the boundary data Gb (zero without data)
 template <int D>
 __device__ __forceinline__ void load_ubar(const double* __restrict__ ulin, const int32_t* __restrict__ eface,
-                                          uint32_t fl, int64_t ne, int64_t k, double (&Ub)[D + 1][D]) {
+                                          uint32_t fl, int64_t ne, int64_t k, const double (&Gb)[D + 1][D],
+                                          double (&Ub)[D + 1][D]) {
 #pragma unroll
   for (int j = 0; j <= D; ++j) {
     bool in = ulin != nullptr && interior(fl, j);
     int f = in ? eface[j * ne + k] : 0;
 #pragma unroll
-    for (int i = 0; i < D; ++i) Ub[j][i] = in ? ulin[(int64_t)f * D + i] : 0.0;
+    for (int i = 0; i < D; ++i) Ub[j][i] = in ? ulin[(int64_t)f * D + i] : Gb[j][i];
   }
 }
 

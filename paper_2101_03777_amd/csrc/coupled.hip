@@ -131,8 +131,9 @@ template <int D>
 __global__ void __launch_bounds__(128) k_coupled_elems(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
                                                        const uint32_t* __restrict__ eflags,
                                                        const int32_t* __restrict__ eface,
-                                                       const double* __restrict__ Aval, double* __restrict__ ea,
-                                                       double* __restrict__ bvec, double* __restrict__ dinv) {
+                                                       const double* __restrict__ Aval, const double* __restrict__ ek,
+                                                       double* __restrict__ ea, double* __restrict__ bvec,
+                                                       double* __restrict__ dinv) {
   constexpr int N = D + 1;
   int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (k >= ne) return;
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(128) k_coupled_elems(int64_t nf, int64_t ne, c
     }
     if (in) sch += a2 / Aval[eface[j * ne + k]];
   }
-  bvec[nf * D + k] = 0.0;
+  bvec[nf * D + k] = (ek != nullptr && !k0) ? ek[k] : 0.0;
   dinv[nf * D + k] = k0 ? 0.0 : 1.0 / sch;
 }
 
@@ -261,13 +262,15 @@ __global__ void __launch_bounds__(NT) k_mr_init(CDims C, MatArgs M, const double
     }
   } else {
     for (int64_t k = lo + threadIdx.x; k < hi; k += NT) {
-      const double ri = -coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x});
+      // divergence rows: right-hand side e_K (boundary data), else zero
+      const double bi = b[off + k], ri = bi - coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x});
       r1[off + k] = ri;
       r2[off + k] = ri;
       w0[off + k] = 0.0;
       w1[off + k] = 0.0;
       acc[0] += ri * ri * dinv[off + k];
       acc[1] += ri * ri;
+      acc[2] += bi * bi;
     }
   }
   block_sum<3>(acc);
@@ -465,15 +468,16 @@ __global__ void k_mr_scatter(int64_t nf, int64_t ne, const double* __restrict__ 
 template <int D, class M>
 __device__ __forceinline__ void ns_amat_elem(int64_t ne, int64_t k, const double* __restrict__ ecoord,
                                              const uint32_t* __restrict__ eflags, const int32_t* __restrict__ eface,
-                                             const double* __restrict__ ulin, double mu, double nu, const M& A,
-                                             double* __restrict__ amat) {
+                                             const double* __restrict__ ulin, double mu, double nu, const Bnd& bnd,
+                                             const M& A, double* __restrict__ amat) {
   constexpr int NU = NsPack<D>::NU;
   Geo<D> g;
   load_geometry<D>(ecoord, ne, k, g);
   const uint32_t fl = eflags[k];
-  double Ub[D + 1][D], Nuu[D + 1][D];
-  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
-  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  double Ub[D + 1][D], Nuu[D + 1][D], Gb[D + 1][D], Rb[D + 1][D];
+  load_bnd<D>(bnd, fl, ne, k, Gb);
+  load_ubar<D>(ulin, eface, fl, ne, k, Gb, Ub);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu, Gb, Rb);
   for (int a = 0; a < NU; ++a)
     for (int b = 0; b < NU; ++b) amat[(int64_t)(a * NU + b) * ne + k] = A(a, b);
 }
@@ -481,23 +485,23 @@ __device__ __forceinline__ void ns_amat_elem(int64_t ne, int64_t k, const double
 __global__ void __launch_bounds__(128) k_ns_amat2(int64_t ne, const double* __restrict__ ecoord,
                                                   const uint32_t* __restrict__ eflags,
                                                   const int32_t* __restrict__ eface, const double* __restrict__ ulin,
-                                                  double mu, double nu, double* __restrict__ amat) {
+                                                  double mu, double nu, Bnd bnd, double* __restrict__ amat) {
   const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (k >= ne) return;
   double A[6][6];
-  ns_amat_elem<2>(ne, k, ecoord, eflags, eface, ulin, mu, nu, RegMat<6>{A}, amat);
+  ns_amat_elem<2>(ne, k, ecoord, eflags, eface, ulin, mu, nu, bnd, RegMat<6>{A}, amat);
 }
 
 constexpr int BS_AM3 = 64;
 __global__ void __launch_bounds__(BS_AM3) k_ns_amat3(int64_t ne, const double* __restrict__ ecoord,
                                                      const uint32_t* __restrict__ eflags,
                                                      const int32_t* __restrict__ eface,
-                                                     const double* __restrict__ ulin, double mu, double nu,
+                                                     const double* __restrict__ ulin, double mu, double nu, Bnd bnd,
                                                      double* __restrict__ amat) {
   extern __shared__ double lds_am[];
   const int64_t k = (int64_t)blockIdx.x * BS_AM3 + threadIdx.x;
   if (k >= ne) return;
-  ns_amat_elem<3>(ne, k, ecoord, eflags, eface, ulin, mu, nu, LdsMat<12>{lds_am + threadIdx.x, BS_AM3}, amat);
+  ns_amat_elem<3>(ne, k, ecoord, eflags, eface, ulin, mu, nu, bnd, LdsMat<12>{lds_am + threadIdx.x, BS_AM3}, amat);
 }
 
 // face rows of the Newton-step coupled matrix: blocks of A, owner face vector,
@@ -570,7 +574,8 @@ template <int D>
 __global__ void __launch_bounds__(128) k_coupled_elems_ns(int64_t nf, int64_t ne, const double* __restrict__ ecoord,
                                                           const uint32_t* __restrict__ eflags,
                                                           const int32_t* __restrict__ eface,
-                                                          const double* __restrict__ Ablk, double* __restrict__ ea,
+                                                          const double* __restrict__ Ablk,
+                                                          const double* __restrict__ ek, double* __restrict__ ea,
                                                           double* __restrict__ bvec, double* __restrict__ dinv) {
   constexpr int N = D + 1;
   const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
@@ -590,7 +595,7 @@ __global__ void __launch_bounds__(128) k_coupled_elems_ns(int64_t nf, int64_t ne
       if (in) sch += g.a[j][i] * g.a[j][i] / fabs(Ablk[(int64_t)(i * D + i) * nf + f]);
     }
   }
-  bvec[nf * D + k] = 0.0;
+  bvec[nf * D + k] = (ek != nullptr && !k0) ? ek[k] : 0.0;
   dinv[nf * D + k] = k0 ? 0.0 : 1.0 / sch;
 }
 
@@ -731,7 +736,7 @@ __global__ void __launch_bounds__(NT) k_cb_init(CDims C, NsMat M, const double* 
     }
   } else {
     for (int64_t k = lo + threadIdx.x; k < hi; k += NT)
-      put(off + k, -coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x}), 0.0);
+      put(off + k, b[off + k] - coupled_elem_row<D>(M.ea, M.eface, C.ne, k, PlainU<D>{x}), b[off + k]);
   }
   block_sum<4>(acc);
   if (threadIdx.x == 0)
@@ -1034,7 +1039,7 @@ cr_status coupled_assemble(cr_system* s, CWs*& w) {
                      s->ecoord, s->eflags, s->fel, s->floc, s->RK, s->params.mu, s->params.nu, w->Aval, w->an, w->b,
                      w->dinv);
   hipLaunchKernelGGL(k_coupled_elems<D>, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->nf, s->ne,
-                     s->ecoord, s->eflags, s->eface, w->Aval, w->ea, w->b, w->dinv);
+                     s->ecoord, s->eflags, s->eface, w->Aval, s->has_bnd ? s->ek : nullptr, w->ea, w->b, w->dinv);
   return check_hip(hipGetLastError(), "coupled assembly");
 }
 
@@ -1134,6 +1139,7 @@ cr_status coupled_assemble_ns(cr_system* s, CWs*& w) {
   cr_status st = ensure_cws(s, w);
   if (st != CR_OK) return st;
   constexpr int NU = NsPack<D>::NU;
+  const Bnd bnd{s->has_bnd ? s->ebf : nullptr, s->gbnd, nullptr};
   if (!w->Ablk) {
     w->Ablk = (double*)dev_alloc(s, sizeof(double) * (2 * D + 1) * D * D * s->nf);
     w->amat = (double*)dev_alloc(s, sizeof(double) * NU * NU * s->ne);
@@ -1146,19 +1152,20 @@ cr_status coupled_assemble_ns(cr_system* s, CWs*& w) {
   }
   if constexpr (D == 2) {
     hipLaunchKernelGGL(k_ns_amat2, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->ne, s->ecoord,
-                       s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, w->amat);
+                       s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, bnd, w->amat);
   } else {
     const size_t lds = sizeof(double) * 144 * BS_AM3;
     st = check_hip(hipFuncSetAttribute((const void*)k_ns_amat3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                    "coupled Newton-step LDS size");
     if (st != CR_OK) return st;
     hipLaunchKernelGGL(k_ns_amat3, dim3((unsigned)((s->ne + BS_AM3 - 1) / BS_AM3)), dim3(BS_AM3), lds, s->stream,
-                       s->ne, s->ecoord, s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, w->amat);
+                       s->ne, s->ecoord, s->eflags, s->eface, s->ulin, s->params.mu, s->params.nu, bnd, w->amat);
   }
   hipLaunchKernelGGL(k_coupled_faces_ns<D>, dim3((unsigned)((s->nf + 127) / 128)), dim3(128), 0, s->stream, s->nf,
                      s->ne, s->ecoord, s->eflags, s->fel, s->floc, s->RK, w->amat, w->Ablk, w->an, w->b, w->dinv);
   hipLaunchKernelGGL(k_coupled_elems_ns<D>, dim3((unsigned)((s->ne + 127) / 128)), dim3(128), 0, s->stream, s->nf,
-                     s->ne, s->ecoord, s->eflags, s->eface, w->Ablk, w->ea, w->b, w->dinv);
+                     s->ne, s->ecoord, s->eflags, s->eface, w->Ablk, s->has_bnd ? s->ek : nullptr, w->ea, w->b,
+                     w->dinv);
   hipLaunchKernelGGL(k_sqrt_vec, dim3((unsigned)((w->n + 255) / 256)), dim3(256), 0, s->stream, w->n, w->dinv, w->q);
   return check_hip(hipGetLastError(), "coupled Newton-step assembly");
 }
@@ -1281,7 +1288,8 @@ cr_status run_coupled_export(cr_system* s, int64_t* rowptr, int32_t* col, double
   if (st != CR_OK) return st;
   const int d = s->d, d1 = d + 1;
   const int64_t nf = s->nf, ne = s->ne, nu = nf * d;
-  std::vector<double> Aval((size_t)(2 * d + 1) * nf), an((size_t)d * nf), ea((size_t)d1 * d * ne), b((size_t)nf * d);
+  std::vector<double> Aval((size_t)(2 * d + 1) * nf), an((size_t)d * nf), ea((size_t)d1 * d * ne),
+      b((size_t)nf * d + ne);
   std::vector<int32_t> cols((size_t)2 * d * nf);
   auto get = [&](void* dst, const void* src, size_t bytes) {
     if (st == CR_OK) st = check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream), "export coupled");
@@ -1326,7 +1334,7 @@ cr_status run_coupled_export(cr_system* s, int64_t* rowptr, int32_t* col, double
         if (fcan < 0) continue;
         for (int i = 0; i < d; ++i) row.emplace_back((int32_t)(fcan * d + i), -ea[(size_t)(j * d + i) * ne + k]);
       }
-      emit(pcol(c), 0.0);
+      emit(pcol(c), b[(size_t)nu + k]);  // e_K (boundary data), else 0
     }
   };
   // count first: the caller's buffers hold coupled_nnz entries

@@ -138,11 +138,15 @@ __device__ __forceinline__ void load_stokes_pack(const double* __restrict__ pack
 
 // R_K (eq. defrhs plus the lumped-mass transient term) and s_K from the factors.
 // (R_K)_{j,i} = a_j^(i) fbar.(x_sigma_j - x_K) with x_sigma_j - x_K = (x_K - x_j)/d.
+// With boundary data the columns of the exterior faces of S_K (stiffness only,
+// the lumped mass is diagonal) times the data leave the interior rows, and
+// e_K = a . g becomes the right-hand side of the divergence row.
 template <int D>
 __device__ __forceinline__ void stokes_rhs(const Geo<D>& g, uint32_t fl, const StokesFactors<D>& F,
                                            const double* __restrict__ fbar, const double* __restrict__ uprev,
-                                           const int32_t* __restrict__ eface, double mu, int64_t ne, int64_t k,
-                                           double* __restrict__ RK, double* __restrict__ sK, int32_t* err) {
+                                           const int32_t* __restrict__ eface, double mu, double nu, const Bnd& bnd,
+                                           int64_t ne, int64_t k, double* __restrict__ RK, double* __restrict__ sK,
+                                           int32_t* err) {
   constexpr int N = D + 1;
   double fb[D];
   bool fin = true;
@@ -173,12 +177,34 @@ __device__ __forceinline__ void stokes_rhs(const Geo<D>& g, uint32_t fl, const S
     }
   }
   if (!fin) report(err, ERR_NONFINITE, k);
+  double ediv = 0.0;
+  if (bnd.ebf != nullptr) {
+    double Gb[N][D];
+    load_bnd<D>(bnd, fl, ne, k, Gb);
+    const double iv = nu / g.vol;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) ediv += g.a[l][i] * Gb[l][i];
+      if (interior(fl, l)) continue;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (!interior(fl, j)) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) s += g.a[j][q] * g.a[l][q];
+#pragma unroll
+        for (int i = 0; i < D; ++i) R[j][i] -= iv * s * Gb[l][i];
+      }
+    }
+    if (bnd.ek != nullptr) bnd.ek[k] = ediv;
+  }
   double vr = 0.0;
 #pragma unroll
   for (int j = 0; j < N; ++j)
 #pragma unroll
     for (int i = 0; i < D; ++i) vr += F.V[j][i] * R[j][i];
-  vr *= F.invB;
+  vr = (vr - ediv) * F.invB;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     double c = csign(fl, j);
@@ -207,7 +233,7 @@ __global__ void __launch_bounds__(BS) k_elim_stokes(int64_t ne, const double* __
                                                     const double* __restrict__ lam,
                                                     const double* __restrict__ fbar,
                                                     const double* __restrict__ uprev, double mu, double nu,
-                                                    double* __restrict__ pack, double* __restrict__ RK,
+                                                    Bnd bnd, double* __restrict__ pack, double* __restrict__ RK,
                                                     double* __restrict__ sK, int32_t* err) {
   constexpr int N = D + 1;
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -273,7 +299,7 @@ __global__ void __launch_bounds__(BS) k_elim_stokes(int64_t ne, const double* __
 #pragma unroll
     for (int i = 0; i < D; ++i) pack[(int64_t)(StokesPack<D>::NS + j * D + i) * ne + k] = F.V[j][i];
   pack[(int64_t)(StokesPack<D>::SIZE - 1) * ne + k] = F.invB;
-  stokes_rhs<D>(g, fl, F, fbar, uprev, eface, mu, ne, k, RK, sK, err);
+  stokes_rhs<D>(g, fl, F, fbar, uprev, eface, mu, nu, bnd, ne, k, RK, sK, err);
 }
 
 // a6: new right-hand side from stored factors (same G).
@@ -282,7 +308,7 @@ __global__ void __launch_bounds__(BS) k_rhs_stokes(int64_t ne, const double* __r
                                                    const uint32_t* __restrict__ eflags,
                                                    const int32_t* __restrict__ eface,
                                                    const double* __restrict__ fbar,
-                                                   const double* __restrict__ uprev, double mu,
+                                                   const double* __restrict__ uprev, double mu, double nu, Bnd bnd,
                                                    const double* __restrict__ pack, double* __restrict__ RK,
                                                    double* __restrict__ sK, int32_t* err) {
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -291,7 +317,7 @@ __global__ void __launch_bounds__(BS) k_rhs_stokes(int64_t ne, const double* __r
   load_geometry<D>(ecoord, ne, k, g);
   StokesFactors<D> F;
   load_stokes_pack<D>(pack, ne, k, F);
-  stokes_rhs<D>(g, eflags[k], F, fbar, uprev, eface, mu, ne, k, RK, sK, err);
+  stokes_rhs<D>(g, eflags[k], F, fbar, uprev, eface, mu, nu, bnd, ne, k, RK, sK, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,13 +384,14 @@ template <int D, class M>
 __device__ __forceinline__ void ns_lambda_elem(int64_t ne, int64_t k, const double* __restrict__ ecoord,
                                                uint32_t fl, const int32_t* __restrict__ eface,
                                                const double* __restrict__ ulin, double mu, double nu, double lscale,
-                                               const M& A, double* __restrict__ lam) {
+                                               const Bnd& bnd, const M& A, double* __restrict__ lam) {
   constexpr int NU = NsPack<D>::NU;
   Geo<D> g;
   load_geometry<D>(ecoord, ne, k, g);
-  double Ub[D + 1][D], Nuu[D + 1][D];
-  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
-  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  double Ub[D + 1][D], Nuu[D + 1][D], Gb[D + 1][D], Rb[D + 1][D];
+  load_bnd<D>(bnd, fl, ne, k, Gb);
+  load_ubar<D>(ulin, eface, fl, ne, k, Gb, Ub);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu, Gb, Rb);
   double mx = 0.0;
 #pragma unroll
   for (int r = 0; r < NU; ++r) {
@@ -380,7 +407,7 @@ __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __re
                                                   const uint32_t* __restrict__ eflags,
                                                   const int32_t* __restrict__ eface,
                                                   const double* __restrict__ ulin, double mu, double nu,
-                                                  double lscale, double* __restrict__ lam) {
+                                                  double lscale, Bnd bnd, double* __restrict__ lam) {
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (k >= ne) return;
   const uint32_t fl = eflags[k];
@@ -389,7 +416,7 @@ __global__ void __launch_bounds__(BS) k_ns_lambda(int64_t ne, const double* __re
     return;
   }
   double A[6][6];
-  ns_lambda_elem<2>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, RegMat<6>{A}, lam);
+  ns_lambda_elem<2>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, bnd, RegMat<6>{A}, lam);
 }
 
 // threads per block of the 3D Newton-step element kernels (LDS: 144 doubles per thread)
@@ -400,7 +427,7 @@ __global__ void __launch_bounds__(BS_NS3) k_ns_lambda3(int64_t ne, const double*
                                                        const uint32_t* __restrict__ eflags,
                                                        const int32_t* __restrict__ eface,
                                                        const double* __restrict__ ulin, double mu, double nu,
-                                                       double lscale, double* __restrict__ lam) {
+                                                       double lscale, Bnd bnd, double* __restrict__ lam) {
   extern __shared__ double lds_ns[];
   int64_t k = (int64_t)blockIdx.x * BS_NS3 + threadIdx.x;
   if (k >= ne) return;
@@ -409,7 +436,7 @@ __global__ void __launch_bounds__(BS_NS3) k_ns_lambda3(int64_t ne, const double*
     lam[k] = 0.0;
     return;
   }
-  ns_lambda_elem<3>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, LdsMat<12>{lds_ns + threadIdx.x, BS_NS3},
+  ns_lambda_elem<3>(ne, k, ecoord, fl, eface, ulin, mu, nu, lscale, bnd, LdsMat<12>{lds_ns + threadIdx.x, BS_NS3},
                     lam);
 }
 
@@ -473,7 +500,7 @@ __global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __rest
                                                 const int32_t* __restrict__ eface,
                                                 const int32_t* __restrict__ enb, const double* __restrict__ lam,
                                                 const double* __restrict__ fbar, const double* __restrict__ uprev,
-                                                const double* __restrict__ ulin, double mu, double nu,
+                                                const double* __restrict__ ulin, double mu, double nu, Bnd bnd,
                                                 double* __restrict__ pack, double* __restrict__ RK,
                                                 double* __restrict__ sK, int32_t* err) {
   int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -481,12 +508,13 @@ __global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __rest
   Geo<2> g;
   load_geometry<2>(ecoord, ne, k, g);
   const uint32_t fl = eflags[k];
-  double Ub[3][2], A[6][6], Nuu[3][2];
-  load_ubar<2>(ulin, eface, fl, ne, k, Ub);
+  double Ub[3][2], A[6][6], Nuu[3][2], Gb[3][2], Rb[3][2];
+  load_bnd<2>(bnd, fl, ne, k, Gb);
+  load_ubar<2>(ulin, eface, fl, ne, k, Gb, Ub);
   bool fin = true;
 #pragma unroll
   for (int j = 0; j < 3; ++j) fin = fin && isfinite(Ub[j][0]) && isfinite(Ub[j][1]);
-  ns_local<2>(g, fl, Ub, mu, nu, RegMat<6>{A}, Nuu);
+  ns_local<2>(g, fl, Ub, mu, nu, RegMat<6>{A}, Nuu, Gb, Rb);
   if (lam != nullptr) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -542,16 +570,23 @@ __global__ void __launch_bounds__(BS) k_elim_ns(int64_t ne, const double* __rest
     int f = in ? eface[j * ne + k] : 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      double rr = g.a[j][i] * proj + Nuu[j][i];
+      double rr = g.a[j][i] * proj + Nuu[j][i] + Rb[j][i];
       if (uprev != nullptr && in) rr += m * uprev[(int64_t)f * 2 + i];
       R[j * 2 + i] = in ? rr : 0.0;
     }
   }
   if (!fin) report(err, ERR_NONFINITE, k);
+  // divergence right-hand side of the boundary data: e_K = -D_K[bnd] . g = a . g
+  double ediv = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) ediv += g.a[j][i] * Gb[j][i];
+  if (bnd.ek != nullptr) bnd.ek[k] = ediv;
   double rR = 0.0;
 #pragma unroll
   for (int a = 0; a < 6; ++a) rR += F.r[a] * R[a];
-  rR *= F.invB;
+  rR = (rR - ediv) * F.invB;
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     double t = 0.0;
@@ -582,7 +617,7 @@ __global__ void __launch_bounds__(BS_NS3) k_elim_ns3(int64_t ne, const double* _
                                                      const double* __restrict__ fbar,
                                                      const double* __restrict__ uprev,
                                                      const double* __restrict__ ulin, double mu, double nu,
-                                                     double* __restrict__ pack, double* __restrict__ RK,
+                                                     Bnd bnd, double* __restrict__ pack, double* __restrict__ RK,
                                                      double* __restrict__ sK, int32_t* err) {
   constexpr int D = 3, N = 4, NU = 12;
   extern __shared__ double lds_ns[];
@@ -592,14 +627,15 @@ __global__ void __launch_bounds__(BS_NS3) k_elim_ns3(int64_t ne, const double* _
   Geo<D> g;
   load_geometry<D>(ecoord, ne, k, g);
   const uint32_t fl = eflags[k];
-  double Ub[N][D], Nuu[N][D];
-  load_ubar<D>(ulin, eface, fl, ne, k, Ub);
+  double Ub[N][D], Nuu[N][D], Gb[N][D], Rb[N][D];
+  load_bnd<D>(bnd, fl, ne, k, Gb);
+  load_ubar<D>(ulin, eface, fl, ne, k, Gb, Ub);
   bool fin = true;
 #pragma unroll
   for (int j = 0; j < N; ++j)
 #pragma unroll
     for (int i = 0; i < D; ++i) fin = fin && isfinite(Ub[j][i]);
-  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu);
+  ns_local<D>(g, fl, Ub, mu, nu, A, Nuu, Gb, Rb);
   if (lam != nullptr) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -660,16 +696,22 @@ __global__ void __launch_bounds__(BS_NS3) k_elim_ns3(int64_t ne, const double* _
     int f = in ? eface[j * ne + k] : 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      double rr = g.a[j][i] * proj + Nuu[j][i];
+      double rr = g.a[j][i] * proj + Nuu[j][i] + Rb[j][i];
       if (uprev != nullptr && in) rr += m * uprev[(int64_t)f * D + i];
       R[j * D + i] = in ? rr : 0.0;
     }
   }
   if (!fin) report(err, ERR_NONFINITE, k);
+  double ediv = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < D; ++i) ediv += g.a[j][i] * Gb[j][i];
+  if (bnd.ek != nullptr) bnd.ek[k] = ediv;
   double rR = 0.0;
 #pragma unroll
   for (int a = 0; a < NU; ++a) rR += rv[a] * R[a];
-  rR *= invB;
+  rR = (rR - ediv) * invB;
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
     double t = 0.0;
@@ -1152,7 +1194,8 @@ __global__ void __launch_bounds__(BS) k_face_rhs(int64_t nf, int64_t ne, const i
 template <int D, bool NSK>
 __device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t fl, const double* __restrict__ y,
                                                 const double* __restrict__ dsq, const double* __restrict__ pack,
-                                                const double* __restrict__ RK, const int32_t* __restrict__ eface,
+                                                const double* __restrict__ RK, const double* __restrict__ ek,
+                                                const int32_t* __restrict__ eface,
                                                 const int32_t* __restrict__ fcanon, double (&u)[D + 1][D],
                                                 double& p, int (&fc)[D + 1]) {
   constexpr int N = D + 1;
@@ -1177,6 +1220,7 @@ __device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t 
     for (int j = 0; j < N; ++j)
 #pragma unroll
       for (int i = 0; i < D; ++i) p += F.V[j][i] * rhs[j][i];
+    if (ek != nullptr) p -= ek[k];
     p *= F.invB;
 #pragma unroll
     for (int j = 0; j < N; ++j)
@@ -1192,6 +1236,7 @@ __device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t 
     constexpr int NU = NsPack<D>::NU;
 #pragma unroll
     for (int a = 0; a < NU; ++a) p += pack[(int64_t)(NU * NU + NU + a) * ne + k] * rhs[a / D][a % D];
+    if (ek != nullptr) p -= ek[k];
     p *= pack[(int64_t)(NU * NU + 2 * NU) * ne + k];
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
@@ -1206,7 +1251,8 @@ __device__ __forceinline__ void recover_element(int64_t ne, int64_t k, uint32_t 
 template <int D, bool NSK>
 __global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __restrict__ y,
                                                 const double* __restrict__ dsq, const double* __restrict__ pack,
-                                                const double* __restrict__ RK, const int32_t* __restrict__ eface,
+                                                const double* __restrict__ RK, const double* __restrict__ ek,
+                                                const int32_t* __restrict__ eface,
                                                 const uint32_t* __restrict__ eflags,
                                                 const int32_t* __restrict__ ecaller,
                                                 const int32_t* __restrict__ fcanon, double* __restrict__ U,
@@ -1217,7 +1263,7 @@ __global__ void __launch_bounds__(BS) k_recover(int64_t ne, const double* __rest
   const uint32_t fl = eflags[k];
   double u[N][D], p;
   int fc[N];
-  recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, eface, fcanon, u, p, fc);
+  recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, ek, eface, fcanon, u, p, fc);
   P[ecaller[k]] = p;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -1238,6 +1284,7 @@ __global__ void __launch_bounds__(BS) k_recover_mismatch(int64_t ne, const doubl
                                                          const double* __restrict__ dsq,
                                                          const double* __restrict__ pack,
                                                          const double* __restrict__ RK,
+                                                         const double* __restrict__ ek,
                                                          const int32_t* __restrict__ eface,
                                                          const uint32_t* __restrict__ eflags,
                                                          const int32_t* __restrict__ fcanon,
@@ -1250,7 +1297,7 @@ __global__ void __launch_bounds__(BS) k_recover_mismatch(int64_t ne, const doubl
     const uint32_t fl = eflags[k];
     double u[N][D], p;
     int fc[N];
-    recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, eface, fcanon, u, p, fc);
+    recover_element<D, NSK>(ne, k, fl, y, dsq, pack, RK, ek, eface, fcanon, u, p, fc);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       if (fc[j] < 0 || csign(fl, j) > 0.0) continue;
@@ -1409,13 +1456,14 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
   const double* up = u_prev ? s->uprev : nullptr;
   const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
   const double lscale = s->params.lambda_scale > 0.0 ? s->params.lambda_scale : 2.0;
+  const Bnd bnd{s->has_bnd ? s->ebf : nullptr, s->gbnd, s->has_bnd ? s->ek : nullptr};
   if (ns && d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_ns_lambda, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->ulin,
-                         s->params.mu, s->params.nu, lscale, s->lam);
+                         s->params.mu, s->params.nu, lscale, bnd, s->lam);
     hipLaunchKernelGGL(k_elim_ns, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->enb,
-                       steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack, s->RK,
-                       s->sK, s->err);
+                       steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, bnd, s->pack,
+                       s->RK, s->sK, s->err);
     hipLaunchKernelGGL((k_face_assemble<2, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
@@ -1430,10 +1478,10 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     const unsigned g3 = nblocks(s->ne, BS_NS3);
     if (steady)
       hipLaunchKernelGGL(k_ns_lambda3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags,
-                         s->eface, s->ulin, s->params.mu, s->params.nu, lscale, s->lam);
+                         s->eface, s->ulin, s->params.mu, s->params.nu, lscale, bnd, s->lam);
     hipLaunchKernelGGL(k_elim_ns3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
-                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, s->pack,
-                       s->RK, s->sK, s->err);
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, bnd,
+                       s->pack, s->RK, s->sK, s->err);
     hipLaunchKernelGGL((k_face_assemble<3, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
@@ -1442,8 +1490,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
       hipLaunchKernelGGL(k_stokes_lambda<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
                          s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
-                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
-                       s->sK, s->err);
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack,
+                       s->RK, s->sK, s->err);
     hipLaunchKernelGGL((k_face_assemble<2, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
@@ -1455,8 +1503,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
       hipLaunchKernelGGL(k_stokes_lambda<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
                          s->params.mu, s->params.nu, lscale, s->lam);
     hipLaunchKernelGGL(k_elim_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
-                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, s->pack, s->RK,
-                       s->sK, s->err);
+                       s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack,
+                       s->RK, s->sK, s->err);
     hipLaunchKernelGGL((k_face_assemble<3, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
                        s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
     hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
@@ -1531,14 +1579,15 @@ cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_pre
   if (st != CR_OK) return st;
   const double* up = u_prev ? s->uprev : nullptr;
   const unsigned ge = nblocks(s->ne, BS), gf = nblocks(s->nf, BS);
+  const Bnd bnd{s->has_bnd ? s->ebf : nullptr, s->gbnd, s->has_bnd ? s->ek : nullptr};
   if (d == 2) {
     hipLaunchKernelGGL(k_rhs_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
-                       s->fbar, up, s->params.mu, s->pack, s->RK, s->sK, s->err);
+                       s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack, s->RK, s->sK, s->err);
     hipLaunchKernelGGL(k_face_rhs<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->sK, s->dsq,
                        s->bs);
   } else {
     hipLaunchKernelGGL(k_rhs_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
-                       s->fbar, up, s->params.mu, s->pack, s->RK, s->sK, s->err);
+                       s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack, s->RK, s->sK, s->err);
     hipLaunchKernelGGL(k_face_rhs<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc, s->sK, s->dsq,
                        s->bs);
   }
@@ -1567,16 +1616,16 @@ cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {
   const unsigned ge = nblocks(s->ne, BS);
   if (ns && d == 2)
     hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
   else if (ns)
     hipLaunchKernelGGL((k_recover<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
   else if (d == 2)
     hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
   else
     hipLaunchKernelGGL((k_recover<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, Uj);
   if (jump) {
     const int64_t n = s->nf * d;
     hipLaunchKernelGGL(k_sqdiff_partial, dim3(1024), dim3(256), 0, s->stream, n, U, Uj, Uj + n);
@@ -1637,29 +1686,29 @@ cr_status run_recover_noalloc(cr_system* s, double* U, double* P, double* jump) 
   }
   if (ns && d == 2)
     hipLaunchKernelGGL((k_recover<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   else if (ns)
     hipLaunchKernelGGL((k_recover<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   else if (d == 2)
     hipLaunchKernelGGL((k_recover<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   else
     hipLaunchKernelGGL((k_recover<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq, s->pack, s->RK,
-                       s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
+                       s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->ecaller, s->fcanon, U, P, nullptr);
   if (jump) {
     if (ns && d == 2)
       hipLaunchKernelGGL((k_recover_mismatch<2, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
-                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+                         s->pack, s->RK, s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->fcanon, U, part);
     else if (ns)
       hipLaunchKernelGGL((k_recover_mismatch<3, true>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
-                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+                         s->pack, s->RK, s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->fcanon, U, part);
     else if (d == 2)
       hipLaunchKernelGGL((k_recover_mismatch<2, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
-                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+                         s->pack, s->RK, s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->fcanon, U, part);
     else
       hipLaunchKernelGGL((k_recover_mismatch<3, false>), dim3(ge), dim3(BS), 0, s->stream, s->ne, s->y, s->dsq,
-                         s->pack, s->RK, s->eface, s->eflags, s->fcanon, U, part);
+                         s->pack, s->RK, s->has_bnd ? s->ek : nullptr, s->eface, s->eflags, s->fcanon, U, part);
     hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s->stream, (int)ge, part, jump);
   }
   return check_hip(hipGetLastError(), "recover launch");

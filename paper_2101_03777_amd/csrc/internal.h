@@ -29,6 +29,10 @@ struct Topology {
   std::vector<int32_t> face_elem;      // [nf][2] caller element ids, K < L
   std::vector<int8_t> face_loc;        // [nf][2] local face index in K and in L
   std::vector<uint8_t> m1;             // [ne] element partition M1 (mu == 0 only)
+  // exterior faces (one element), lexicographic in their sorted vertex ids
+  int64_t nbf = 0;
+  std::vector<int32_t> bface_vertices; // [nbf][d]
+  std::vector<int32_t> elem_bface;     // [ne][d+1] exterior face of local face j, -1 interior
   // renumbering
   std::vector<int32_t> face_perm;      // canonical -> internal
   std::vector<int32_t> face_iperm;     // internal -> canonical
@@ -125,6 +129,13 @@ struct cr_system {
   double* uprev = nullptr;     // [nf*d] internal face order
   double* ulin = nullptr;      // [nf*d] internal face order
   int32_t* err = nullptr;      // [4] device error word, first element
+  // non-homogeneous Dirichlet data (cr_set_boundary): exterior face of each
+  // local face, the data in canonical exterior order, and the right-hand side
+  // e_K of the divergence rows
+  bool has_bnd = false;
+  int32_t* ebf = nullptr;      // [d+1][ne] internal element order, -1 interior
+  double* gbnd = nullptr;      // [nbf*d]
+  double* ek = nullptr;        // [ne]
   double* ujump = nullptr;     // [nf*d + 1024] non-owner copies for the mismatch diagnostic
   int npack = 0;
   bool eliminated = false;

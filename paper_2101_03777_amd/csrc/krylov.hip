@@ -1671,7 +1671,10 @@ CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
 // Operator form of a solve: the element factors (built for transient Stokes)
 // serve CG; the assembled rows serve BiCGStab and explicit requests.
 cr_status resolve_op(const cr_system* s, const cr_solve_opts* o, int& op) {
-  const bool have = s->efo64 != nullptr && o->method == CR_PCG;
+  // the element form carries K0's divergence row too (gauge-shifted system),
+  // which holds only for homogeneous data: with boundary data CG applies the
+  // assembled rows
+  const bool have = s->efo64 != nullptr && o->method == CR_PCG && !s->has_bnd;
   switch (o->operator_form) {
     case CR_OP_AUTO:
       op = have ? 1 : 0;
@@ -1681,7 +1684,7 @@ cr_status resolve_op(const cr_system* s, const cr_solve_opts* o, int& op) {
       return CR_OK;
     case CR_OP_ELEMENT:
       if (!have) {
-        set_error("the element-factor operator needs CG on a transient Stokes system");
+        set_error("the element-factor operator needs CG on a transient Stokes system without boundary data");
         return CR_E_INVAL;
       }
       op = 1;

@@ -195,6 +195,7 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
   std::sort(lf.begin(), lf.end(), key_less);
 
   t.elem_face.assign((size_t)ne * d1, -1);
+  t.elem_bface.assign((size_t)ne * d1, -1);
   int64_t nf = 0;
   for (size_t i = 0; i < lf.size();) {
     size_t j = i + 1;
@@ -202,6 +203,12 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     if (j - i > 2) {
       set_error("a face is shared by %zu elements (element %d)", j - i, lf[i].elem);
       return CR_E_MESH;
+    }
+    if (j - i == 1) {
+      // exterior face: canonical exterior id in the same lexicographic key order
+      for (int a = 0; a < d; ++a) t.bface_vertices.push_back((int32_t)lf[i].v[a]);
+      t.elem_bface[(size_t)lf[i].elem * d1 + lf[i].loc] = (int32_t)t.nbf;
+      ++t.nbf;
     }
     if (j - i == 2) {
       // interior face: canonical id in lexicographic key order; K < L by caller id

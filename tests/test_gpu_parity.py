@@ -459,3 +459,101 @@ def test_precond_options(gpu):
     assert relerr(s.export_W(), Wa) <= 1e-9
     assert a["iters"] < b["iters"]
     s.close()
+
+
+# --------------------------------------------------------------------------
+# Non-homogeneous Dirichlet data (cr_set_boundary)
+# --------------------------------------------------------------------------
+
+def make_bnd_case(name):
+    """(coords, elems, mu, nu, fbar, ulin, g, problem, method) with random data on the exterior faces."""
+    dim = 3 if "3d" in name else 2
+    if dim == 2:
+        coords, elems = synth.square_mesh(10, jitter=0.2, seed=17)
+    else:
+        coords, elems = synth.cube_mesh(3)
+    rng = np.random.default_rng(len(name))
+    g = rng.normal(size=(len(wl.exterior_face_list(elems)), dim))
+    f = rng.normal(size=(len(elems), dim))
+    nf = len(wl.interior_face_list(elems))
+    if name.startswith("bnd_stokes"):
+        return coords, elems, 80.0, 1.0, f, None, g, "stokes", "pcg"
+    if name == "bnd_steady2d":
+        return coords, elems, 0.0, 1.0, f, None, g, "stokes", "minres"
+    return coords, elems, 0.0, 0.05, f, 0.5 * rng.normal(size=(nf, dim)), g, "ns", "bicgstab2"
+
+
+BND_CASES = ["bnd_stokes2d", "bnd_stokes3d", "bnd_steady2d", "bnd_ns2d", "bnd_ns3d"]
+
+
+def bnd_system(gpu, c):
+    coords, elems, mu, nu, f, ulin, g, prob, method = c
+    s = gpu.System(coords, elems, mu, nu, problem=prob)
+    assert (s.boundary_faces() == wl.exterior_face_list(elems)).all()
+    s.set_boundary(g)
+    s.eliminate(dev(f), None, None if ulin is None else dev(ulin))
+    return s
+
+
+@pytest.mark.parametrize("name", BND_CASES)
+def test_boundary_data_parity(gpu, name):
+    """With boundary data: S element-wise against the oracle's elimination, and
+    the solution U, P against the oracle's coupled solve (FP64, 2-norm and max-norm)."""
+    c = make_bnd_case(name)
+    coords, elems, mu, nu, f, ulin, g, prob, method = c
+    print(f"case {name}", flush=True)
+    P = cr.make_problem(coords, elems, mu, nu, f, ulin=ulin, gbnd=g)
+    U_o, P_o = cr.solve_coupled(P)
+    H = cr.eliminate(P)
+    s = bnd_system(gpu, c)
+    G, S = s.export_G()
+    assert np.abs(S - H.S).max() <= 1e-10 * np.abs(H.S).max()
+    info = s.solve(method, "fp64", tol=1e-13, maxit=200000)
+    assert info["rel_residual"] <= 1e-13
+    U, Pk = s.recover()
+    torch.cuda.synchronize()
+    assert_close(U.cpu().numpy(), U_o, 1e-10)
+    assert_close(Pk.cpu().numpy(), P_o, 1e-10)
+    # the coupled baseline with the same data
+    Uc, Pc, ci = s.coupled_solve(tol=1e-11, maxit=200000)
+    torch.cuda.synchronize()
+    assert ci["status"] == 0
+    assert_close(Uc.cpu().numpy(), U_o, 1e-9)
+    assert_close(Pc.cpu().numpy(), P_o, 1e-9)
+    # the element form is not available with boundary data; homogeneous data again restores it
+    if name == "bnd_stokes2d":
+        with pytest.raises(gpu.CRError, match="without boundary data"):
+            s.solve("pcg", "fp64", tol=1e-12, operator="element")
+        s.set_boundary(None)
+        s.eliminate(dev(f))
+        s.solve("pcg", "fp64", tol=1e-12, operator="element")
+    s.close()
+
+
+def test_boundary_data_time_steps(gpu):
+    """Backward Euler steps with boundary data changing in time (cr_set_boundary
+    then cr_update_rhs with the previous U), against the oracle's chain."""
+    coords, elems = synth.square_mesh(12, jitter=0.2, seed=23)
+    from synth.fields import GreenTaylor2D, face_means
+    gt = GreenTaylor2D(amp=1.0, nu=1.0)
+    bf = wl.exterior_face_list(elems)
+    dt, mu = 0.01, 100.0
+    f0 = np.zeros((len(elems), 2))
+    s = gpu.System(coords, elems, mu, 1.0)
+    up_o = None
+    U = None
+    for n in range(1, 4):
+        g = face_means(coords, bf, lambda x: gt.u(x, n * dt))
+        s.set_boundary(g)
+        if n == 1:
+            s.eliminate(dev(f0))
+        else:
+            s.update_rhs(dev(f0), U)
+        s.solve("pcg", "fp64", tol=1e-13, warm_start=n > 1)
+        U, Pk = s.recover()
+        P = cr.make_problem(coords, elems, mu, 1.0, f0, u_prev=up_o, gbnd=g)
+        U_o, P_o = cr.solve_coupled(P)
+        assert_close(U.cpu().numpy(), U_o, 1e-10)
+        assert_close(Pk.cpu().numpy(), P_o, 1e-10)
+        up_o = U_o
+    s.close()
