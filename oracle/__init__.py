@@ -24,6 +24,7 @@ Modules:
   brute    the three-field system of eq. syslinhyb assembled densely (tiny meshes)
   norms    broken L2 / H1 error norms against a manufactured solution
   krylov   plain FP64 preconditioned CG on G (for sizes a direct solve cannot take)
+  newton   Newton iterations of the nonlinear scheme (each step a coupled direct solve)
 
 Functions whose result the tests cannot tie to the paper or to mathematics
 independently of the oracle itself say "parity unpinned" in their docstring.

@@ -340,46 +340,62 @@ def face_means(coords, faces, fn, n: int = 5):
 
 
 class GreenTaylor2D:
-    """The Green-Taylor vortex on the unit square, an exact solution of the
-    Navier-Stokes equations with zero force for any viscosity nu:
-      u = amp (-cos(pi x) sin(pi y), sin(pi x) cos(pi y)) exp(-2 pi^2 nu t),
-      p = -amp^2 (cos(2 pi x) + cos(2 pi y)) / 4 exp(-4 pi^2 nu t).
-    Its velocity does not vanish on the boundary of the square (non-homogeneous
-    Dirichlet data, zero net flux).  Also the force that makes (u, p) a
-    solution of the Stokes problem mu u - nu Lap u + grad p = f at time t."""
+    """The Green-Taylor vortex of the paper's 2D convergence test (Section 4.1,
+    eqs. gretayvel and gretaypre), an exact solution of the Navier-Stokes
+    equations with zero force and viscosity nu:
+      u = amp (-cos(k (x + 1/4)) sin(k (y + 1/2)), sin(k (x + 1/4)) cos(k (y + 1/2))) exp(-2 k^2 nu t),
+      p = -amp^2 (cos(2k (x + 1/4)) + cos(2k (y + 1/2))) / 4 exp(-4 k^2 nu t),
+    with k = 2 pi (the paper: amp = Re = 100, nu = 1).  Its velocity does not
+    vanish on the boundary of the unit square (non-homogeneous Dirichlet data,
+    zero net flux).  u.grad u + grad p = 0, so (u, p) also solves the steady
+    problem -nu Lap u + u.grad u + grad p = 2 k^2 nu u, and the Stokes problem
+    mu u - nu Lap u + grad p = f with f = (mu + 2 k^2 nu) u + grad p."""
 
-    def __init__(self, amp: float = 1.0, nu: float = 1.0):
+    def __init__(self, amp: float = 1.0, nu: float = 1.0, k: float = 2.0 * math.pi):
         self.amp = float(amp)
         self.nu = float(nu)
+        self.k = float(k)
 
-    def _decay(self, t, k=2):
-        return math.exp(-k * math.pi ** 2 * self.nu * t)
+    def _decay(self, t, m=2):
+        return math.exp(-m * self.k ** 2 * self.nu * t)
+
+    def _xy(self, pts):
+        return self.k * (pts[:, 0] + 0.25), self.k * (pts[:, 1] + 0.5)
 
     def u(self, pts, t=0.0):
-        x, y = pts[:, 0], pts[:, 1]
+        X, Y = self._xy(pts)
         e = self.amp * self._decay(t)
-        return np.stack([-np.cos(np.pi * x) * np.sin(np.pi * y), np.sin(np.pi * x) * np.cos(np.pi * y)], axis=1) * e
+        return np.stack([-np.cos(X) * np.sin(Y), np.sin(X) * np.cos(Y)], axis=1) * e
 
     def grad_u(self, pts, t=0.0):
         """[m, 2 (component), 2 (derivative)]"""
-        x, y = pts[:, 0], pts[:, 1]
-        e = self.amp * self._decay(t) * np.pi
-        g = np.empty((len(x), 2, 2))
-        g[:, 0, 0] = np.sin(np.pi * x) * np.sin(np.pi * y) * e
-        g[:, 0, 1] = -np.cos(np.pi * x) * np.cos(np.pi * y) * e
-        g[:, 1, 0] = np.cos(np.pi * x) * np.cos(np.pi * y) * e
-        g[:, 1, 1] = -np.sin(np.pi * x) * np.sin(np.pi * y) * e
+        X, Y = self._xy(pts)
+        e = self.amp * self._decay(t) * self.k
+        g = np.empty((len(X), 2, 2))
+        g[:, 0, 0] = np.sin(X) * np.sin(Y) * e
+        g[:, 0, 1] = -np.cos(X) * np.cos(Y) * e
+        g[:, 1, 0] = np.cos(X) * np.cos(Y) * e
+        g[:, 1, 1] = -np.sin(X) * np.sin(Y) * e
         return g
 
     def p(self, pts, t=0.0):
-        x, y = pts[:, 0], pts[:, 1]
-        return -self.amp ** 2 * (np.cos(2 * np.pi * x) + np.cos(2 * np.pi * y)) / 4.0 * self._decay(t, 4)
+        X, Y = self._xy(pts)
+        return -self.amp ** 2 * (np.cos(2 * X) + np.cos(2 * Y)) / 4.0 * self._decay(t, 4)
+
+    def grad_p(self, pts, t=0.0):
+        X, Y = self._xy(pts)
+        c = self.amp ** 2 * self.k / 2.0 * self._decay(t, 4)
+        return np.stack([np.sin(2 * X), np.sin(2 * Y)], axis=1) * c
 
     def stokes_force(self, mu, t=0.0):
-        """f = mu u - nu Lap u + grad p at time t (Lap u = -2 pi^2 u)."""
+        """f = mu u - nu Lap u + grad p at time t (Lap u = -2 k^2 u)."""
         def fn(pts):
-            x, y = pts[:, 0], pts[:, 1]
-            gp = self.amp ** 2 * np.pi / 2.0 * self._decay(t, 4) * np.stack([np.sin(2 * np.pi * x),
-                                                                             np.sin(2 * np.pi * y)], axis=1)
-            return (mu + 2.0 * np.pi ** 2 * self.nu) * self.u(pts, t) + gp
+            return (mu + 2.0 * self.k ** 2 * self.nu) * self.u(pts, t) + self.grad_p(pts, t)
+        return fn
+
+    def steady_ns_force(self, t=0.0):
+        """f = -nu Lap u + u.grad u + grad p = 2 k^2 nu u (the convection and the
+        pressure gradient cancel)."""
+        def fn(pts):
+            return 2.0 * self.k ** 2 * self.nu * self.u(pts, t)
         return fn

@@ -507,3 +507,63 @@ def test_serving_against_oracle(gpu):
             assert_close(Us, Uo, 1e-9)
             assert_close(Ps, Po, 1e-9)
             u_prev = Uo
+
+
+# --------------------------------------------------------------------------
+# Newton iterations with boundary data (lid-driven cavity, Green-Taylor vortex)
+# --------------------------------------------------------------------------
+
+def _cavity(n):
+    coords, elems = synth.square_mesh(n)
+    bf = wl.exterior_face_list(elems)
+    g = np.zeros((len(bf), 2))
+    g[coords[bf].mean(axis=1)[:, 1] > 1.0 - 1e-12, 0] = 1.0
+    return coords, elems, g
+
+
+def test_newton_cavity_against_oracle(gpu):
+    """Lid-driven cavity, Re = 100, 8 x 8 x 2, Newton from rest: the GPU's
+    iterations (hybridised Newton steps, BiCGStab(2)) follow the oracle's
+    (coupled direct solves): same number of iterations, U and P within 1e-9."""
+    from oracle import newton as onewton
+    from paper_2101_03777_amd.newton import NewtonSolver
+    coords, elems, g = _cavity(8)
+    f = np.zeros((len(elems), 2))
+    Uo, Po, inc_o = onewton.newton(coords, elems, 0.0, 0.01, f, gbnd=g, tol=1e-10)
+    ns = NewtonSolver(coords, elems, 0.0, 0.01)
+    ns.set_boundary(g)
+    U, P, rec = ns.solve(f, tol=1e-10, lin_tol=1e-13)
+    print("oracle increments", inc_o, "gpu", rec, flush=True)
+    assert rec["converged"] and all(st == 0 for st in rec["linear_status"])
+    assert abs(len(rec["increments"]) - len(inc_o)) <= 1
+    assert_close(U.cpu().numpy(), Uo, 1e-9)
+    assert_close(P.cpu().numpy(), Po, 1e-9)
+    ns.close()
+
+
+def test_newton_green_taylor_time_steps_against_oracle(gpu):
+    """Backward-Euler steps of the Green-Taylor vortex (amplitude Re = 100,
+    nu = 1, Section 4.1) on 8 x 8 x 2 with its face means on the boundary at
+    each time, Newton at every step from the previous step: against the
+    oracle's chain of Newton solves, U and P within 1e-9 at every step."""
+    from oracle import newton as onewton
+    from paper_2101_03777_amd.newton import NewtonSolver
+    from synth.fields import GreenTaylor2D, face_means
+    gt = GreenTaylor2D(amp=100.0, nu=1.0)
+    coords, elems = synth.square_mesh(8)
+    bf = wl.exterior_face_list(elems)
+    fi = wl.interior_face_list(elems)
+    dt = 0.002 / 64.0
+    f = np.zeros((len(elems), 2))
+    u0 = gt.u(coords[fi].mean(axis=1), 0.0)
+    ns = NewtonSolver(coords, elems, 1.0 / dt, 1.0)
+    Ug, Uo = dev(u0), u0
+    for n in range(1, 4):
+        g = face_means(coords, bf, lambda x: gt.u(x, n * dt))
+        Uo, Po, inc_o = onewton.newton(coords, elems, 1.0 / dt, 1.0, f, gbnd=g, u_prev=Uo, u0=Uo, tol=1e-11)
+        ns.set_boundary(g)
+        Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-11, lin_tol=1e-13)
+        assert rec["converged"], rec
+        assert_close(Ug.cpu().numpy(), Uo, 1e-9)
+        assert_close(Pg.cpu().numpy(), Po, 1e-9)
+    ns.close()

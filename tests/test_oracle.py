@@ -759,3 +759,59 @@ def test_green_taylor_stokes_orders_with_boundary_data():
         errs.append(norms.errors(P.mesh, U, Pk, gt.u, gt.grad_u, gt.p, quad, gbnd=g))
     o = _orders(errs)
     assert o[-1]["l2u"] > 1.8 and 0.9 < o[-1]["h1u"] < 1.2 and o[-1]["l2p"] > 1.0, o
+
+
+# --------------------------------------------------------------------------
+# The Newton method on the nonlinear scheme (Section 3.1; Section 4 tests)
+# --------------------------------------------------------------------------
+
+def test_newton_steady_green_taylor_orders():
+    """The steady Navier-Stokes problem with the Green-Taylor vortex as exact
+    solution (force 2 k^2 nu u, the convection balanced by the pressure
+    gradient) and its face means on the boundary: Newton converges
+    quadratically (increments fall at least like the square of the previous
+    ones) to a solution whose nonlinear residual is at rounding level, and the
+    errors fall with the orders of Table tab0 (velocity L2 about 2, pressure
+    above 1)."""
+    from oracle import newton
+    from synth.fields import GreenTaylor2D, face_means
+    gt = GreenTaylor2D(amp=1.0, nu=0.1)
+    quad = synth.simplex_rule(2, 5)
+    errs = []
+    for n in (8, 16, 32):
+        coords, elems = synth.square_mesh(n)
+        fbar = synth.element_means(coords, elems, gt.steady_ns_force(), n=4)
+        g = face_means(coords, wl.exterior_face_list(elems), gt.u)
+        U, Pk, inc = newton.newton(coords, elems, 0.0, gt.nu, fbar, gbnd=g, tol=1e-12)
+        assert inc[-1] <= 1e-12 and len(inc) <= 8, inc
+        for a, b in zip(inc[1:-1], inc[2:]):
+            assert b <= max(10.0 * a * a, 1e-13), inc
+        res, div = newton.nonlinear_residual(coords, elems, 0.0, gt.nu, fbar, U, Pk, gbnd=g)
+        assert res < 1e-11, res
+        m = cr.build_mesh(coords, elems)
+        errs.append(norms.errors(m, U, Pk, gt.u, gt.grad_u, gt.p, quad, gbnd=g))
+    o = _orders(errs)
+    assert o[-1]["l2u"] > 1.8 and o[-1]["l2p"] > 1.0, o
+
+
+def test_newton_cavity_small():
+    """Lid-driven cavity (Section 4.3: velocity (1, 0) on the top side, zero on
+    the others) at Re = 100 on 8 x 8 x 2: Newton from rest converges, the
+    solution carries the lid's velocity into the cavity (a recirculation: the
+    horizontal velocity changes sign along the vertical centre line) and
+    is divergence-free on every element."""
+    from oracle import newton
+    coords, elems = synth.square_mesh(8)
+    bf = wl.exterior_face_list(elems)
+    ymid = coords[bf].mean(axis=1)[:, 1]
+    g = np.zeros((len(bf), 2))
+    g[ymid > 1.0 - 1e-12, 0] = 1.0
+    U, Pk, inc = newton.newton(coords, elems, 0.0, 0.01, np.zeros((len(elems), 2)), gbnd=g, tol=1e-10)
+    assert inc[-1] <= 1e-10 and len(inc) <= 12, inc
+    faces = wl.interior_face_list(elems)
+    xm = coords[faces].mean(axis=1)
+    centre = np.abs(xm[:, 0] - 0.5) < 0.07
+    ux = U[centre, 0]
+    assert ux.max() > 0.05 and ux.min() < -0.05
+    P = cr.make_problem(coords, elems, 0.0, 0.01, np.zeros((len(elems), 2)), ulin=U, gbnd=g)
+    assert np.abs(cr.divergence(P, U) - P.ediv())[np.arange(len(elems)) != 0].max() < 1e-12
