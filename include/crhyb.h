@@ -80,7 +80,7 @@ enum { CR_OP_AUTO = 0, CR_OP_ASSEMBLED = 1, CR_OP_ELEMENT = 2 };
  * correction M^-1 = I + Z E^-1 Z^t (one column per aggregate: the null vector
  * of the gauge-shifted G restricted to the aggregate's faces):
  * CR_PC_DEFAULT: Jacobi scaling, plus the coarse correction where the mesh has
- *   aggregates (transient Stokes meshes of at least 8192 elements in 2D, 4096 in 3D);
+ *   aggregates (transient Stokes meshes of at least 512 elements in 2D, 1024 in 3D);
  * CR_PC_JACOBI: Jacobi scaling only;
  * CR_PC_COARSE: the coarse correction is required: CR_E_INVAL where it does
  *   not exist (no aggregates, or another method or operator form). */
@@ -175,7 +175,8 @@ typedef struct {
   int32_t precision;   /* CR_FP64, or CR_FP32_IR: FP32 Krylov inside FP64 iterative refinement */
   double tol;          /* stop when ||S - G W||_2 <= tol ||S||_2, residual recomputed in FP64 */
   double inner_tol;    /* factor by which the recursive residual falls between FP64 residual
-                          replacements (reliable updates); <= 0: automatic (0.1 for FP32) */
+                          replacements (reliable updates); <= 0: automatic (0.1 for FP32
+                          iterations and for CG, none otherwise) */
   int32_t maxit;       /* cap on the total number of Krylov iterations */
   int32_t max_outer;   /* cap on refinement passes */
   int32_t check_every; /* iterations per convergence poll (rounded up to even); <= 0: automatic */

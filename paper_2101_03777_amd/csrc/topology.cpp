@@ -312,12 +312,20 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     }
     std::reverse(order.begin(), order.end());
     // Aggregates for the coarse correction: recursive coordinate bisection of
-    // the element centroids into nagg parts (a power of two; in 2D at least
-    // 2048 elements each and at most 256 parts, in 3D at least 1024 and at most
-    // MAX_AGG = 512: measured on 512x512x2 and 64^3x6; none below 4 parts),
-    // numbered in bisection order so that consecutive aggregates are
-    // neighbours.  A face belongs to the aggregate of its owner element (the
-    // lower caller id, C = +1).
+    // the element centroids into nagg parts, numbered in bisection order so
+    // that consecutive aggregates are neighbours.  nagg is a power of 4 in 2D
+    // and of 8 in 3D (bisection alternates the axes on a square or a cube, so
+    // the parts come out square or cubic: a power of two in between, with
+    // elongated parts, takes about as many CG iterations as the power below
+    // it), as many as the mesh has room for with at least 128 elements each,
+    // at most 256 in 2D and MAX_AGG = 512 in 3D (the dense coarse inverse is
+    // read at every iteration); none below 4 parts.  Smaller aggregates take
+    // fewer iterations (2D, mu = 1000: 64x64x2 657 -> 260 with 4 -> 64
+    // aggregates, 128x128x2 860 -> 439 with 16 -> 256; 3D 12^3 x 6: 340 -> 239
+    // with 8 -> 64); 128 elements keep at least half a face block in each
+    // aggregate, so that a face block of the solver touches at most 3 of them.
+    // A face belongs to the aggregate of its owner element (the lower caller
+    // id, C = +1).
     // With aggregates the element-form CG gathers its vectors element by
     // element, so the order is chosen for locality of those gathers rather
     // than for a narrow band: the bisection continues inside each aggregate
@@ -327,10 +335,11 @@ cr_status build_topology(const cr_mesh_desc* mesh, int renumber, bool need_m1, b
     // them, grouped by aggregate.  The two elements of most faces then fall in
     // the same workgroup pass, and the faces a wavefront gathers lie on few
     // cache lines.
+    const int agg_base = d == 3 ? 8 : 4;
     const int agg_cap = d == 3 ? MAX_AGG : 256;
-    const int64_t agg_min = d == 3 ? 1024 : 2048;
+    const int64_t agg_min = 128;
     int nagg = 1;
-    while (nagg < agg_cap && (int64_t)nagg * 2 * agg_min <= ne) nagg *= 2;
+    while (nagg * agg_base <= agg_cap && (int64_t)nagg * agg_base * agg_min <= ne) nagg *= agg_base;
     if (aggregate && nagg >= 4) {
       std::vector<double> cen((size_t)ne * d, 0.0);
       for (int64_t k = 0; k < ne; ++k)

@@ -328,8 +328,8 @@ def test_multistep_update_rhs_parity(gpu):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_batch_bitwise_equals_single(gpu, precision):
     systems = []
-    # 64 x 64 x 2 = 8192 elements: the smallest mesh with aggregates, so the
-    # batched coarse solve runs too
+    # 20 x 20 x 2, 33 x 33 x 2 and 64 x 64 x 2 have aggregates (4, 16 and 64),
+    # so the batched coarse solve runs too, beside systems without
     for n, mu in [(8, 300.0), (12, 50.0), (20, 1000.0), (33, 10.0), (64, 1000.0)]:
         co, el = synth.square_mesh(n, jitter=0.2, seed=n)
         fb = np.random.default_rng(n).normal(size=(len(el), 2))
@@ -396,7 +396,7 @@ def test_serving_mix_equals_solo(gpu):
 def test_prepared_assembly_equals_direct(gpu):
     """cr_prepare + cr_assemble_prepared (host part on a worker thread) builds the
     same system as cr_assemble: bitwise equal W and iteration count, with the
-    coarse correction (128 x 128 x 2: 16 aggregates) and without (steady case)."""
+    coarse correction (128 x 128 x 2: 256 aggregates) and without (steady case)."""
     import concurrent.futures
     for n, mu, method in [(128, 1000.0, "pcg"), (24, 0.0, "minres")]:
         co, el = synth.square_mesh(n, jitter=0.2, seed=7)

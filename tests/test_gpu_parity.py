@@ -266,8 +266,8 @@ def test_kernel_timing_runs_the_full_kernel(gpu, precision, operator):
 
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32_ir", 1e-9)])
 def test_coarse_correction_parity(gpu, precision, bar):
-    """CG with the aggregate coarse correction (64 x 64 x 2 = 8192 elements, 4
-    aggregates, and 128 x 128 x 2 with 16) against the oracle's direct solve, and
+    """CG with the aggregate coarse correction (64 x 64 x 2 = 8192 elements, 64
+    aggregates, and 128 x 128 x 2 with 256) against the oracle's direct solve, and
     against the same solve with Jacobi only: same solution, fewer iterations."""
     for n, seed in [(64, 21), (128, 22)]:
         coords, elems = synth.square_mesh(n, jitter=0.2, seed=seed)
@@ -293,7 +293,7 @@ def test_coarse_correction_parity(gpu, precision, bar):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_coarse_correction_3d(gpu, precision):
-    """3D coarse correction (12^3 x 6 = 10,368 tetrahedra, 8 aggregates): the
+    """3D coarse correction (12^3 x 6 = 10,368 tetrahedra, 64 aggregates): the
     same W as the Jacobi-only solve of the same system (whose parity with the
     oracle is tested on 5^3 x 6; the oracle's direct solve at this size takes
     about a minute), fewer iterations, and the FP64 residual at the tolerance."""
