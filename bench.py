@@ -445,12 +445,13 @@ def run_newton(crh, torch):
     """Newton iterations with non-homogeneous Dirichlet data (Section 4): the
     steady lid-driven cavity at Re = 100 on 64x64x2 from rest to the paper's
     threshold 5e-7, and the Green-Taylor vortex (amplitude Re = 100, nu = 1,
-    final time 0.01, dt/h^2 = 0.002 as in Table tab0) on 8, 16, 32 cells per
-    side with its errors against the exact solution and their orders."""
+    final time 0.01) in 2D (dt/h^2 = 0.002 as in Table tab0; 8, 16, 32 cells
+    per side) and in 3D (the time steps of the 3D Navier-Stokes table; 8 and 16
+    cubes per side) with its errors against the exact solution and their
+    orders."""
     import numpy as np
     import synth
     import synth.workloads as wl
-    from synth.fields import GreenTaylor2D, face_means
     from paper_2101_03777_amd.newton import NewtonSolver
     out = {}
     coords, elems = synth.square_mesh(64)
@@ -468,60 +469,86 @@ def run_newton(crh, torch):
         "time_s": round(time.perf_counter() - t0, 2)}
     log(f"cavity Re=100 64x64x2: {len(rec['increments'])} Newton iterations, {out['cavity_re100_64']['time_s']} s")
     ns.close()
-    gt = GreenTaylor2D(amp=100.0, nu=1.0)
+    out["green_taylor_2d"] = {"workload": "Green-Taylor vortex, amplitude Re = 100, nu = 1, unit square n x n x 2, "
+                                          "final time 0.01, dt/h^2 = 0.002, exact velocity on the boundary, "
+                                          "Newton at every backward-Euler step",
+                              "rows": green_taylor_rows(crh, torch, 2, (8, 16, 32), 0.002),
+                              "paper_table_tab0_ratios": "velocity 1.70, 1.44, 1.78, 1.94, 1.98; pressure 0.89, 1.23, "
+                                                         "1.67, 1.83, 1.72 (h = 0.125 ... 0.0078, FVCA Mesh1 family)"}
+    out["green_taylor_3d"] = {"workload": "3D Green-Taylor vortex (Section 4.1: the 2D vortex in (x1, x2), third "
+                                          "component zero), amplitude Re = 100, nu = 1, unit cube n^3 x 6 "
+                                          "tetrahedra, final time 0.01, dt = 0.01 a^2 with a = 1/n the cube side "
+                                          "(the time steps of the paper's 3D Navier-Stokes table, whose h = "
+                                          "(a^3/6)^(1/3) is the size of a tetrahedron), exact velocity on the "
+                                          "boundary, Newton at every backward-Euler step (12 x 12 local inverses)",
+                              "rows": green_taylor_rows(crh, torch, 3, (8, 16), 0.01),
+                              "paper_3d_ns_table": "n = 8, 16, 32 (h = 6.88e-2, 3.44e-2, 1.72e-2): velocity errors "
+                                                   "10.7, 4.10, 1.28 (ratios 1.38, 1.68); pressure 297, 143, 48.5 "
+                                                   "(1.05, 1.56)"}
+    return out
+
+
+def green_taylor_rows(crh, torch, dim, sizes, ratio):
+    """Errors of the Green-Taylor vortex at the final time 0.01 on n^dim cells
+    (dt = ratio h^2, h = 1/n): velocity at the face centroids weighted by the lumped mass
+    |K|/(d+1) of the two elements of each face, pressure at the element
+    centroids weighted by |K|, both without their means; and their orders."""
+    import numpy as np
+    import synth
+    import synth.workloads as wl
+    from synth.fields import GreenTaylor2D, GreenTaylor3D, face_means
+    from paper_2101_03777_amd.newton import NewtonSolver
+    gt = (GreenTaylor2D if dim == 2 else GreenTaylor3D)(amp=100.0, nu=1.0)
     rows = []
-    for n in (8, 16, 32):
-        coords, elems = synth.square_mesh(n)
+    for n in sizes:
+        coords, elems = synth.square_mesh(n) if dim == 2 else synth.cube_mesh(n)
         bf, fi = wl.exterior_face_list(elems), wl.interior_face_list(elems)
         h = 1.0 / n
-        dt = 0.002 * h * h
+        dt = ratio * h * h
         nsteps = int(round(0.01 / dt))
+        dt = 0.01 / nsteps
         ns = NewtonSolver(coords, elems, 1.0 / dt, 1.0)
         xf = coords[fi].mean(axis=1)
-        Ug = torch.from_numpy(gt.u(xf, 0.0)).cuda()
-        f = np.zeros((len(elems), 2))
+        Ug = torch.from_numpy(face_means(coords, fi, lambda x: gt.u(x, 0.0))).cuda()
+        f = np.zeros((len(elems), dim))
         t0 = time.perf_counter()
         newt = 0
+        lin = 0
         for k in range(1, nsteps + 1):
             ns.set_boundary(face_means(coords, bf, lambda x: gt.u(x, k * dt)))
             Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-9, lin_tol=1e-11)
             newt += len(rec["increments"])
+            lin += sum(rec["linear_iters"])
         wall = time.perf_counter() - t0
         T = nsteps * dt
-        # errors: velocity at the face centres (the CR nodes) weighted by the lumped
-        # mass |K|/3 of the two elements, pressure at the element centres weighted
-        # by |K|, both without their means
         X = coords[elems]
-        vol = 0.5 * np.abs((X[:, 1, 0] - X[:, 0, 0]) * (X[:, 2, 1] - X[:, 0, 1]) -
-                           (X[:, 2, 0] - X[:, 0, 0]) * (X[:, 1, 1] - X[:, 0, 1]))
+        if dim == 2:
+            vol = 0.5 * np.abs((X[:, 1, 0] - X[:, 0, 0]) * (X[:, 2, 1] - X[:, 0, 1]) -
+                               (X[:, 2, 0] - X[:, 0, 0]) * (X[:, 1, 1] - X[:, 0, 1]))
+        else:
+            vol = np.abs(np.einsum("ij,ij->i", X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]))) / 6.0
         fidx = {tuple(v): i for i, v in enumerate(fi)}
         mass = np.zeros(len(fi))
         for e, el in enumerate(elems):
-            for j in range(3):
+            for j in range(dim + 1):
                 key = tuple(sorted(np.delete(el, j)))
                 if key in fidx:
-                    mass[fidx[key]] += vol[e] / 3.0
+                    mass[fidx[key]] += vol[e] / (dim + 1)
         Ue = gt.u(xf, T)
         eu = np.sqrt((mass[:, None] * (Ug.cpu().numpy() - Ue) ** 2).sum())
         pe = gt.p(X.mean(axis=1), T)
         ph = Pg.cpu().numpy()
         dp = (ph - (vol * ph).sum() / vol.sum()) - (pe - (vol * pe).sum() / vol.sum())
         ep = np.sqrt((vol * dp ** 2).sum())
-        rows.append({"n": n, "h": h, "dt": dt, "steps": nsteps, "newton_iters": newt, "time_s": round(wall, 2),
-                     "err_l2_u": float(f"{eu:.4g}"), "err_l2_p": float(f"{ep:.4g}")})
-        log(f"Green-Taylor {n}x{n}x2: {nsteps} steps, {newt} Newton iterations, {wall:.1f} s, "
-            f"errors u {eu:.3g} p {ep:.3g}")
+        rows.append({"n": n, "h": h, "dt": dt, "steps": nsteps, "newton_iters": newt, "linear_iters": lin,
+                     "time_s": round(wall, 2), "err_l2_u": float(f"{eu:.4g}"), "err_l2_p": float(f"{ep:.4g}")})
+        log(f"Green-Taylor {dim}D n={n}: {nsteps} steps, {newt} Newton iterations, {lin} linear iterations, "
+            f"{wall:.1f} s, errors u {eu:.3g} p {ep:.3g}")
         ns.close()
     for a, b in zip(rows[:-1], rows[1:]):
-        b["ratio_u"] = round(float(np.log2(a["err_l2_u"] / b["err_l2_u"])), 2)
-        b["ratio_p"] = round(float(np.log2(a["err_l2_p"] / b["err_l2_p"])), 2)
-    out["green_taylor_2d"] = {"workload": "Green-Taylor vortex, amplitude Re = 100, nu = 1, unit square n x n x 2, "
-                                          "final time 0.01, dt/h^2 = 0.002, exact velocity on the boundary, "
-                                          "Newton at every backward-Euler step",
-                              "rows": rows,
-                              "paper_table_tab0_ratios": "velocity 1.70, 1.44, 1.78, 1.94, 1.98; pressure 0.89, 1.23, "
-                                                         "1.67, 1.83, 1.72 (h = 0.125 ... 0.0078, FVCA Mesh1 family)"}
-    return out
+        b["ratio_u"] = round(float(np.log2(a["err_l2_u"] / b["err_l2_u"]) / np.log2(b["n"] / a["n"])), 2)
+        b["ratio_p"] = round(float(np.log2(a["err_l2_p"] / b["err_l2_p"]) / np.log2(b["n"] / a["n"])), 2)
+    return rows
 
 
 def main():

@@ -399,3 +399,28 @@ class GreenTaylor2D:
         def fn(pts):
             return 2.0 * self.k ** 2 * self.nu * self.u(pts, t)
         return fn
+
+
+class GreenTaylor3D(GreenTaylor2D):
+    """The 3D extension of the Green-Taylor vortex used by the paper's 3D tests
+    (Section 4.1): the first two velocity components and the pressure are those
+    of the 2D vortex in (x1, x2), independent of x3, and the third component is
+    zero.  It solves the unforced 3D Navier-Stokes equations on the unit cube
+    (non-homogeneous Dirichlet data on every face)."""
+
+    def u(self, pts, t=0.0):
+        u2 = super().u(pts[:, :2], t)
+        return np.concatenate([u2, np.zeros((len(pts), 1))], axis=1)
+
+    def grad_u(self, pts, t=0.0):
+        g2 = super().grad_u(pts[:, :2], t)
+        g = np.zeros((len(pts), 3, 3))
+        g[:, :2, :2] = g2
+        return g
+
+    def p(self, pts, t=0.0):
+        return super().p(pts[:, :2], t)
+
+    def grad_p(self, pts, t=0.0):
+        g2 = super().grad_p(pts[:, :2], t)
+        return np.concatenate([g2, np.zeros((len(pts), 1))], axis=1)

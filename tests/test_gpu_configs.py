@@ -11,6 +11,8 @@ row by row (its own element matrices, no global solve):
 Smaller meshes are compared with the oracle's direct solution element by
 element.  Batched and served solves are compared bitwise with single solves.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -567,3 +569,104 @@ def test_newton_green_taylor_time_steps_against_oracle(gpu):
         assert_close(Ug.cpu().numpy(), Uo, 1e-9)
         assert_close(Pg.cpu().numpy(), Po, 1e-9)
     ns.close()
+
+
+def test_newton_green_taylor_3d_time_steps_against_oracle(gpu):
+    """The 3D Green-Taylor vortex of Section 4.1's 3D Navier-Stokes test
+    (amplitude Re = 100, nu = 1, third component zero) on 3^3 x 6 tetrahedra,
+    face means on the boundary at each time, two backward-Euler steps with
+    Newton from the previous step: against the oracle's chain of Newton solves
+    (12 x 12 local inverses on the GPU, general inverses in the oracle), U and
+    P within 1e-9 at every step."""
+    from oracle import newton as onewton
+    from paper_2101_03777_amd.newton import NewtonSolver
+    from synth.fields import GreenTaylor3D, face_means
+    gt = GreenTaylor3D(amp=100.0, nu=1.0)
+    coords, elems = synth.cube_mesh(3)
+    bf = wl.exterior_face_list(elems)
+    fi = wl.interior_face_list(elems)
+    dt = 0.01 / 9.0
+    f = np.zeros((len(elems), 3))
+    u0 = face_means(coords, fi, lambda x: gt.u(x, 0.0))
+    ns = NewtonSolver(coords, elems, 1.0 / dt, 1.0)
+    Ug, Uo = dev(u0), u0
+    for n in range(1, 3):
+        g = face_means(coords, bf, lambda x: gt.u(x, n * dt))
+        Uo, Po, inc_o = onewton.newton(coords, elems, 1.0 / dt, 1.0, f, gbnd=g, u_prev=Uo, u0=Uo, tol=1e-11)
+        ns.set_boundary(g)
+        # linear tolerance 1e-11: on this 54-element mesh BiCGStab(2) in FP64
+        # stagnates before 1e-13
+        Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-10, lin_tol=1e-11, lin_maxit=50000)
+        print(f"3D Green-Taylor step {n}: oracle {len(inc_o)} Newton iterations, GPU {rec}", flush=True)
+        assert rec["converged"], rec
+        assert_close(Ug.cpu().numpy(), Uo, 1e-9)
+        assert_close(Pg.cpu().numpy(), Po, 1e-9)
+    ns.close()
+
+
+def _paper_3d_ns_table():
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_3d_ns_green_taylor.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                n, dt, h, eu, ep = line.split()
+                rows[int(n)] = dict(dt=float(dt), h=float(h), eu=float(eu), ep=float(ep))
+    return rows
+
+
+def _green_taylor_errors_3d(gpu, n):
+    """The 3D Green-Taylor vortex to t = 0.01 on n^3 x 6 tetrahedra with
+    dt = 0.01 / n^2, through the Newton driver; velocity error at the face
+    centroids with the lumped mass |K|/4 of the two elements, pressure error at
+    the element centroids weighted by |K|, both without their means."""
+    from paper_2101_03777_amd.newton import NewtonSolver
+    from synth.fields import GreenTaylor3D, face_means
+    gt = GreenTaylor3D(amp=100.0, nu=1.0)
+    coords, elems = synth.cube_mesh(n)
+    bf, fi = wl.exterior_face_list(elems), wl.interior_face_list(elems)
+    nsteps = n * n
+    dt = 0.01 / nsteps
+    ns = NewtonSolver(coords, elems, 1.0 / dt, 1.0)
+    Ug = dev(face_means(coords, fi, lambda x: gt.u(x, 0.0)))
+    f = np.zeros((len(elems), 3))
+    for k in range(1, nsteps + 1):
+        ns.set_boundary(face_means(coords, bf, lambda x: gt.u(x, k * dt)))
+        Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-9, lin_tol=1e-11)
+        assert rec["converged"], (k, rec)
+    ns.close()
+    X = coords[elems]
+    vol = np.abs(np.einsum("ij,ij->i", X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]))) / 6.0
+    fidx = {tuple(v): i for i, v in enumerate(fi)}
+    mass = np.zeros(len(fi))
+    for e, el in enumerate(elems):
+        for j in range(4):
+            key = tuple(sorted(np.delete(el, j)))
+            if key in fidx:
+                mass[fidx[key]] += vol[e] / 4.0
+    eu = np.sqrt((mass[:, None] * (Ug.cpu().numpy() - gt.u(coords[fi].mean(axis=1), 0.01)) ** 2).sum())
+    pe = gt.p(X.mean(axis=1), 0.01)
+    ph = Pg.cpu().numpy()
+    dp = (ph - (vol * ph).sum() / vol.sum()) - (pe - (vol * pe).sum() / vol.sum())
+    return eu, np.sqrt((vol * dp ** 2).sum())
+
+
+def test_green_taylor_3d_reproduces_the_paper_table(gpu):
+    """Section 4.1, 3D Navier-Stokes Green-Taylor table: on 8^3 and 16^3 cubes
+    x 6 tetrahedra with the printed time steps, the GPU path (boundary data,
+    Newton driver, 3D Newton steps with 12 x 12 local inverses, BiCGStab(2))
+    gives the printed velocity and pressure errors within 5% and their ratio
+    within 0.05 (tests/golden/paper_3d_ns_green_taylor.txt)."""
+    paper = _paper_3d_ns_table()
+    errs = {}
+    for n in (8, 16):
+        assert abs(0.01 / (n * n) - paper[n]["dt"]) <= 0.01 * paper[n]["dt"]
+        errs[n] = _green_taylor_errors_3d(gpu, n)
+        print(f"3D Green-Taylor n={n}: errors u {errs[n][0]:.4g} p {errs[n][1]:.4g}, paper {paper[n]}", flush=True)
+        assert abs(errs[n][0] - paper[n]["eu"]) <= 0.05 * paper[n]["eu"]
+        assert abs(errs[n][1] - paper[n]["ep"]) <= 0.05 * paper[n]["ep"]
+    for k in (0, 1):
+        key = "eu" if k == 0 else "ep"
+        ours = np.log2(errs[8][k] / errs[16][k])
+        theirs = np.log2(paper[8][key] / paper[16][key])
+        assert abs(ours - theirs) <= 0.05, (key, ours, theirs)

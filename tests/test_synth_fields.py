@@ -80,3 +80,30 @@ def test_green_taylor_paper_constants():
     k2 = (2 * np.pi) ** 2
     assert np.allclose(gt.u(x, t), u0 * np.exp(-2 * k2 * t), rtol=1e-14, atol=0)
     assert np.allclose(gt.p(x, t), gt.p(x, 0.0) * np.exp(-4 * k2 * t), rtol=1e-14, atol=0)
+
+
+def test_green_taylor_3d_solves_unforced_navier_stokes():
+    """The 3D extension (third component zero, no x3 dependence) by central
+    differences in all three directions."""
+    from synth.fields import GreenTaylor3D
+    nu = 0.5
+    gt = GreenTaylor3D(amp=20.0, nu=nu)
+    x = np.random.default_rng(7).uniform(0.0, 1.0, size=(48, 3))
+    t, h = 0.004, 1e-4
+    u = gt.u(x, t)
+    assert u.shape == (48, 3) and np.all(u[:, 2] == 0.0)
+    du_dt = (gt.u(x, t + h) - gt.u(x, t - h)) / (2 * h)
+    g = np.zeros((len(x), 3, 3))
+    lap = np.zeros_like(u)
+    gp = np.zeros((len(x), 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        g[:, :, j] = (gt.u(x + e, t) - gt.u(x - e, t)) / (2 * h)
+        lap += (gt.u(x + e, t) - 2 * u + gt.u(x - e, t)) / h ** 2
+        gp[:, j] = (gt.p(x + e, t) - gt.p(x - e, t)) / (2 * h)
+    res = du_dt + np.einsum("mj,mij->mi", u, g) - nu * lap + gp
+    assert np.abs(res).max() < 1e-5 * (np.abs(du_dt).max() + np.abs(nu * lap).max())
+    assert np.abs(np.trace(g, axis1=1, axis2=2)).max() < 1e-7 * np.abs(g).max()
+    assert np.abs(gt.grad_u(x, t) - g).max() < 1e-6 * np.abs(g).max()
+    assert np.abs(gt.grad_p(x, t) - gp).max() < 1e-6 * np.abs(gp).max()
