@@ -485,14 +485,25 @@ def run_newton(crh, torch):
                               "paper_3d_ns_table": "n = 8, 16, 32 (h = 6.88e-2, 3.44e-2, 1.72e-2): velocity errors "
                                                    "10.7, 4.10, 1.28 (ratios 1.38, 1.68); pressure 297, 143, 48.5 "
                                                    "(1.05, 1.56)"}
+    out["green_taylor_3d_stokes"] = {
+        "workload": "3D Green-Taylor Stokes test (Section 4.1: the vortex's velocity, zero pressure, unforced "
+                    "transient Stokes), unit cube n^3 x 6 tetrahedra, final time 0.01, dt = 0.0016 a^2 (the time "
+                    "steps of the paper's 3D Stokes table), exact velocity on the boundary, one hybridised CG "
+                    "solve (FP64, 1e-11) per step",
+        "rows": green_taylor_rows(crh, torch, 3, (4, 8, 16), 0.0016, stokes=True),
+        "paper_3d_stokes_table": "n = 4, 8, 16, 32 (h = 1.38e-1 ... 1.72e-2): velocity errors 3.44, 0.85, 0.22, "
+                                 "5.4e-2 (ratios 2.02, 1.95, 2.03); pressure 33, 17, 8.1, 4.0 (0.96, 1.07, 1.02)"}
     return out
 
 
-def green_taylor_rows(crh, torch, dim, sizes, ratio):
+def green_taylor_rows(crh, torch, dim, sizes, ratio, stokes=False):
     """Errors of the Green-Taylor vortex at the final time 0.01 on n^dim cells
-    (dt = ratio h^2, h = 1/n): velocity at the face centroids weighted by the lumped mass
-    |K|/(d+1) of the two elements of each face, pressure at the element
-    centroids weighted by |K|, both without their means; and their orders."""
+    (dt = ratio h^2, h = 1/n): velocity at the face centroids weighted by the
+    lumped mass |K|/(d+1) of the two elements of each face, pressure at the
+    element centroids weighted by |K|, both without their means; and their
+    orders.  stokes: the unforced transient Stokes problem with the vortex's
+    velocity and zero pressure (one hybridised solve per step, CG) instead of
+    Navier-Stokes (Newton at every step)."""
     import numpy as np
     import synth
     import synth.workloads as wl
@@ -507,18 +518,25 @@ def green_taylor_rows(crh, torch, dim, sizes, ratio):
         dt = ratio * h * h
         nsteps = int(round(0.01 / dt))
         dt = 0.01 / nsteps
-        ns = NewtonSolver(coords, elems, 1.0 / dt, 1.0)
+        ns = crh.System(coords, elems, 1.0 / dt, 1.0) if stokes else NewtonSolver(coords, elems, 1.0 / dt, 1.0)
         xf = coords[fi].mean(axis=1)
         Ug = torch.from_numpy(face_means(coords, fi, lambda x: gt.u(x, 0.0))).cuda()
         f = np.zeros((len(elems), dim))
+        fd = torch.zeros((len(elems), dim), dtype=torch.float64, device="cuda")
         t0 = time.perf_counter()
         newt = 0
         lin = 0
         for k in range(1, nsteps + 1):
             ns.set_boundary(face_means(coords, bf, lambda x: gt.u(x, k * dt)))
-            Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-9, lin_tol=1e-11)
-            newt += len(rec["increments"])
-            lin += sum(rec["linear_iters"])
+            if stokes:
+                ns.eliminate(fd, Ug)
+                info = ns.solve("pcg", "fp64", tol=1e-11, warm_start=k > 1)
+                Ug, Pg = ns.recover()
+                lin += info["iters"]
+            else:
+                Ug, Pg, rec = ns.solve(f, u_prev=Ug, u0=Ug, tol=1e-9, lin_tol=1e-11)
+                newt += len(rec["increments"])
+                lin += sum(rec["linear_iters"])
         wall = time.perf_counter() - t0
         T = nsteps * dt
         X = coords[elems]
@@ -536,13 +554,13 @@ def green_taylor_rows(crh, torch, dim, sizes, ratio):
                     mass[fidx[key]] += vol[e] / (dim + 1)
         Ue = gt.u(xf, T)
         eu = np.sqrt((mass[:, None] * (Ug.cpu().numpy() - Ue) ** 2).sum())
-        pe = gt.p(X.mean(axis=1), T)
+        pe = np.zeros(len(elems)) if stokes else gt.p(X.mean(axis=1), T)
         ph = Pg.cpu().numpy()
         dp = (ph - (vol * ph).sum() / vol.sum()) - (pe - (vol * pe).sum() / vol.sum())
         ep = np.sqrt((vol * dp ** 2).sum())
         rows.append({"n": n, "h": h, "dt": dt, "steps": nsteps, "newton_iters": newt, "linear_iters": lin,
                      "time_s": round(wall, 2), "err_l2_u": float(f"{eu:.4g}"), "err_l2_p": float(f"{ep:.4g}")})
-        log(f"Green-Taylor {dim}D n={n}: {nsteps} steps, {newt} Newton iterations, {lin} linear iterations, "
+        log(f"Green-Taylor {dim}D{' Stokes' if stokes else ''} n={n}: {nsteps} steps, {newt} Newton iterations, {lin} linear iterations, "
             f"{wall:.1f} s, errors u {eu:.3g} p {ep:.3g}")
         ns.close()
     for a, b in zip(rows[:-1], rows[1:]):
