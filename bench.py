@@ -529,7 +529,11 @@ def green_taylor_rows(crh, torch, dim, sizes, ratio, stokes=False):
         for k in range(1, nsteps + 1):
             ns.set_boundary(face_means(coords, bf, lambda x: gt.u(x, k * dt)))
             if stokes:
-                ns.eliminate(fd, Ug)
+                # the operator stays; each step refreshes the right-hand side
+                if k == 1:
+                    ns.eliminate(fd, Ug)
+                else:
+                    ns.update_rhs(fd, Ug)
                 info = ns.solve("pcg", "fp64", tol=1e-11, warm_start=k > 1)
                 Ug, Pg = ns.recover()
                 lin += info["iters"]

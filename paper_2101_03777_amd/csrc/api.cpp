@@ -324,6 +324,7 @@ cr_status finish_device(cr_system* s, Staging& h, const cr_allocator* alloc, voi
     if (st == CR_OK) st = alloc_n(s, s->bs1, nvec);
     if (st == CR_OK) st = alloc_n(s, s->zy, nvec);
     if (st == CR_OK) st = alloc_n(s, s->k0t, (size_t)1);
+    if (st == CR_OK) st = alloc_n(s, s->k0eps, (size_t)1);
     if (st == CR_OK && h.coarse) {
       const size_t m = (size_t)s->nagg;
       st = upload(s, s->fagg, t.face_agg);

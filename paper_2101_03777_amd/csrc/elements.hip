@@ -945,12 +945,34 @@ __global__ void __launch_bounds__(BS) k_zvec(int64_t nf, int64_t ne, const int32
   for (int i = 0; i < D; ++i) zy[f * D + i] = dsq[f * D + i] * g.a[j][i];
 }
 
-// Right-hand side of the element form: S' = S - u (l_K0^t R_K0) / B_K0, a
-// change on the faces of K0 only (bs1 holds a copy of the scaled S).  One thread.
+// Divergence data eps of K0's row in the gauge-shifted system.  G W = S has
+// no divergence row at K0, so eps is free; z^t S' = 0 (the consistency of
+// G' W' = S', z the null vector of G') holds exactly when
+// eps = -sum_{K != K0} e_K, the flux that K0 takes up.  Without boundary data
+// eps = 0.  One workgroup, fixed summation order.
+__global__ void __launch_bounds__(256) k_k0_eps(int64_t ne, int64_t k0, const double* __restrict__ ek,
+                                                double* __restrict__ eps) {
+  __shared__ double red[256];
+  double v = 0.0;
+  if (ek != nullptr)
+    for (int64_t k = threadIdx.x; k < ne; k += 256) v += k == k0 ? 0.0 : ek[k];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) eps[0] = -red[0];
+}
+
+// Right-hand side of the element form: S' = S - u (l_K0^t R_K0 - eps) / B_K0,
+// a change on the faces of K0 only (bs1 holds a copy of the scaled S).  One
+// thread.
 template <int D>
 __global__ void k_k0_rhs(int64_t ne, int64_t k, const double* __restrict__ pack, const double* __restrict__ ecoord,
                          const int32_t* __restrict__ eface, const uint32_t* __restrict__ eflags,
-                         const double* __restrict__ RK, const double* __restrict__ dsq, double* __restrict__ bs1) {
+                         const double* __restrict__ RK, const double* __restrict__ dsq, const double* __restrict__ eps,
+                         double* __restrict__ bs1) {
   constexpr int N = D + 1;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   StokesFactors<D> F;
@@ -963,6 +985,7 @@ __global__ void k_k0_rhs(int64_t ne, int64_t k, const double* __restrict__ pack,
 #pragma unroll
     for (int i = 0; i < D; ++i)
       if (interior(fl, j)) rho += F.V[j][i] * RK[(int64_t)(j * D + i) * ne + k];
+  rho -= eps[0];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     if (!interior(fl, j)) continue;
@@ -973,12 +996,13 @@ __global__ void k_k0_rhs(int64_t ne, int64_t k, const double* __restrict__ pack,
 }
 
 // Gauge shift: for a solution W' of G' W' = S', W = W' + t z solves G W = S
-// with t = -P_K0(W'), P_K0(W') = l^t (R - C W') / B at K0.  One thread writes t.
+// with t = -P_K0(W'), P_K0(W') = (l^t (R - C W') - eps) / B at K0.  One
+// thread writes t.
 template <int D>
 __global__ void k_k0_gauge(int64_t ne, int64_t k, const double* __restrict__ pack, const double* __restrict__ ecoord,
                            const int32_t* __restrict__ eface, const uint32_t* __restrict__ eflags,
                            const double* __restrict__ RK, const double* __restrict__ y,
-                           const double* __restrict__ dsq, double* __restrict__ t) {
+                           const double* __restrict__ dsq, const double* __restrict__ eps, double* __restrict__ t) {
   constexpr int N = D + 1;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   StokesFactors<D> F;
@@ -994,7 +1018,7 @@ __global__ void k_k0_gauge(int64_t ne, int64_t k, const double* __restrict__ pac
     for (int i = 0; i < D; ++i)
       p += F.V[j][i] * (RK[(int64_t)(j * D + i) * ne + k] - csign(fl, j) * y[f * D + i] / dsq[f * D + i]);
   }
-  t[0] = -p * F.invB;
+  t[0] = -(p - eps[0]) * F.invB;
 }
 
 // ---------------------------------------------------------------------------
@@ -1424,22 +1448,24 @@ static cr_status k0_rhs(cr_system* s) {
   cr_status st = check_hip(hipMemcpyAsync(s->bs1, s->bs, sizeof(double) * s->nf * s->d, hipMemcpyDeviceToDevice,
                                           s->stream), "element-form right-hand side");
   if (st != CR_OK) return st;
+  hipLaunchKernelGGL(k_k0_eps, dim3(1), dim3(256), 0, s->stream, s->ne, s->k0i, s->has_bnd ? s->ek : nullptr,
+                     s->k0eps);
   if (s->d == 2)
     hipLaunchKernelGGL(k_k0_rhs<2>, dim3(1), dim3(64), 0, s->stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
-                       s->eflags, s->RK, s->dsq, s->bs1);
+                       s->eflags, s->RK, s->dsq, s->k0eps, s->bs1);
   else
     hipLaunchKernelGGL(k_k0_rhs<3>, dim3(1), dim3(64), 0, s->stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
-                       s->eflags, s->RK, s->dsq, s->bs1);
+                       s->eflags, s->RK, s->dsq, s->k0eps, s->bs1);
   return check_hip(hipGetLastError(), "element-form right-hand side");
 }
 
 cr_status enqueue_gauge_fix(cr_system* s, hipStream_t stream) {
   if (s->d == 2)
     hipLaunchKernelGGL(k_k0_gauge<2>, dim3(1), dim3(64), 0, stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
-                       s->eflags, s->RK, s->y, s->dsq, s->k0t);
+                       s->eflags, s->RK, s->y, s->dsq, s->k0eps, s->k0t);
   else
     hipLaunchKernelGGL(k_k0_gauge<3>, dim3(1), dim3(64), 0, stream, s->ne, s->k0i, s->pack, s->ecoord, s->eface,
-                       s->eflags, s->RK, s->y, s->dsq, s->k0t);
+                       s->eflags, s->RK, s->y, s->dsq, s->k0eps, s->k0t);
   const int64_t n = s->nf * s->d;
   hipLaunchKernelGGL(k_gauge_axpy, dim3(nblocks(n, BS)), dim3(BS), 0, stream, n, s->k0t, s->zy, s->y);
   return check_hip(hipGetLastError(), "gauge shift");

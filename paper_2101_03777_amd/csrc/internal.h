@@ -107,6 +107,7 @@ struct cr_system {
   double* bs1 = nullptr;       // [nf*d]
   double* zy = nullptr;        // [nf*d]
   double* k0t = nullptr;       // [1]
+  double* k0eps = nullptr;     // [1] divergence data of K0's row in the gauge-shifted system
   int64_t k0i = 0;             // internal id of K0
   // coarse correction of the element-form CG (nagg > 0): aggregate of each
   // face, the (element, j, l) entries of each nonzero of E = Z^t G' Z grouped

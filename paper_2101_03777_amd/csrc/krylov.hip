@@ -1671,10 +1671,10 @@ CgSys make_sys(cr_system* s, KWs* w, int prec, KState* st) {
 // Operator form of a solve: the element factors (built for transient Stokes)
 // serve CG; the assembled rows serve BiCGStab and explicit requests.
 cr_status resolve_op(const cr_system* s, const cr_solve_opts* o, int& op) {
-  // the element form carries K0's divergence row too (gauge-shifted system),
-  // which holds only for homogeneous data: with boundary data CG applies the
-  // assembled rows
-  const bool have = s->efo64 != nullptr && o->method == CR_PCG && !s->has_bnd;
+  // the element form carries K0's divergence row too (gauge-shifted system;
+  // with boundary data K0's row takes up the net flux, so that the system
+  // stays consistent)
+  const bool have = s->efo64 != nullptr && o->method == CR_PCG;
   switch (o->operator_form) {
     case CR_OP_AUTO:
       op = have ? 1 : 0;
@@ -1684,7 +1684,7 @@ cr_status resolve_op(const cr_system* s, const cr_solve_opts* o, int& op) {
       return CR_OK;
     case CR_OP_ELEMENT:
       if (!have) {
-        set_error("the element-factor operator needs CG on a transient Stokes system without boundary data");
+        set_error("the element-factor operator needs CG on a transient Stokes system");
         return CR_E_INVAL;
       }
       op = 1;
