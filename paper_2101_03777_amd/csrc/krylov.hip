@@ -109,7 +109,7 @@ struct KState {
   // parameters written by the host
   double rep_tol2, tol2;
   int maxit;
-  int interval_cap;  // > 0: at most this many iterations between replacements (FP32)
+  int interval_cap;  // > 0: at most this many iterations between replacements (FP32, and CG)
 };
 
 template <typename T, int D>
@@ -288,8 +288,11 @@ struct Decision {
   double rr_rep, thr_rep, tgt;
 };
 
+// capped: the interval cap applies (FP32 iterations, and CG in either
+// precision: a restart every interval_cap iterations bounds how long a run
+// that no longer reaches a replacement can drift)
 __device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh, double rr, double tres2,
-                                           double snorm2, bool f32) {
+                                           double snorm2, bool capped) {
   Decision d;
   d.done = RUNNING;
   if (fresh) {
@@ -313,7 +316,7 @@ __device__ __forceinline__ Decision decide(const KState* st, int it, bool fresh,
     d.done = LIMIT;
   else if (!fresh && !(it & 1) && (rr <= d.thr_rep || rr <= d.tgt))
     d.done = REPLACE;
-  else if (f32 && !fresh && !(it & 1) && st->interval_cap > 0 && it - st->it_rep >= st->interval_cap)
+  else if (capped && !fresh && !(it & 1) && st->interval_cap > 0 && it - st->it_rep >= st->interval_cap)
     d.done = STALL;
   return d;
 }
@@ -346,7 +349,7 @@ __device__ __forceinline__ void record_decision(KState* st, const Decision& d, b
 // new direction.  The state words and all the sums' inputs are requested
 // before any is used, and one workgroup reduction forms every sum (each in the
 // same order as its own reduction would).
-__device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f32, double& beta, bool& first,
+__device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, double& beta, bool& first,
                                         bool with_coarse = false) {
   KState* st = S.st;
   const int done = st->done;
@@ -366,7 +369,7 @@ __device__ __forceinline__ bool cg_head(const CgSys& S, int lb, int par, bool f3
   first = it == it_first;
   const bool fresh = it == it_rep;
   const double rr = v[0], tres2 = fresh ? v[1] : 0.0, snorm2 = fresh ? v[2] : 0.0, coarse = v[3];
-  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, f32);
+  const Decision dec = decide(st, it, fresh, rr, tres2, snorm2, true);
   if (threadIdx.x == 0 && lb == 0) record_decision(st, dec, fresh, it, rr, tres2, snorm2);
   beta = first ? 0.0 : (rr + coarse) / gam_old;
   if (threadIdx.x == 0 && lb == 0 && !dec.done) {
@@ -383,7 +386,7 @@ template <int D, typename T, int OP>
 __device__ __forceinline__ void cg_spmv_body(const CgSys& S, int lb, int par) {
   double beta_d;
   bool first;
-  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first)) return;
+  if (!cg_head(S, lb, par, beta_d, first)) return;
   const Part P = S.P;
   const T beta = (T)beta_d;
   const T* __restrict__ r = (const T*)S.r;
@@ -641,7 +644,7 @@ __device__ __forceinline__ void ec1_body(const CgSys& S, int lb, int par) {
   constexpr int EB = ec1_batch<D, T>();
   double beta_d;
   bool first;
-  if (!cg_head(S, lb, par, std::is_same<T, float>::value, beta_d, first, S.nagg > 0)) return;
+  if (!cg_head(S, lb, par, beta_d, first, S.nagg > 0)) return;
   const int64_t lo = (int64_t)lb * S.PE.chunk, hi = min(S.ne, lo + S.PE.chunk);
   double acc[1] = {0.0};
   if (EB > 1 && S.PE.chunk >= (int64_t)EB * NT)
@@ -1890,7 +1893,8 @@ void fill_params(KState& h, const cr_solve_opts* o, double& tol_out) {
   h.rep_tol2 = rep * rep;
   h.tol2 = tol * tol;
   h.maxit = o->maxit > 0 ? o->maxit : 1000000;
-  // FP32 iterations between replacements are capped (checked in the FP32 kernels only)
+  // iterations between replacements are capped for FP32 iterations and for
+  // CG (a stop that restarts the direction from the FP64 residual)
   h.interval_cap = 4000;
   tol_out = tol;
 }
@@ -1916,7 +1920,13 @@ struct Ctl {
   int maxit = 0, max_rep = 400;
   int reps = 1, restarts = 0, reason = 0, iters = 0, fp32_iters = 0;
   double rel = -1.0, prev_true = -1.0;
-  bool fell_back = false, final_eval = false;
+  // FP64 iterations: smallest true residual seen at a replacement, and the
+  // replacements since it last fell by half (stagnation at the attainable
+  // accuracy ends the solve after STAGNANT of them)
+  double best_true = -1.0;
+  int stagnant = 0;
+  static constexpr int STAGNANT = 8;
+  bool fell_back = false, final_eval = false, stagnated = false;
 
   void init(const cr_solve_opts* o) {
     prec = o->precision;
@@ -1972,7 +1982,16 @@ struct Ctl {
       residual(prec, ks.done == STALL ? 2 : 1);
     }
     ++reps;
-    if ((!stall && ks.done != REPLACE && ks.done != BREAKDOWN && ks.done != DIVERGED) || reps > max_rep ||
+    if (!f32 && (ks.done == REPLACE || ks.done == STALL)) {
+      if (best_true < 0.0 || ks.tres2 < 0.25 * best_true) {
+        best_true = ks.tres2;
+        stagnant = 0;
+      } else if (++stagnant >= STAGNANT) {
+        stagnated = true;
+      }
+    }
+    if ((!stall && ks.done != REPLACE && ks.done != STALL && ks.done != BREAKDOWN && ks.done != DIVERGED) ||
+        reps > max_rep || stagnated ||
         iters >= maxit)
       final_eval = true;
     return false;
@@ -1988,8 +2007,12 @@ struct Ctl {
       set_error("non-finite Krylov scalar after %d iterations", iters);
       return CR_E_NONFINITE;
     }
-    set_error("no convergence: relative residual %.3e after %d iterations, %d residual evaluations", rel, iters,
-              reps);
+    if (stagnated)
+      set_error("no convergence: the residual stagnated at %.3e (the attainable accuracy) after %d iterations",
+                rel, iters);
+    else
+      set_error("no convergence: relative residual %.3e after %d iterations, %d residual evaluations", rel, iters,
+                reps);
     return CR_E_NOCONV;
   }
 

@@ -339,6 +339,19 @@ def test_error_paths(gpu):
     s.eliminate(dev(fbar))
     out = s.solve("pcg", "fp64", tol=1e-12, maxit=3, raise_on_error=False)
     assert out["status"] == -5 and out["iters"] <= 3
+    # a tolerance below the attainable accuracy: the FP64 residual stagnates
+    # (or p.Gp loses its sign to rounding there) and the solve ends with no
+    # convergence or a breakdown long before the iteration cap, with the
+    # residual at the attainable accuracy (both operator forms, both
+    # precisions; FP32 iterations fall back to FP64)
+    for op in ("element", "assembled"):
+        for prec in ("fp64", "fp32_ir"):
+            out = s.solve("pcg", prec, tol=1e-19, maxit=200000, operator=op, raise_on_error=False)
+            msg = gpu.load().cr_last_error().decode()
+            print(f"tol 1e-19 {op} {prec}: {out} {msg}", flush=True)
+            assert out["status"] in (-5, -6) and out["iters"] < 40000
+            assert out["rel_residual"] < 1e-13
+            assert "stagnated" in msg or "breakdown" in msg
     s.close()
 
 
