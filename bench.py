@@ -170,6 +170,55 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def run_c1(crh, torch):
+    """The smallest configuration (16x16x2, mu = 100): eliminate + CG (FP64, to
+    1e-12) + recover on the GPU; returns the record and the solution, which the
+    oracle leg compares with the oracle's coupled direct solve."""
+    import synth.workloads as wl
+    w = wl.square16()
+    s = crh.System(w["coords"], w["elems"], w["mu"], w["nu"])
+    f = torch.from_numpy(w["fbar"]).cuda()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.eliminate(f)
+        info = s.solve("pcg", "fp64", tol=1e-12)
+        U, P = s.recover()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    s.close()
+    rec = {"workload": "2D transient Stokes, 16x16x2 (512 elements), nu = 1, mu = 100, manufactured RHS; "
+                       "eliminate + CG (FP64, coarse correction) to 1e-12 + recover",
+           "ms_per_solve": round(min(ts), 3), "iters": info["iters"], "rel_residual": info["rel_residual"]}
+    return rec, U.cpu().numpy(), P.cpu().numpy()
+
+
+def c1_oracle_leg(rec, U, P):
+    """Oracle leg of the smallest configuration: the coupled direct solve (FP64,
+    one thread) timed on this host, and the GPU solution's error against it."""
+    import numpy as np
+    import synth.workloads as wl
+    from oracle import cr
+    from threadpoolctl import threadpool_limits
+    w = wl.square16()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Pr = cr.make_problem(w["coords"], w["elems"], w["mu"], w["nu"], w["fbar"])
+        Uo, Po = cr.solve_coupled(Pr)
+        wall = time.perf_counter() - t0
+    rec = dict(rec)
+    rec["oracle_ms"] = round(1e3 * wall, 1)
+    rec["err_vs_oracle"] = {
+        "U_rel2": float(np.linalg.norm(U - Uo) / np.linalg.norm(Uo)),
+        "U_max_rel": float(np.abs(U - Uo).max() / np.abs(Uo).max()),
+        "P_rel2": float(np.linalg.norm(P - Po) / np.linalg.norm(Po)),
+        "P_max_rel": float(np.abs(P - Po).max() / np.abs(Po).max())}
+    return rec
+
+
 def cpu_oracle_baseline(ne_target, n_sample=10):
     """The oracle's primary result (assembly and sparse LU of the coupled system,
     FP64, one thread) on a bounded sample of the headline workload family: the
@@ -427,6 +476,18 @@ def run_ns(crh, torch):
                                                                     "status", "oracle")}}
     log(f"NS 256x256x2 BiCGStab(2): {info['t_solve_ms']:.0f} ms, {info['iters']} iterations, status {info['status']}, "
         f"error {json.dumps(out['err_vs_oracle'])}")
+    # the configured precision (FP32 iterations inside FP64 residual
+    # replacement): the FP32 passes stall and the solve falls back to FP64
+    i32 = s.solve("bicgstab2", "fp32_ir", tol=1e-9, maxit=600000, raise_on_error=False)
+    U32, P32 = s.recover()
+    e32 = oracle_error("ns256", U32, P32)
+    out["fp32_ir_attempt"] = {"status": i32["status"], "time_to_tol_ms": round(i32["t_solve_ms"], 1),
+                              "iters": i32["iters"], "fp32_iters": i32["fp32_iters"],
+                              "fp64_fallback": i32["fp64_fallback"], "rel_residual": i32["rel_residual"],
+                              "err_vs_oracle": {k: v for k, v in e32.items()
+                                                if k in ("U_rel2", "U_max_rel", "P_rel2", "P_max_rel")}}
+    log(f"NS 256x256x2 BiCGStab(2) FP32 iterations + FP64 replacement: {i32['t_solve_ms']:.0f} ms, {i32['iters']} "
+        f"iterations ({i32['fp32_iters']} FP32), FP64 fallback {i32['fp64_fallback']}, status {i32['status']}")
     Uc, Pc, ci = s.coupled_solve(tol=1e-9, maxit=100000, raise_on_error=False)
     ce = oracle_error("ns256", Uc, Pc)
     out["coupled_gpu"] = {"method": "FP64 BiCGStab on eq. syslin (Jacobian blocks in A), symmetric scaling by the "
@@ -698,6 +759,7 @@ def main():
     second = None
     ns = None
     context = None
+    c1, c1_sol = None, None
     if not args.no_other:
         other = "square512j" if args.workload == "cube64" else "cube64"
         second, _ = measure_transient(crh, torch, other, args, max(3, args.steps // 2), 1, args.precision, copy_gbps,
@@ -705,6 +767,9 @@ def main():
         ns = run_ns(crh, torch)
         ns.update(run_newton(crh, torch))
         context = run_paper_context(crh, torch)
+        c1, U1, P1 = run_c1(crh, torch)
+        c1_sol = (U1, P1)
+        log(f"16x16x2: {c1['ms_per_solve']} ms per solve, {c1['iters']} iterations")
 
     serving = None
     if args.serve_requests > 0:
@@ -715,6 +780,9 @@ def main():
         cpu = cpu_oracle_baseline(head["elements"]) if WORKLOADS[args.workload]["dim"] == 3 else None
         if cpu:
             log(f"cpu oracle: {cpu['value']:.3g} solves/s ({cpu['sample']})")
+        if c1 is not None:
+            c1 = c1_oracle_leg(c1, *c1_sol)
+            log(f"16x16x2 against the oracle: {json.dumps(c1['err_vs_oracle'])}, oracle {c1['oracle_ms']} ms")
 
     out = {
         "metric": METRIC,
@@ -744,6 +812,7 @@ def main():
         "headline_detail": {k: v for k, v in head.items()
                             if k not in ("roofline", "err_vs_oracle", "coupled_gpu", "jacobi_only", "at_config_tol")},
         "second_workload": second,
+        "smallest_config": c1,
         "ns_newton_256": ns,
         "paper_context": context,
         "serving": serving,
