@@ -273,11 +273,14 @@ cr_status cr_export_G(const cr_system* sys, int64_t* rowptr, int32_t* col, doubl
  * not eliminated, Navier-Stokes), CR_E_NOMEM, CR_E_DEVICE. */
 cr_status cr_export_coupled(cr_system* sys, int64_t* rowptr, int32_t* col, double* val, double* R);
 
-/* Host copy of the resident W [n_int_faces][dim] (canonical). Synchronises. */
+/* Host copy of the resident W [n_int_faces][dim] (canonical): the auxiliary
+ * face unknowns of the hybrid system (Section 3.2, eq. syslinhyb), the
+ * solution of G W = S after cr_solve.  Synchronises. */
 cr_status cr_export_W(const cr_system* sys, double* W);
 
-/* Set the resident W from a host array [n_int_faces][dim] (canonical), e.g. to
- * recover U and P from a W computed elsewhere.  Synchronises. */
+/* Set the resident W (Section 3.2, eq. syslinhyb) from a host array
+ * [n_int_faces][dim] (canonical), e.g. to recover U and P (Section 3.2 items
+ * 2 and 4) from a W computed elsewhere.  Synchronises. */
 cr_status cr_import_W(cr_system* sys, const double* W);
 
 /* Host copy of the interior faces of Section 2 item 1 (faces shared by two
@@ -303,10 +306,10 @@ cr_status cr_boundary_faces(const cr_system* sys, int64_t* n_bnd_faces, int32_t*
  * (r_K^t (R_K - C_K W_K) - e_K) / B_K).  For the Newton step the exterior faces
  * of the linearisation velocity take the data too.  The divergence row of K0
  * is not imposed, so it absorbs the net flux of the data (zero for exact data
- * of a divergence-free field).  With boundary data, CG applies the assembled
- * rows of G (the element form and its coarse correction need homogeneous
- * data).  Errors: CR_E_INVAL (NULL system, no exterior face), CR_E_NOMEM,
- * CR_E_DEVICE. */
+ * of a divergence-free field).  In the element-form CG (whose gauge-shifted
+ * system keeps a divergence row at K0) that row takes up the net flux, so the
+ * element form and its coarse correction serve boundary data too.  Errors:
+ * CR_E_INVAL (NULL system, no exterior face), CR_E_NOMEM, CR_E_DEVICE. */
 cr_status cr_set_boundary(cr_system* sys, const double* g);
 
 /* Host-only topology (step a0 without any device work), for inspection:
@@ -388,8 +391,11 @@ cr_status cr_batch_pop(cr_batch* b, cr_system** sys, cr_solve_info* info, int32_
 /* Number of active and of finished-but-not-popped systems. */
 cr_status cr_batch_count(const cr_batch* b, int32_t* n_active, int32_t* n_finished);
 
+/* Releases the batch's tables and graphs (not its systems).  NULL is a no-op. */
 void cr_batch_destroy(cr_batch* b);
 
+/* Waits for the system's stream, then releases every device buffer of the
+ * system through its allocator.  NULL is a no-op. */
 void cr_destroy(cr_system* sys);
 
 /* Message of the last failing call on this thread ("" if none). */
