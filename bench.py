@@ -585,9 +585,13 @@ def green_taylor_rows(crh, torch, dim, sizes, ratio, stokes=False):
         f = np.zeros((len(elems), dim))
         fd = torch.zeros((len(elems), dim), dtype=torch.float64, device="cuda")
         t0 = time.perf_counter()
+        t_log = t0
         newt = 0
         lin = 0
         for k in range(1, nsteps + 1):
+            if time.perf_counter() - t_log > 60.0:
+                t_log = time.perf_counter()
+                log(f"Green-Taylor {dim}D n={n}: step {k - 1}/{nsteps}, {t_log - t0:.0f} s")
             ns.set_boundary(face_means(coords, bf, lambda x: gt.u(x, k * dt)))
             if stokes:
                 # the operator stays; each step refreshes the right-hand side
@@ -716,6 +720,9 @@ def main():
                     help="skip the second transient workload and the Navier-Stokes step")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only build the workload's system and time the dominant kernel (for counter collection)")
+    ap.add_argument("--green-taylor-3d", default="",
+                    help="only the 3D Navier-Stokes Green-Taylor rows on these cube counts (e.g. 8,16,32), "
+                         "one JSON line")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 20 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -738,6 +745,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 20}), flush=True)
+        return
+    if args.green_taylor_3d:
+        sizes = tuple(int(v) for v in args.green_taylor_3d.split(","))
+        print(json.dumps({"green_taylor_3d": green_taylor_rows(crh, torch, 3, sizes, 0.01)}), flush=True)
         return
     if args.kernel_only:
         cfg = WORKLOADS[args.workload]
