@@ -278,6 +278,14 @@ cr_status cr_export_coupled(cr_system* sys, int64_t* rowptr, int32_t* col, doubl
  * solution of G W = S after cr_solve.  Synchronises. */
 cr_status cr_export_W(const cr_system* sys, double* W);
 
+/* The resident W (as cr_export_W) into a caller-owned DEVICE array
+ * [n_int_faces][dim] (canonical), on the system's stream, asynchronous: e.g.
+ * the initial guess (cr_solve_opts.w0) of the next solve after a new
+ * cr_eliminate, which starts from W = 0 otherwise (a Newton iteration or a time
+ * step whose W changes little).  Zero before any solve.  Errors: CR_E_INVAL
+ * (NULL system or buffer, not eliminated), CR_E_DEVICE. */
+cr_status cr_export_W_device(cr_system* sys, double* W);
+
 /* Set the resident W (Section 3.2, eq. syslinhyb) from a host array
  * [n_int_faces][dim] (canonical), e.g. to recover U and P (Section 3.2 items
  * 2 and 4) from a W computed elsewhere.  Synchronises. */

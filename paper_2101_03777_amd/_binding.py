@@ -30,7 +30,7 @@ _PRECOND = {"default": CR_PC_DEFAULT, "jacobi": CR_PC_JACOBI, "coarse": CR_PC_CO
 
 # every function declared in include/crhyb.h
 EXPORTS = ["cr_assemble", "cr_eliminate", "cr_update_rhs", "cr_solve", "cr_recover", "cr_query_sizes",
-           "cr_export_G", "cr_export_W", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
+           "cr_export_G", "cr_export_W", "cr_export_W_device", "cr_import_W", "cr_interior_faces", "cr_topology", "cr_coupled_solve",
            "cr_time_spmv", "cr_destroy", "cr_last_error", "cr_version", "cr_batch_create", "cr_batch_add",
            "cr_batch_advance", "cr_batch_pop", "cr_batch_count", "cr_batch_destroy", "cr_prepare",
            "cr_assemble_prepared", "cr_prepared_destroy", "cr_export_coupled", "cr_recover_noalloc",
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
         "cr_query_sizes": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
         "cr_export_G": (I32, [P, P, P, P, P]),
         "cr_export_W": (I32, [P, P]),
+        "cr_export_W_device": (I32, [P, P]),
         "cr_export_coupled": (I32, [P, P, P, P, P]),
         "cr_import_W": (I32, [P, P]),
         "cr_interior_faces": (I32, [P, P]),
@@ -437,6 +438,16 @@ class System:
         W = np.empty((self.n_int_faces, self.dim), dtype=np.float64)
         _check(self.lib.cr_export_W(self.h, _ptr(W)))
         return W
+
+    def export_W_device(self, out=None):
+        """The resident W [n_int_faces, dim] (canonical) into a device tensor, on
+        the system's stream (no host copy)."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty((self.n_int_faces, self.dim), dtype=torch.float64, device="cuda")
+        out = self._dev(out, (self.n_int_faces, self.dim))
+        _check(self.lib.cr_export_W_device(self.h, _ptr(out)))
+        return out
 
     def import_W(self, W):
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(self.n_int_faces, self.dim)

@@ -609,6 +609,15 @@ cr_status cr_export_W(const cr_system* s, double* W) {
   return CR_OK;
 }
 
+cr_status cr_export_W_device(cr_system* s, double* W) {
+  clear_error();
+  if (!s || !W || !s->eliminated) {
+    set_error("cr_export_W_device needs an eliminated system and a device buffer");
+    return CR_E_INVAL;
+  }
+  return enqueue_export_w(s, W);
+}
+
 cr_status cr_import_W(cr_system* s, const double* W) {
   clear_error();
   if (!s || !W || !s->eliminated) {

@@ -1352,6 +1352,17 @@ __global__ void __launch_bounds__(BS) k_import_w(int64_t n, int d, const int32_t
   y[t] = dsq[t] * w0[(int64_t)fcanon[f] * d + i];
 }
 
+// the resident W in canonical order: W = y / dsq (inverse of k_import_w)
+__global__ void __launch_bounds__(BS) k_export_w(int64_t n, int d, const int32_t* __restrict__ fcanon,
+                                                 const double* __restrict__ dsq, const double* __restrict__ y,
+                                                 double* __restrict__ w) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t >= n * d) return;
+  const int64_t f = t / d;
+  const int i = (int)(t - f * d);
+  w[(int64_t)fcanon[f] * d + i] = y[t] / dsq[t];
+}
+
 // deterministic sum of squared differences: per-block partials then one block
 __global__ void __launch_bounds__(256) k_sqdiff_partial(int64_t n, const double* __restrict__ a,
                                                         const double* __restrict__ b, double* __restrict__ part) {
@@ -1628,6 +1639,13 @@ cr_status enqueue_import_w(cr_system* s, const double* w0) {
                      s->y);
   s->has_solution = true;
   return check_hip(hipGetLastError(), "import W launch");
+}
+
+cr_status enqueue_export_w(cr_system* s, double* w) {
+  const int64_t n = s->nf;
+  hipLaunchKernelGGL(k_export_w, dim3(nblocks(n * s->d, BS)), dim3(BS), 0, s->stream, n, s->d, s->fcanon, s->dsq,
+                     s->y, w);
+  return check_hip(hipGetLastError(), "export W launch");
 }
 
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump) {

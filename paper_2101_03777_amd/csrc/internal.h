@@ -158,6 +158,8 @@ cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_pre
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump);
 // y = dsq * w0 from a device array in canonical order (initial guess of a solve)
 cr_status enqueue_import_w(cr_system* s, const double* w0);
+// w = y / dsq into a device array in canonical order (the resident W)
+cr_status enqueue_export_w(cr_system* s, double* w);
 // cr_recover without device allocation: mismatch partials in a static device array
 cr_status run_recover_noalloc(cr_system* s, double* U, double* P, double* jump);
 // Maps a solution of the element-form system (with the K0 Schur term) to the

@@ -5,9 +5,11 @@ the Newton method; every Newton iteration is one linear system
 J(ubar) u + D^t P = R_f + b_h(ubar, ubar) about the current iterate ubar, and
 the hybrid method of Section 3.2 solves it.  This module only orders the
 library calls: per iteration cr_eliminate with u_lin = ubar (the exterior faces
-of ubar take the boundary data of cr_set_boundary), cr_solve (warm-started from
-the previous step's W), cr_recover; the iterate becomes the recovered U until
-max|U - ubar| <= tol max|U|.  Every step of the path runs in the HIP library.
+of ubar take the boundary data of cr_set_boundary), cr_solve with the W of the
+previous linear solve as its initial guess (cr_export_W_device; across time
+steps too: W changes little from one Newton step to the next), cr_recover; the
+iterate becomes the recovered U until max|U - ubar| <= tol max|U|.  Every step
+of the path runs in the HIP library.
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ class NewtonSolver:
         self.torch = torch
         self.sys = System(coords, elems, mu, nu, k0=k0, problem="ns", lambda_scale=lambda_scale, stream=stream)
         self.dim = self.sys.dim
+        self._W = None  # W of the last linear solve, the next one's initial guess
 
     def set_boundary(self, g):
         self.sys.set_boundary(g)
@@ -47,7 +50,9 @@ class NewtonSolver:
         for it in range(maxit):
             t0 = time.perf_counter()
             s.eliminate(f, up, ubar)
-            info = s.solve(method, precision, tol=lin_tol, maxit=lin_maxit, warm_start=it > 0, raise_on_error=False)
+            info = s.solve(method, precision, tol=lin_tol, maxit=lin_maxit, w0=self._W, raise_on_error=False)
+            # a failed solve's W is no guess for the next one
+            self._W = s.export_W_device(self._W) if info["status"] == 0 else None
             U, P = s.recover()
             inc = (torch.max(torch.abs(U - ubar)) / torch.clamp(torch.max(torch.abs(U)), min=1e-300)).item()
             rec["times_ms"].append(1e3 * (time.perf_counter() - t0))

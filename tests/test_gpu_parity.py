@@ -603,3 +603,24 @@ def test_boundary_data_time_steps(gpu):
         assert_close(Pk.cpu().numpy(), P_o, 1e-10)
         up_o = U_o
     s.close()
+
+
+def test_export_w_device_matches_host_export(gpu):
+    """cr_export_W_device writes the resident W in canonical order as
+    cr_export_W does, and as the initial guess of a solve after a new
+    elimination it reaches the same solution in fewer iterations."""
+    c = make_case("ns10")
+    s = gpu_system(gpu, c)
+    s.solve("bicgstab2", "fp64", tol=1e-12, maxit=100000)
+    Wd = s.export_W_device()
+    torch.cuda.synchronize()
+    assert np.array_equal(Wd.cpu().numpy(), s.export_W())
+    coords, elems, mu, nu, fbar, ulin, prob = c
+    s.eliminate(dev(fbar), None, dev(ulin))
+    cold = s.solve("bicgstab2", "fp64", tol=1e-12, maxit=100000)
+    s.eliminate(dev(fbar), None, dev(ulin))
+    warm = s.solve("bicgstab2", "fp64", tol=1e-12, maxit=100000, w0=Wd)
+    print(f"cold {cold['iters']} warm {warm['iters']} iterations", flush=True)
+    assert warm["iters"] < cold["iters"]
+    assert relerr(s.export_W(), Wd.cpu().numpy()) <= 1e-9
+    s.close()
