@@ -312,8 +312,6 @@ cr_status finish_device(cr_system* s, Staging& h, const cr_allocator* alloc, voi
   if (st == CR_OK) st = alloc_n(s, s->RK, (size_t)d1 * d * ne);
   if (st == CR_OK) st = alloc_n(s, s->sK, (size_t)d1 * d * ne);
   if (st == CR_OK) st = alloc_n(s, s->lam, (size_t)ne);
-  if (st == CR_OK) st = alloc_n(s, s->G64, nslot * d * d * nf);
-  if (st == CR_OK) st = alloc_n(s, s->G32, nslot * d * d * nf);
   if (st == CR_OK) st = alloc_n(s, s->dsq, nvec);
   if (st == CR_OK && !ns && s->params.mu > 0.0) {
     // element-factor form of the scaled operator (transient Stokes CG)
@@ -545,6 +543,10 @@ cr_status cr_export_G(const cr_system* s, int64_t* rowptr, int32_t* col, double*
     set_error("cr_export_G needs an eliminated system");
     return CR_E_INVAL;
   }
+  // the block rows are a cache of the eliminated system: building them leaves
+  // its state otherwise unchanged
+  cr_status st0 = ensure_assembled(const_cast<cr_system*>(s));
+  if (st0 != CR_OK) return st0;
   const int d = s->d, DD = d * d, ns = 2 * d + 1;
   const int64_t nf = s->nf;
   std::vector<double> G((size_t)ns * DD * nf), dsq((size_t)nf * d), bs((size_t)nf * d);

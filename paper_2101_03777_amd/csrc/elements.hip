@@ -782,7 +782,9 @@ struct BlockSrc<2, true> {
   }
 };
 
-template <int D, bool NSK>
+// FULL = false: only the diagonal blocks (for the Jacobi scale), S and the
+// column table; the block rows of G (G may be NULL) are not written.
+template <int D, bool NSK, bool FULL = true>
 __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, const int32_t* __restrict__ fel,
                                                       const int32_t* __restrict__ floc,
                                                       const int32_t* __restrict__ eface,
@@ -827,12 +829,14 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
       const int64_t col = in ? eface[l * ne + K] : f;
       const double c = cj * csign(fl, l);
       cols[(int64_t)(slot - 1) * nf + f] = (int32_t)col;
+      if constexpr (FULL) {
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+        for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int ip = 0; ip < D; ++ip) {
-          G[(int64_t)(slot * DD + i * D + ip) * nf + f] = in ? c * src.g(j, i, l, ip) : 0.0;
-        }
+          for (int ip = 0; ip < D; ++ip) {
+            G[(int64_t)(slot * DD + i * D + ip) * nf + f] = in ? c * src.g(j, i, l, ip) : 0.0;
+          }
+      }
       ++slot;
     }
   }
@@ -840,9 +844,9 @@ __global__ void __launch_bounds__(BS) k_face_assemble(int64_t nf, int64_t ne, co
   double dsum = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
+    if constexpr (FULL) {
 #pragma unroll
-    for (int ip = 0; ip < D; ++ip) {
-      G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
+      for (int ip = 0; ip < D; ++ip) G[(int64_t)(i * D + ip) * nf + f] = diag[i][ip];
     }
     const double dg = fabs(diag[i][i]);
     if (!(dg > 0.0) || !isfinite(dg)) report(err, ERR_ZERODIAG, f);
@@ -1482,6 +1486,38 @@ cr_status enqueue_gauge_fix(cr_system* s, hipStream_t stream) {
   return check_hip(hipGetLastError(), "gauge shift");
 }
 
+// Face gather of step a3.  full: the block rows of G in FP64 and FP32 (the
+// operator of the assembled form), allocated on first use.  Otherwise, where
+// CG applies the element factors, only what the element form needs (the Jacobi
+// scale from the diagonal blocks, S, the column table): the rows are built when
+// an assembled-form call first asks for them (ensure_assembled), which saves
+// their memory and a pass over 2(2d+1)d^2 numbers per face at each elimination.
+template <int D, bool NSK>
+static cr_status face_gather(cr_system* s, bool full) {
+  const unsigned gf = nblocks(s->nf, BS);
+  if (full) {
+    const size_t n = (size_t)(2 * D + 1) * D * D * (size_t)s->nf;
+    if (!s->G64) s->G64 = (double*)dev_alloc(s, sizeof(double) * n);
+    if (!s->G32) s->G32 = (float*)dev_alloc(s, sizeof(float) * n);
+    if (!s->G64 || !s->G32) return CR_E_NOMEM;
+    hipLaunchKernelGGL((k_face_assemble<D, NSK, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel,
+                       s->floc, s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
+    hipLaunchKernelGGL(k_face_scale<D>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+  } else {
+    hipLaunchKernelGGL((k_face_assemble<D, NSK, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel,
+                       s->floc, s->eface, s->eflags, s->pack, s->sK, s->cols, nullptr, s->dsq, s->bs, s->err);
+  }
+  s->g_valid = full;
+  return check_hip(hipGetLastError(), "face gather");
+}
+
+cr_status ensure_assembled(cr_system* s) {
+  if (s->g_valid) return CR_OK;
+  const bool ns = s->params.problem == CR_NS_NEWTON;
+  if (s->d == 2) return ns ? face_gather<2, true>(s, true) : face_gather<2, false>(s, true);
+  return ns ? face_gather<3, true>(s, true) : face_gather<3, false>(s, true);
+}
+
 cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin) {
   const int d = s->d;
   const bool ns = s->params.problem == CR_NS_NEWTON;
@@ -1501,9 +1537,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL(k_elim_ns, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface, s->enb,
                        steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, bnd, s->pack,
                        s->RK, s->sK, s->err);
-    hipLaunchKernelGGL((k_face_assemble<2, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
-                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
-    hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    st = face_gather<2, true>(s, true);
+    if (st != CR_OK) return st;
   } else if (ns) {
     // 3D Newton step: the local 12 x 12 matrices live in LDS (72 KiB per workgroup)
     st = check_hip(hipFuncSetAttribute((const void*)k_elim_ns3, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1519,9 +1554,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL(k_elim_ns3, dim3(g3), dim3(BS_NS3), LDS_NS3, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->ulin, s->params.mu, s->params.nu, bnd,
                        s->pack, s->RK, s->sK, s->err);
-    hipLaunchKernelGGL((k_face_assemble<3, true>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
-                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
-    hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    st = face_gather<3, true>(s, true);
+    if (st != CR_OK) return st;
   } else if (d == 2) {
     if (steady)
       hipLaunchKernelGGL(k_stokes_lambda<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags,
@@ -1529,9 +1563,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL(k_elim_stokes<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack,
                        s->RK, s->sK, s->err);
-    hipLaunchKernelGGL((k_face_assemble<2, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
-                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
-    hipLaunchKernelGGL(k_face_scale<2>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    st = face_gather<2, false>(s, s->efo64 == nullptr);
+    if (st != CR_OK) return st;
     if (s->efo64)
       hipLaunchKernelGGL(k_efo_build<2>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->ecoord, s->eface,
                          s->eflags, s->dsq, s->efo64, s->efo32, s->egat);
@@ -1542,9 +1575,8 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
     hipLaunchKernelGGL(k_elim_stokes<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->ecoord, s->eflags, s->eface,
                        s->enb, steady ? s->lam : nullptr, s->fbar, up, s->params.mu, s->params.nu, bnd, s->pack,
                        s->RK, s->sK, s->err);
-    hipLaunchKernelGGL((k_face_assemble<3, false>), dim3(gf), dim3(BS), 0, s->stream, s->nf, s->ne, s->fel, s->floc,
-                       s->eface, s->eflags, s->pack, s->sK, s->cols, s->G64, s->dsq, s->bs, s->err);
-    hipLaunchKernelGGL(k_face_scale<3>, dim3(gf), dim3(BS), 0, s->stream, s->nf, s->cols, s->dsq, s->G64, s->G32);
+    st = face_gather<3, false>(s, s->efo64 == nullptr);
+    if (st != CR_OK) return st;
     if (s->efo64)
       hipLaunchKernelGGL(k_efo_build<3>, dim3(ge), dim3(BS), 0, s->stream, s->ne, s->pack, s->ecoord, s->eface,
                          s->eflags, s->dsq, s->efo64, s->efo32, s->egat);

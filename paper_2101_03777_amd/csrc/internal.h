@@ -141,6 +141,9 @@ struct cr_system {
   int npack = 0;
   bool eliminated = false;
   bool has_solution = false;
+  // the block rows G64 / G32 hold the current G (built on first use where CG
+  // applies the element factors)
+  bool g_valid = false;
 
   // Krylov workspace (allocated on first solve), coupled-baseline workspace
   void* kws = nullptr;
@@ -154,6 +157,8 @@ cr_status check_hip(hipError_t e, const char* what);
 
 // element / face kernels (elements.hip)
 cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev, const double* u_lin);
+// builds the block rows of G (FP64, FP32) if the last elimination left them out
+cr_status ensure_assembled(cr_system* s);
 cr_status run_update_rhs(cr_system* s, const double* f_mean, const double* u_prev);
 cr_status run_recover(cr_system* s, double* U, double* P, double* jump);
 // y = dsq * w0 from a device array in canonical order (initial guess of a solve)

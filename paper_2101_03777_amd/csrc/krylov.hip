@@ -2055,7 +2055,8 @@ void enqueue_minres(cr_system* s, KWs* w, const CgSys& S, int k0, int niter) {
 // to FP64.
 cr_status run_minres(cr_system* s, KWs* w, const cr_solve_opts* o, cr_solve_info* info,
                      std::chrono::steady_clock::time_point t_start) {
-  cr_status st = CR_OK;
+  cr_status st = ensure_assembled(s);  // MINRES applies the assembled rows
+  if (st != CR_OK) return st;
   if (!w->mst) {
     w->mst = (MState*)dev_alloc(s, sizeof(MState));
     if (!w->mst) return CR_E_NOMEM;
@@ -2201,6 +2202,7 @@ cr_status run_solve(cr_system* s, const cr_solve_opts* o, cr_solve_info* info) {
   }
   int op = 0;
   st = resolve_op(s, o, op);
+  if (st == CR_OK && op == 0) st = ensure_assembled(s);
   if (st != CR_OK) return st;
   st = pick_coarse(s, w, o, op);
   if (st != CR_OK) return st;
@@ -2254,6 +2256,7 @@ cr_status run_time_spmv(cr_system* s, int precision, int form, int reps, double*
   o.operator_form = form;
   int op = 0;
   st = resolve_op(s, &o, op);
+  if (st == CR_OK && op == 0) st = ensure_assembled(s);
   if (st != CR_OK) return st;
   w->use_coarse = op == 1 && w->coarse_ok;
   const int d = s->d;
@@ -2601,6 +2604,7 @@ cr_status cr_batch_add(cr_batch* b, cr_system* s, const cr_solve_opts* o) {
   }
   int op = 0;
   cr_status st = resolve_op(s, o, op);
+  if (st == CR_OK && op == 0) st = ensure_assembled(s);
   if (st != CR_OK) return st;
   int n_act = 0;
   for (const BEntry& en : b->e) n_act += en.active ? 1 : 0;

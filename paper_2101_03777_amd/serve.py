@@ -33,12 +33,14 @@ import numpy as np
 
 from ._binding import Batch, Prepared, System
 
-# device bytes per element of a resident 2D system with its Krylov workspace
-# (element data ~510 B including the operator factors and the per-element Krylov
-# contributions; per-face data ~370 B and twelve Krylov vectors ~190 B per
-# face, about 1.5 faces per element; a margin for the recovery buffers), used
+# device bytes per element of a resident 2D transient-Stokes system with its
+# Krylov workspace (element data ~510 B including the operator factors and the
+# per-element Krylov contributions; per-face data ~110 B and twelve Krylov
+# vectors ~190 B per face, about 1.5 faces per element -- the assembled block
+# rows of G are not built for the element-form CG; measured 1,050-1,140 B per
+# element on 128x128x2 and 512x512x2; a margin for the recovery buffers), used
 # to decide admission before the system exists
-BYTES_PER_ELEMENT_2D = 1450
+BYTES_PER_ELEMENT_2D = 1200
 
 
 class Session:
