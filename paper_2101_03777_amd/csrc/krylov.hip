@@ -761,13 +761,22 @@ __device__ __forceinline__ void ec2_body(const CgSys& S, int lb, int par) {
 }
 
 // Coarse solve: c_a = sum of the restriction partials of the face blocks that
-// hold aggregate a (fixed order), mu = E^-1 c; one wavefront per row.
+// hold aggregate a (fixed order), mu = E^-1 c; one wavefront per row.  Only
+// in the first of those blocks can a be other than the block's first
+// aggregate (its faces are contiguous), so bfa carries, with that block
+// shifted left by two bits, a's slot in it, and every later block contributes
+// its slot 0.
+static_assert(KMAX == 4, "the slot of an aggregate in its first face block takes two bits");
 __device__ __forceinline__ void coarse_body(const CgSys& S, int cb) {
   if (S.st->done) return;
   __shared__ double c[MAX_AGG];
   for (int a = threadIdx.x; a < S.nagg; a += NT) {
+    const int pk = S.bfa[a], b1 = S.bla[a], b0 = pk >> 2;
     double v = 0.0;
-    for (int b = S.bfa[a]; b <= S.bla[a]; ++b) v += S.Pr[(int64_t)b * KMAX + (a - S.ablk[b])];
+    if (b0 <= b1) {
+      v = S.Pr[(int64_t)b0 * KMAX + (pk & 3)];
+      for (int b = b0 + 1; b <= b1; ++b) v += S.Pr[(int64_t)b * KMAX];
+    }
     c[a] = v;
   }
   __syncthreads();
@@ -1590,6 +1599,12 @@ cr_status ensure_ws(cr_system* s, KWs*& w) {
       const int a = fa[f], b = (int)(f / P.chunk);
       if (f == 0 || fa[f - 1] != a) bfa[a] = b;
       bla[a] = b;
+    }
+    // the first block of each aggregate, shifted, with the aggregate's slot in
+    // that block's restriction partials (an empty aggregate keeps b0 > bla)
+    for (int a = 0; a < m; ++a) {
+      const int slot = bfa[a] <= bla[a] ? std::min(KMAX - 1, std::max(0, a - ablk[bfa[a]])) : 0;
+      bfa[a] = (bfa[a] << 2) | slot;
     }
     w->coarse_ok = ok;
     auto up = [&](int32_t*& dst, const std::vector<int32_t>& src) {
