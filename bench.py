@@ -219,7 +219,7 @@ def c1_oracle_leg(rec, U, P):
     return rec
 
 
-def cpu_oracle_baseline(ne_target, n_sample=10):
+def cpu_oracle_baseline(ne_target, n_sample=12):
     """The oracle's primary result (assembly and sparse LU of the coupled system,
     FP64, one thread) on a bounded sample of the headline workload family: the
     same 3D transient Stokes problem on n_sample^3 cubes x 6 tetrahedra, timed on
