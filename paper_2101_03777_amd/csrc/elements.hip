@@ -1116,6 +1116,133 @@ __global__ void __launch_bounds__(256) k_gj_final(int m, const double* __restric
   Einv[q] = scal[0] != 0.0 ? 0.0 : X[(int64_t)i * 2 * m + m + c];
 }
 
+// The same inverse, blocked, for m a multiple of GJB = 32 (m > 128): in-place
+// Gauss-Jordan by 32 x 32 pivot blocks on A = E + s 1 1^t (held in Einv).  For
+// pivot block K, with P = A_KK^-1 (one workgroup, in LDS), T = P A_K* (the
+// block row) and C = A_*K (the block column, copied first):
+//   A_ij -= C_iK T_Kj (i, j not in K),  A_iK = -C_iK P,  A_Kj = T_Kj,  A_KK = P;
+// after the last block A holds the inverse.  m / 32 steps of three launches
+// instead of m launches over an m x 2m array.  A pivot that is not positive
+// sets the flag and leaves a zero inverse, as in the unblocked form.
+constexpr int GJB = 32;
+
+__global__ void __launch_bounds__(1024) k_gjb_init(int m, const double* __restrict__ E, double* __restrict__ A,
+                                                   double* __restrict__ flag) {
+  __shared__ double red[16];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) tr += E[(int64_t)i * m + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k];
+    red[0] = t / m;
+  }
+  __syncthreads();
+  const double sh = red[0];
+  for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += 1024) A[q] = E[q] + sh;
+  if (threadIdx.x == 0) flag[0] = 0.0;
+}
+
+// P = A_KK^-1 by unblocked Gauss-Jordan in LDS; one workgroup of GJB * GJB threads
+__global__ void __launch_bounds__(GJB * GJB) k_gjb_pivot(int m, int K0, const double* __restrict__ A,
+                                                        double* __restrict__ P, double* __restrict__ flag) {
+  __shared__ double B[GJB][GJB];
+  __shared__ double fac[GJB];
+  __shared__ int bad;
+  const int r = threadIdx.x / GJB, c = threadIdx.x % GJB;
+  B[r][c] = A[(int64_t)(K0 + r) * m + K0 + c];
+  if (threadIdx.x == 0) bad = flag[0] != 0.0;
+  __syncthreads();
+  for (int k = 0; k < GJB; ++k) {
+    const double piv = B[k][k];
+    if (bad || !(piv > 0.0) || !isfinite(piv)) {
+      if (threadIdx.x == 0) bad = 1;
+      break;
+    }
+    if (c == 0) fac[r] = B[r][k];
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    if (r == k) B[k][c] = (c == k ? 1.0 : B[k][c]) * ip;
+    __syncthreads();
+    if (r != k) B[r][c] = (c == k ? 0.0 : B[r][c]) - fac[r] * B[k][c];
+    __syncthreads();
+  }
+  __syncthreads();
+  P[r * GJB + c] = B[r][c];
+  if (threadIdx.x == 0 && bad) flag[0] = 1.0;
+}
+
+// T = P A_K* (GJB x m) and C = A_*K (m x GJB); one thread per entry of each
+__global__ void __launch_bounds__(256) k_gjb_panel(int m, int K0, const double* __restrict__ A,
+                                                   const double* __restrict__ P, double* __restrict__ T,
+                                                   double* __restrict__ C) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)GJB * m;
+  if (q < n) {
+    const int l = (int)(q / m), j = (int)(q % m);
+    double v = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < GJB; ++t) v += P[l * GJB + t] * A[(int64_t)(K0 + t) * m + j];
+    T[q] = v;
+  } else if (q < 2 * n) {
+    const int64_t u = q - n;
+    const int i = (int)(u / GJB), l = (int)(u % GJB);
+    C[u] = A[(int64_t)i * m + K0 + l];
+  }
+}
+
+// the update of every entry of A for pivot block K; 16 x 16 tiles (a tile lies
+// wholly inside or outside K in either direction), C and T (or P) staged in LDS
+__global__ void __launch_bounds__(256) k_gjb_update(int m, int K0, double* __restrict__ A,
+                                                    const double* __restrict__ P, const double* __restrict__ T,
+                                                    const double* __restrict__ C, const double* __restrict__ flag) {
+  __shared__ double Cs[16][GJB + 1];
+  __shared__ double Ts[GJB][16 + 1];
+  if (flag[0] != 0.0) return;
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int i = i0 + ti, j = j0 + tj;
+  const bool rowK = i0 >= K0 && i0 < K0 + GJB, colK = j0 >= K0 && j0 < K0 + GJB;
+  if (rowK) {
+    A[(int64_t)i * m + j] = colK ? P[(i - K0) * GJB + (j - K0)] : T[(int64_t)(i - K0) * m + j];
+    return;
+  }
+  for (int q = threadIdx.x; q < 16 * GJB; q += 256) {
+    const int a = q / GJB, l = q % GJB;
+    Cs[a][l] = C[(int64_t)(i0 + a) * GJB + l];
+    const int lb = q / 16, b = q % 16;
+    Ts[lb][b] = colK ? P[lb * GJB + (j0 - K0 + b)] : T[(int64_t)lb * m + j0 + b];
+  }
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll 8
+  for (int l = 0; l < GJB; ++l) acc += Cs[ti][l] * Ts[l][tj];
+  double* a = A + (int64_t)i * m + j;
+  *a = colK ? -acc : *a - acc;
+}
+
+// zero inverse after a bad pivot; else make it exactly symmetric (the blocked
+// updates leave an asymmetry of a few ulps that the unblocked form does not,
+// and CG wants a symmetric preconditioner): the thread of (i, j), i < j,
+// writes the mean of the pair to both entries
+__global__ void __launch_bounds__(256) k_gjb_final(int m, const double* __restrict__ flag, double* __restrict__ A) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (int64_t)m * m) return;
+  if (flag[0] != 0.0) {
+    A[q] = 0.0;
+    return;
+  }
+  const int i = (int)(q / m), j = (int)(q % m);
+  if (i >= j) return;
+  const int64_t t = (int64_t)j * m + i;
+  const double v = 0.5 * (A[q] + A[t]);
+  A[q] = v;
+  A[t] = v;
+}
+
 // The same inverse for m <= 128 with E held in LDS (m^2 doubles, at most
 // 128 KB) and inverted in place: for each pivot k, row k is divided by the
 // pivot (its diagonal entry becoming 1 / pivot) and eliminated from every
@@ -1609,6 +1736,25 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
                        "coarse inverse LDS size");
         if (st != CR_OK) return st;
         hipLaunchKernelGGL(k_coarse_inv_lds, dim3(1), dim3(1024), sizeof(double) * m * m, s->stream, m, s->Ec, s->Einv);
+      } else if (m % GJB == 0) {
+        // blocked, in place in Einv; scratch: P, T, C and the flag
+        const size_t nscr = (size_t)GJB * GJB + (size_t)2 * GJB * m + 1;
+        if (!s->gjbuf) s->gjbuf = (double*)dev_alloc(s, sizeof(double) * nscr);
+        if (!s->gjbuf) return CR_E_NOMEM;
+        double* P = s->gjbuf;
+        double* T = P + (size_t)GJB * GJB;
+        double* C = T + (size_t)GJB * m;
+        double* flag = C + (size_t)GJB * m;
+        hipLaunchKernelGGL(k_gjb_init, dim3(1), dim3(1024), 0, s->stream, m, s->Ec, s->Einv, flag);
+        const unsigned gpan = (unsigned)(((int64_t)2 * GJB * m + 255) / 256);
+        const dim3 gupd((unsigned)(m / 16), (unsigned)(m / 16));
+        for (int K0 = 0; K0 < m; K0 += GJB) {
+          hipLaunchKernelGGL(k_gjb_pivot, dim3(1), dim3(GJB * GJB), 0, s->stream, m, K0, s->Einv, P, flag);
+          hipLaunchKernelGGL(k_gjb_panel, dim3(gpan), dim3(256), 0, s->stream, m, K0, s->Einv, P, T, C);
+          hipLaunchKernelGGL(k_gjb_update, gupd, dim3(256), 0, s->stream, m, K0, s->Einv, P, T, C, flag);
+        }
+        hipLaunchKernelGGL(k_gjb_final, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, s->stream, m,
+                           flag, s->Einv);
       } else {
         // two m x 2m buffers and a flag in scratch memory of this system
         if (!s->gjbuf) s->gjbuf = (double*)dev_alloc(s, sizeof(double) * ((size_t)4 * m * m + 1));
