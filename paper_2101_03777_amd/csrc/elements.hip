@@ -1067,63 +1067,14 @@ __global__ void __launch_bounds__(256) k_coarse_E(int32_t npairs, const int32_t*
 
 // Inverse of E + s 1 1^t (s = trace(E) / m; E is positive semi-definite with
 // null vector 1, since the columns of Z sum to z) by Gauss-Jordan without
-// pivoting on the m x 2m array [E + s 1 1^t | I], one launch per pivot,
-// reading one buffer and writing the other.  A pivot that is not positive
-// leaves a zero inverse (the correction then does nothing).
-__global__ void __launch_bounds__(1024) k_gj_init(int m, const double* __restrict__ E, double* __restrict__ X,
-                                                  double* __restrict__ scal) {
-  __shared__ double red[16];
-  double tr = 0.0;
-  for (int i = threadIdx.x; i < m; i += 1024) tr += E[(int64_t)i * m + i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tr;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int k = 0; k < 16; ++k) t += red[k];
-    red[0] = t / m;
-  }
-  __syncthreads();
-  const double sh = red[0];
-  for (int64_t q = threadIdx.x; q < (int64_t)m * 2 * m; q += 1024) {
-    const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
-    X[q] = c < m ? E[(int64_t)i * m + c] + sh : (c - m == i ? 1.0 : 0.0);
-  }
-  if (threadIdx.x == 0) scal[0] = 0.0;  // bad-pivot flag
-}
-
-__global__ void __launch_bounds__(256) k_gj_step(int m, int k, const double* __restrict__ X, double* __restrict__ Y,
-                                                 double* __restrict__ scal) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (int64_t)m * 2 * m) return;
-  const int i = (int)(q / (2 * m)), c = (int)(q % (2 * m));
-  const double piv = X[(int64_t)k * 2 * m + k];
-  if (!(piv > 0.0) || !isfinite(piv)) {
-    if (q == 0) scal[0] = 1.0;
-    Y[q] = X[q];
-    return;
-  }
-  const double rk = X[(int64_t)k * 2 * m + c] / piv;
-  Y[q] = i == k ? rk : X[q] - X[(int64_t)i * 2 * m + k] * rk;
-}
-
-__global__ void __launch_bounds__(256) k_gj_final(int m, const double* __restrict__ X, const double* __restrict__ scal,
-                                                  double* __restrict__ Einv) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (int64_t)m * m) return;
-  const int i = (int)(q / m), c = (int)(q % m);
-  Einv[q] = scal[0] != 0.0 ? 0.0 : X[(int64_t)i * 2 * m + m + c];
-}
-
-// The same inverse, blocked, for m a multiple of GJB = 32 (m > 128): in-place
-// Gauss-Jordan by 32 x 32 pivot blocks on A = E + s 1 1^t (held in Einv).  For
-// pivot block K, with P = A_KK^-1 (one workgroup, in LDS), T = P A_K* (the
-// block row) and C = A_*K (the block column, copied first):
+// pivoting, for m a multiple of GJB = 32 (m > 128; the smaller ones are
+// inverted in LDS below): in place, by 32 x 32 pivot blocks, on A = E + s 1 1^t
+// (held in Einv).  For pivot block K, with P = A_KK^-1 (one workgroup, in LDS),
+// T = P A_K* (the block row) and C = A_*K (the block column, copied first):
 //   A_ij -= C_iK T_Kj (i, j not in K),  A_iK = -C_iK P,  A_Kj = T_Kj,  A_KK = P;
-// after the last block A holds the inverse.  m / 32 steps of three launches
-// instead of m launches over an m x 2m array.  A pivot that is not positive
-// sets the flag and leaves a zero inverse, as in the unblocked form.
+// after the last block A holds the inverse: m / 32 steps of three launches.  A
+// pivot that is not positive sets the flag and leaves a zero inverse (the
+// correction then does nothing).
 constexpr int GJB = 32;
 
 __global__ void __launch_bounds__(1024) k_gjb_init(int m, const double* __restrict__ E, double* __restrict__ A,
@@ -1225,9 +1176,9 @@ __global__ void __launch_bounds__(256) k_gjb_update(int m, int K0, double* __res
 }
 
 // zero inverse after a bad pivot; else make it exactly symmetric (the blocked
-// updates leave an asymmetry of a few ulps that the unblocked form does not,
-// and CG wants a symmetric preconditioner): the thread of (i, j), i < j,
-// writes the mean of the pair to both entries
+// updates leave a relative asymmetry near 1e-13, and CG wants a symmetric
+// preconditioner): the thread of (i, j), i < j, writes the mean of the pair to
+// both entries
 __global__ void __launch_bounds__(256) k_gjb_final(int m, const double* __restrict__ flag, double* __restrict__ A) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= (int64_t)m * m) return;
@@ -1737,7 +1688,7 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
         if (st != CR_OK) return st;
         hipLaunchKernelGGL(k_coarse_inv_lds, dim3(1), dim3(1024), sizeof(double) * m * m, s->stream, m, s->Ec, s->Einv);
       } else if (m % GJB == 0) {
-        // blocked, in place in Einv; scratch: P, T, C and the flag
+        // in place in Einv; scratch: P, T, C and the flag
         const size_t nscr = (size_t)GJB * GJB + (size_t)2 * GJB * m + 1;
         if (!s->gjbuf) s->gjbuf = (double*)dev_alloc(s, sizeof(double) * nscr);
         if (!s->gjbuf) return CR_E_NOMEM;
@@ -1756,20 +1707,9 @@ cr_status run_eliminate(cr_system* s, const double* f_mean, const double* u_prev
         hipLaunchKernelGGL(k_gjb_final, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, s->stream, m,
                            flag, s->Einv);
       } else {
-        // two m x 2m buffers and a flag in scratch memory of this system
-        if (!s->gjbuf) s->gjbuf = (double*)dev_alloc(s, sizeof(double) * ((size_t)4 * m * m + 1));
-        if (!s->gjbuf) return CR_E_NOMEM;
-        double* X = s->gjbuf;
-        double* Y = X + (size_t)2 * m * m;
-        double* flag = Y + (size_t)2 * m * m;
-        hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(1024), 0, s->stream, m, s->Ec, X, flag);
-        const unsigned gq = (unsigned)(((int64_t)m * 2 * m + 255) / 256);
-        for (int k = 0; k < m; ++k) {
-          hipLaunchKernelGGL(k_gj_step, dim3(gq), dim3(256), 0, s->stream, m, k, X, Y, flag);
-          std::swap(X, Y);
-        }
-        hipLaunchKernelGGL(k_gj_final, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, s->stream, m, X,
-                           flag, s->Einv);
+        // the aggregate rule makes m a power of 4 (2D) or 8 (3D) up to 512
+        set_error("coarse setup: %d aggregates, neither at most 128 nor a multiple of %d", m, GJB);
+        return CR_E_INVAL;
       }
       const int64_t n = s->nf * d;
       hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(n, BS)), dim3(BS), 0, s->stream, n, s->zy, s->zy32);
